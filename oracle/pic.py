@@ -1,0 +1,61 @@
+"""One PIC step in the paper's order (FP64).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Per step (Eq. pusher time levels; Sec. 3.3 for the source):
+  1. gather E^n, B^n at x^n (App. A) and push u^{n-1/2} -> u^{n+1/2}
+  2. advance x^n -> x^{n+1} (second order, Sec. 4.1)
+  3. deposit J^{n+1/2} from (x^n, x^{n+1}) (charge conserving, Sec. 3.3).
+     The x1 current correction of Eq. (correction) is the identity when
+     [k]_B1 equals the Yee symbol, which is exactly the case dt = dx1/2 of
+     the proposed solver; other cases are rejected here.
+  4. field sweep (E^n, B^n) -> (E^{n+1}, B^{n+1}) with J^{n+1/2}.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import fdtd, particles
+
+
+def _ampere_is_yee(CB):
+    """[k]_B1 is the Yee symbol when C^B = e1; coefficients left over at the
+    1e-20 level by the fit's rounding are far below FP64 resolution."""
+    CB = np.asarray(CB, dtype=np.float64)
+    return abs(CB[0] - 1.0) <= 1e-20 and bool(np.all(np.abs(CB[1:]) <= 1e-20))
+
+
+def step(E, B, species, CE, CB, dx, dt, *, pusher="boris", deposit=False, ndim=3):
+    """Advance fields and every species by one step; species entries are
+    dicts with keys x, u, q, m, w (x and u are replaced)."""
+    shape = E[0].shape
+    n3, n2, n1 = shape
+    L = [n1 * dx[0], n2 * dx[1], n3 * dx[2]][:ndim]
+    J = [np.zeros(shape) for _ in range(3)] if deposit else None
+    if deposit and not _ampere_is_yee(CB):
+        raise ValueError("current correction other than the identity is not implemented")
+    for sp in species:
+        Ep, Bp = particles.gather(E, B, sp["x"], dx, ndim)
+        qm = sp["q"] / sp["m"]
+        if pusher == "boris":
+            u = particles.boris(sp["u"], Ep, Bp, qm, dt)
+        elif pusher == "analytic":
+            u = particles.analytic(sp["u"], Ep, Bp, qm, dt)
+        else:
+            raise ValueError(pusher)
+        x_old = sp["x"]
+        x_new, _ = particles.advance_position(x_old, u, dt, L, ndim)
+        if ndim == 2 and x_old.shape[0] == 3:
+            x_new = np.concatenate([x_new, x_old[2:3]], axis=0)
+        if deposit:
+            Js = particles.deposit(x_old, x_new, sp["q"], sp["w"], dx, dt, shape, ndim, u=u)
+            J = [a + b for a, b in zip(J, Js)]
+        sp["x"], sp["u"] = x_new, u
+    return fdtd.sweep(E, B, J, CE, CB, dx, dt)
+
+
+def run(E, B, species, CE, CB, dx, dt, nsteps, **kw):
+    """``nsteps`` calls of ``step``."""
+    for _ in range(nsteps):
+        E, B = step(E, B, species, CE, CB, dx, dt, **kw)
+    return E, B

@@ -1,0 +1,138 @@
+"""Seeded synthetic inputs shared by the tests, the oracle checks and the
+benchmark.  Holds none of the solver's arithmetic: only grid constants, laser
+vector potentials sampled onto the staggered mesh, and particle loads.
+
+Grid (all workloads): dx1 = lambda0/32, dx2 = dx3 = lambda0/8, dt = dx1/2,
+k0 = omega0 = 1 (normalised units of Sec. 2.1, lambda0 = 2 pi).
+
+Laser: a plane wave along +x1 polarised along x2, given by its normalised
+vector potential a(s) with the local phase s = t - x1 + x_head (s = 0 at the
+pulse head).  At t = 0 both E and B are sampled at their own staggered
+locations (E2 = B3 = -a'(s), times an optional transverse Gaussian profile).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+LAMBDA0 = 2.0 * np.pi
+DX1 = LAMBDA0 / 32.0
+DX2 = LAMBDA0 / 8.0
+DX3 = LAMBDA0 / 8.0
+DT = DX1 / 2.0
+
+
+def rng(seed: int) -> np.random.Generator:
+    """The one random source of every workload (PCG64, seeded)."""
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# ----------------------------------------------------------------------------
+# laser vector potentials a(s) and their derivatives
+# ----------------------------------------------------------------------------
+
+
+@dataclass
+class Sin2Pulse:
+    """a(s) = a0 sin^2(pi s/Lp) sin(s) for 0 <= s <= Lp, else 0; optionally
+    periodic with period ``period`` (a box length)."""
+    a0: float
+    Lp: float
+    period: float | None = None
+
+    def _s(self, s):
+        s = np.asarray(s, dtype=np.float64)
+        return np.mod(s, self.period) if self.period else s
+
+    def a(self, s):
+        s = self._s(s)
+        inside = (s >= 0) & (s <= self.Lp)
+        return np.where(inside, self.a0 * np.sin(np.pi * s / self.Lp) ** 2 * np.sin(s), 0.0)
+
+    def da(self, s):
+        s = self._s(s)
+        inside = (s >= 0) & (s <= self.Lp)
+        k = np.pi / self.Lp
+        v = self.a0 * (k * np.sin(2 * k * s) * np.sin(s) + np.sin(k * s) ** 2 * np.cos(s))
+        return np.where(inside, v, 0.0)
+
+
+@dataclass
+class PlaneWave:
+    """a(s) = a0 sin(s): monochromatic, exactly periodic over whole lambda0."""
+    a0: float
+
+    def a(self, s):
+        return self.a0 * np.sin(np.asarray(s, dtype=np.float64))
+
+    def da(self, s):
+        return self.a0 * np.cos(np.asarray(s, dtype=np.float64))
+
+
+def laser_fields(n, dx, pulse, x_head=0.0, w0=None, centre=None, dtype=np.float64):
+    """(E, B) at t = 0 on the (n3, n2, n1) mesh: E2 = B3 = -a'(x_head - x1)
+    (times exp(-r_perp^2/w0^2) if ``w0``), every other component zero."""
+    n1, n2, n3 = n
+    i = np.arange(n1, dtype=np.float64)
+    s_e = x_head - i * dx[0]            # E2 at x1 = i dx1
+    s_b = x_head - (i + 0.5) * dx[0]    # B3 at x1 = (i+1/2) dx1
+    e2 = -pulse.da(s_e)
+    b3 = -pulse.da(s_b)
+    if w0 is None:
+        prof = np.ones((n3, n2))
+    else:
+        c2, c3 = centre if centre is not None else (n2 * dx[1] / 2, n3 * dx[2] / 2)
+        y = (np.arange(n2) + 0.5) * dx[1] - c2   # E2, B3 both at j+1/2
+        z = np.arange(n3) * dx[2] - c3           # and at k
+        prof = np.exp(-(z[:, None] ** 2 + y[None, :] ** 2) / w0 ** 2)
+    E = [np.zeros((n3, n2, n1), dtype=dtype) for _ in range(3)]
+    B = [np.zeros((n3, n2, n1), dtype=dtype) for _ in range(3)]
+    E[1][...] = (prof[:, :, None] * e2[None, None, :]).astype(dtype)
+    B[2][...] = (prof[:, :, None] * b3[None, None, :]).astype(dtype)
+    return E, B
+
+
+def random_fields(n, seed, scale=1.0, dtype=np.float64):
+    """Six independent uniform(-scale, scale) arrays (parity inputs)."""
+    g = rng(seed)
+    n1, n2, n3 = n
+    comps = [(scale * (2 * g.random((n3, n2, n1)) - 1)).astype(dtype) for _ in range(6)]
+    return comps[:3], comps[3:]
+
+
+def uniform_particles(npart, lo, hi, seed, u_th=0.0):
+    """x uniform in the box [lo, hi) (per direction), u ~ N(0, u_th^2) per
+    component (zeros for u_th = 0)."""
+    g = rng(seed)
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    x = lo[:, None] + (hi - lo)[:, None] * g.random((3, npart))
+    u = u_th * g.standard_normal((3, npart)) if u_th > 0 else np.zeros((3, npart))
+    return x, u
+
+
+def lattice_particles(n, dx, ppc_per_dim, seed, u_th):
+    """Plasma load: ppc_per_dim^3 particles per cell on a regular sub-lattice
+    (cell-centred offsets), thermal u ~ N(0, u_th^2)."""
+    n1, n2, n3 = n
+    p = ppc_per_dim
+    off = (np.arange(p) + 0.5) / p
+    cells = [np.arange(m, dtype=np.float64) for m in (n1, n2, n3)]
+    coords = []
+    for d in range(3):
+        c = (cells[d][:, None] + off[None, :]).ravel() * dx[d]
+        coords.append(c)
+    z, y, x = np.meshgrid(coords[2], coords[1], coords[0], indexing="ij")
+    X = np.stack([x.ravel(), y.ravel(), z.ravel()])
+    g = rng(seed)
+    U = u_th * g.standard_normal(X.shape)
+    return X, U
+
+
+def small_moves(x, dx, L, seed, frac=0.9):
+    """New positions within ``frac`` cells of ``x`` (periodic), for deposit
+    checks."""
+    g = rng(seed)
+    d = (2 * g.random(x.shape) - 1) * frac * np.asarray(dx)[:, None]
+    return np.mod(x + d, np.asarray(L)[:, None]), d
