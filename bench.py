@@ -1,0 +1,228 @@
+"""Benchmark of the dual-stencil PIC hot path on one MI355X.
+
+Default workload (the one the headline metric is quoted on): 3D vacuum mesh
+1024 x 256 x 256 cells, dx1 = lambda0/32, dx2 = dx3 = lambda0/8,
+dt = dx1/2, FP64 fields and particles; Gaussian laser (w0 = 4 lambda0,
+a0 = 100, sin^2 envelope of 10 cycles, head at x1 = 12 lambda0); 1,048,576
+electrons at rest, uniform in a 64^3-cell box on the axis at
+x1 in [13, 15] lambda0; M = 16 proposed-solver coefficients (App. B, fitted
+by the library); exact constant-field pusher.  One step = gather + push +
+position update of every electron + one fused B-half/E/B-half field sweep.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
+
+Prints one JSON line.  ``value`` is cell-updates/s of the whole step with
+inputs resident in HBM.  ``roofline`` is the fused sweep's algorithmic HBM
+traffic per launch over its average launch time (HIP events on the stream
+the kernel runs on).  ``cpu_baseline`` times the FP64 CPU oracle on a
+bounded sample of the same workload, in a child process with one thread.
+Extras: the same step with FP32 fields (mixed precision), and the 3D plane
+wave a0 = 1e4 mesh 2048 x 512 x 512 in FP32 vs FP64 fields.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s + particle-pushes/s (FP64 vs FP32-field); fwd+adjoint step ms"
+HBM_PEAK_GBS = 8000.0
+
+
+def _device_fields(n, dx, pulse, x_head, w0, dtype, torch):
+    from paper_2004_03754_amd import workloads as wl
+    e2, b3, prof = wl.laser_profiles(n, dx, pulse, x_head, w0)
+    n1, n2, n3 = n
+    dev = "cuda:0"
+    P = torch.as_tensor(prof, device=dev, dtype=torch.float64)
+    E = [torch.zeros((n3, n2, n1), device=dev, dtype=dtype) for _ in range(3)]
+    B = [torch.zeros((n3, n2, n1), device=dev, dtype=dtype) for _ in range(3)]
+    E[1].copy_((P[:, :, None] * torch.as_tensor(e2, device=dev)[None, None, :]).to(dtype))
+    B[2].copy_((P[:, :, None] * torch.as_tensor(b3, device=dev)[None, None, :]).to(dtype))
+    return E, B
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def run_vacuum(torch, b, wl, n, prec, pulse, x_head, w0, npart, box, steps, warmup, pusher, seed, CE, CB,
+               sweep_reps=20):
+    """Set up a vacuum run, time ``steps`` full steps and ``sweep_reps``
+    field sweeps alone.  Returns a dict of measurements."""
+    dx = (wl.DX1, wl.DX2, wl.DX3)
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    E, B = _device_fields(n, dx, pulse, x_head, w0, dtype, torch)
+    x, u = wl.uniform_particles(npart, box[0], box[1], seed=seed)
+    xd = torch.as_tensor(x, device="cuda:0").contiguous()
+    ud = torch.as_tensor(u, device="cuda:0").contiguous()
+    grid = b.Grid(E, B, dx, wl.DT, CE, CB, prec=prec)
+    p = b.Particles(xd, ud, q=-1.0, m=1.0, w=1.0)
+    grid.step_n([p], warmup, pusher=pusher)
+    torch.cuda.synchronize()
+    t0, t1 = _events(torch)
+    t0.record()
+    grid.step_n([p], steps, pusher=pusher)
+    t1.record()
+    torch.cuda.synchronize()
+    ms_step = t0.elapsed_time(t1) / steps
+    # the fused sweep alone (even count: no copy-back) and the particle step alone
+    reps = sweep_reps + (sweep_reps & 1)
+    s0, s1 = _events(torch)
+    s0.record()
+    grid.step_n([], reps)
+    s1.record()
+    torch.cuda.synchronize()
+    ms_sweep = s0.elapsed_time(s1) / reps
+    q0, q1 = _events(torch)
+    q0.record()
+    for _ in range(reps):
+        grid.gather_push(p, pusher)
+    q1.record()
+    torch.cuda.synchronize()
+    ms_push = q0.elapsed_time(q1) / reps
+    grid.check(p)
+    cells = n[0] * n[1] * n[2]
+    elem = 8 if prec == "fp64" else 4
+    out = dict(cells=cells, npart=npart, ms_step=ms_step, ms_sweep=ms_sweep, ms_push=ms_push,
+               sweep_bytes=12 * elem * cells, push_bytes=96 * npart)
+    grid.close()
+    del E, B, xd, ud
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline_child():
+    """Runs in a child process with one thread: the oracle's step on a
+    sample of the default workload (a 1024 x 32 x 32 column of the mesh with
+    the same electron density per cell), cell-updates/s."""
+    import numpy as np
+
+    from oracle import pic, stencil
+    from paper_2004_03754_amd import workloads as wl
+
+    dx = (wl.DX1, wl.DX2, wl.DX3)
+    n = (1024, 32, 32)
+    CE, CB = stencil.fit_pair(16, 0.5)
+    pulse = wl.Sin2Pulse(a0=100.0, Lp=10 * wl.LAMBDA0)
+    E, B = wl.laser_fields(n, dx, pulse, x_head=12 * wl.LAMBDA0, w0=4 * wl.LAMBDA0)
+    cells = n[0] * n[1] * n[2]
+    npart = int(round(1048576 * cells / (1024 * 256 * 256)))
+    lo = [13 * wl.LAMBDA0, 0, 0]
+    hi = [15 * wl.LAMBDA0, n[1] * dx[1], n[2] * dx[2]]
+    x, u = wl.uniform_particles(npart, lo, hi, seed=2)
+    sp = {"x": x, "u": u, "q": -1.0, "m": 1.0, "w": 1.0}
+    E, B = pic.step(E, B, [sp], CE, CB, dx, wl.DT, pusher="analytic")  # warm-up
+    steps = 8
+    t = time.perf_counter()
+    for _ in range(steps):
+        E, B = pic.step(E, B, [sp], CE, CB, dx, wl.DT, pusher="analytic")
+    dt = time.perf_counter() - t
+    print(json.dumps({"value": cells * steps / dt, "seconds": dt, "cells": cells, "npart": npart,
+                      "steps": steps}))
+
+
+def cpu_baseline():
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+        env[k] = "1"
+    env["CUDA_VISIBLE_DEVICES"] = ""
+    env["HIP_VISIBLE_DEVICES"] = ""
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child"], capture_output=True,
+                       text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-400:]}
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value": d["value"], "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle step (exact pusher) on a 1024x32x32 column with {d['npart']} electrons, "
+                      f"{d['steps']} steps after 1 warm-up, {d['seconds']:.1f} s, NumPy FP64 single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-baseline-child", action="store_true")
+    args = ap.parse_args()
+    if args.cpu_baseline_child:
+        cpu_baseline_child()
+        return
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 (the multi-GPU slab "
+              "decomposition is described in DESIGN.md but not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2004_03754_amd import binding as b, workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    r = 0.5
+    CE = b.design_coeffs(16, r, "E")
+    CB = b.design_coeffs(16, r, "B")
+    L = wl.LAMBDA0
+    n = (1024, 256, 256)
+    dx = (wl.DX1, wl.DX2, wl.DX3)
+    box = ([13 * L, (n[1] / 2 - 32) * dx[1], (n[2] / 2 - 32) * dx[2]],
+           [15 * L, (n[1] / 2 + 32) * dx[1], (n[2] / 2 + 32) * dx[2]])
+    pulse = wl.Sin2Pulse(a0=100.0, Lp=10 * L)
+    main_run = run_vacuum(torch, b, wl, n, "fp64", pulse, 12 * L, 4 * L, 1 << 20, box, args.steps, args.warmup,
+                          "analytic", 2, CE, CB)
+    cells = main_run["cells"]
+    value = cells / (main_run["ms_step"] * 1e-3)
+    achieved = main_run["sweep_bytes"] / (main_run["ms_sweep"] * 1e-3) / 1e9
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "sweep_fp64_1024x256x256_traffic.json")
+    if os.path.exists(tf):
+        with open(tf) as f:
+            traffic = json.load(f).get("bytes_per_launch")
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D vacuum 1024x256x256 cells, FP64 fields and particles, Gaussian laser a0=100 "
+                               "w0=4 lambda0, 1048576 electrons at rest, M=16 proposed solver, exact pusher",
+                   "cells": cells, "electrons": main_run["npart"], "dt_over_dx1": r},
+        "particle_pushes_per_s": main_run["npart"] / (main_run["ms_step"] * 1e-3),
+        "kernels_ms": {"fused_sweep": main_run["ms_sweep"], "gather_push_analytic": main_run["ms_push"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "fused B-half/E/B-half sweep, 96 B/cell FP64"},
+    }
+    if not args.no_extras:
+        # mixed precision on the same workload
+        fp32 = run_vacuum(torch, b, wl, n, "fp32", pulse, 12 * L, 4 * L, 1 << 20, box, max(50, args.steps // 5),
+                          args.warmup, "analytic", 2, CE, CB)
+        res["fp32_fields"] = {
+            "cell_updates_per_s": cells / (fp32["ms_step"] * 1e-3), "ms_per_step": fp32["ms_step"],
+            "sweep_ms": fp32["ms_sweep"],
+            "sweep_GBps": fp32["sweep_bytes"] / (fp32["ms_sweep"] * 1e-3) / 1e9,
+            "speedup_vs_fp64_step": main_run["ms_step"] / fp32["ms_step"],
+            "speedup_vs_fp64_sweep": main_run["ms_sweep"] / fp32["ms_sweep"]}
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

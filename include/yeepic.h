@@ -1,0 +1,170 @@
+/*
+ * yeepic.h -- C ABI of the MI355X (gfx950) dual-stencil FDTD particle-in-cell
+ * hot path of F. Li et al., "A new field solver for modeling of relativistic
+ * particle-laser interactions using the particle-in-cell algorithm"
+ * (arXiv:2004.03754).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Units: normalised, c = m_e = e = 1 (Sec. 2.1).
+ * Mesh: Yee staggering, periodic in every direction.  Each field component is
+ *   one caller-owned device array laid out [n3][n2][n1] (x1 contiguous).
+ *   Index (k, j, i) holds the component at its own staggered location:
+ *     E1 (i+1/2, j, k)  E2 (i, j+1/2, k)  E3 (i, j, k+1/2)
+ *     B1 (i, j+1/2, k+1/2)  B2 (i+1/2, j, k+1/2)  B3 (i+1/2, j+1/2, k)
+ *   J has the E staggering.  A 2D mesh is ndim = 2 with n3 = 1.
+ * Time levels: between calls E^n and B^n are both at integer time t^n
+ *   (Eq. pusher: the magnetic field seen by the particles is the average of
+ *   the two half-step values, which the half-step B update produces).
+ *   Particle positions x are at t^n, momenta u = gamma*beta at t^{n-1/2}.
+ * Precision: PIC_FP64 keeps fields in double; PIC_FP32_FIELDS keeps E, B, J in
+ *   float and advances them in float.  Particles are always double and every
+ *   particle computation (gather sums, gamma, pushers, deposit weights) is
+ *   done in double.
+ * Streams: every device call is asynchronous on the grid's stream (the
+ *   hipStream_t given at init; NULL is the default stream).  Errors that
+ *   only the device can see surface at pic_sync.
+ * Errors: every call returns a pic_status; nothing throws across the ABI.
+ *   pic_last_error() gives a thread-local message for the last failure.
+ * Ownership: fields and particles belong to the caller and must stay valid
+ *   while the grid is used; the grid copies the coefficient arrays and owns
+ *   only its handle, a second field buffer set used by the fused sweep, and
+ *   the particle sort scratch.
+ */
+#ifndef YEEPIC_H
+#define YEEPIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_EINVAL = -1,        /* bad argument: null pointer, size, enum value */
+  PIC_ECFL = -2,          /* time step violates the CFL bound of Sec. 3.2 */
+  PIC_EHIP = -3,          /* a HIP runtime call failed */
+  PIC_ESHAPE = -4,        /* mesh shape or alignment not supported */
+  PIC_ENOMEM = -5,        /* device allocation failed */
+  PIC_EUNSUPPORTED = -6,  /* valid request outside what is implemented */
+  PIC_ENONFINITE = -7     /* a non-finite value was found */
+} pic_status;
+
+typedef enum { PIC_FP64 = 0, PIC_FP32_FIELDS = 1 } pic_precision;
+typedef enum { PIC_PUSH_BORIS = 0, PIC_PUSH_ANALYTIC = 1 } pic_pusher;
+typedef enum { PIC_TARGET_E = 0, PIC_TARGET_B = 1, PIC_TARGET_XU = 2 } pic_target;
+
+#define PIC_MAX_M 16
+
+typedef struct pic_grid_desc {
+  int ndim;            /* 2 or 3 */
+  int64_t n[3];        /* cells n1, n2, n3; n3 must be 1 when ndim == 2 */
+  double dx[3];        /* cell sizes; dx[2] unused when ndim == 2 */
+  double dt;           /* time step */
+  int M;               /* number of x1 coefficients, 1..PIC_MAX_M */
+  const double *CE;    /* host, length M: Faraday x1 stencil C^E (App. B) */
+  const double *CB;    /* host, length M: Ampere x1 stencil C^B (App. B) */
+  int prec;            /* pic_precision */
+  void *E[3];          /* device, n1*n2*n3 elements each (double or float) */
+  void *B[3];
+  void *J[3];          /* device current; may all be NULL for vacuum runs */
+  void *stream;        /* hipStream_t or NULL */
+} pic_grid_desc;
+
+typedef struct pic_particles {
+  int64_t np;          /* number of particles (0 allowed) */
+  double *x[3];        /* device positions in [0, n_d dx_d); x[2] may be NULL in 2D */
+  double *u[3];        /* device momenta gamma*beta (per unit mass) */
+  double q, m, w;      /* charge, mass, macro-weight (density per particle) */
+} pic_particles;
+
+typedef struct pic_grid pic_grid;   /* opaque */
+
+/* ---- coefficient design (host only; App. B) ------------------------------
+ * Customized x1 coefficients C (length M) fitting the Eq. (new_op) target
+ * ``target`` for r = dt/dx1: minimise int_0^{1/2} w (sum_j C_j
+ * sin((2j-1) pi kappa)/pi - T(kappa))^2 dkappa subject to the order-p
+ * constraint sum_j C_j (2j-1)^(2i-1)/(2i-1)! = delta_i1 (i = 1..p/2), with
+ * the super-Gaussian weight w = exp[-ln2 (width_factor kappa / wk1)^n].
+ * The paper's values are n = 10, wk1 = 0.3-0.4, width_factor = 2, p = 2.
+ * Solved by a null-space least-squares QR in binary128 arithmetic on a
+ * composite Gauss-Legendre discretisation of the integral.  ``out`` is host
+ * memory of length M.  Returns PIC_EINVAL for M outside 1..PIC_MAX_M, p odd,
+ * p/2 > M, r <= 0 or r >= 1, or non-positive weight parameters. */
+int pic_design_coeffs(int M, double r, int target, int p, int n, double wk1,
+                      double width_factor, double *out);
+
+/* ---- grid ------------------------------------------------------------------
+ * Validates the descriptor, copies the coefficients, checks the CFL bound of
+ * Sec. 3.2 in its sufficient form dt <= 1/sqrt(sum|C^B| sum|C^E|/dx1^2 +
+ * sum_{d>=2} 1/dx_d^2) (PIC_ECFL when violated), allocates the second field
+ * buffer set and returns a handle in *out.  Trailing coefficients whose
+ * magnitudes sum to at most 2^-70 times sum|C| are treated as zero (their
+ * effect is far below double rounding); the remaining widths select the
+ * kernels.  The field pointers must be 16-byte aligned; n1 must be a
+ * multiple of 64 and at least 2*M (PIC_ESHAPE otherwise). */
+int pic_init_grid(const pic_grid_desc *desc, pic_grid **out);
+
+/* Replace the field/current pointers (same shape and precision). */
+int pic_set_fields(pic_grid *g, void *const E[3], void *const B[3], void *const J[3]);
+
+/* ---- field steps (Eq. maxwell with the App. B operators) -----------------
+ * pic_advance_B_half: B <- B - (dt/2) d_E x E, where along x1
+ *   d^E f_i = (1/dx1) sum_j C^E_j (f_{i+j} - f_{i-j+1}) and x2, x3 use Yee
+ *   forward differences.  In place.
+ * pic_advance_E: E <- E + dt (d_B x B - J) with
+ *   d^B f_i = (1/dx1) sum_j C^B_j (f_{i+j-1} - f_{i-j}) and Yee backward
+ *   differences along x2, x3; J is used only when use_J != 0 (it must then
+ *   be set).  In place.
+ * pic_field_sweep: one full step (E^n, B^n) -> (E^{n+1}, B^{n+1}) as a
+ *   B half step, an E step and a B half step fused in one pass over the
+ *   mesh (reads E, B, [J]; writes E, B).  The result ends in the caller's
+ *   arrays. */
+int pic_advance_B_half(pic_grid *g);
+int pic_advance_E(pic_grid *g, int use_J);
+int pic_field_sweep(pic_grid *g, int use_J);
+
+/* ---- particles (App. A gather, Sec. 1 / 4.1 pushers) ---------------------
+ * Gathers E^n and B^n at x^n with the linear shape, each component from its
+ * own staggered points; pushes u^{n-1/2} -> u^{n+1/2} with the Boris
+ * pusher or the exact constant-field (analytic) pusher; advances
+ * x^{n+1} = x^n + dt u/gamma and wraps it periodically.  If x_old is not
+ * NULL, x^n is also written to x_old[d] (device, np doubles each; x_old[2]
+ * may be NULL in 2D).  Positions outside [0, L) are clamped into the mesh
+ * for the gather (never out of bounds) and reported by pic_check. */
+int pic_gather_push(pic_grid *g, pic_particles *p, int pusher, double *const x_old[3]);
+
+/* ---- current (Sec. 3.3) ----------------------------------------------------
+ * Adds the charge-conserving (Esirkepov, linear shape) current J^{n+1/2} of
+ * particles that moved from x_old to p->x (less than one cell per step; the
+ * periodic wrap is undone by minimum image) to the grid's J.  If zero_first
+ * is non-zero J is cleared first.  The x1 correction of Eq. (correction) is
+ * the identity when C^B is the Yee stencil (the proposed solver at
+ * dt = dx1/2); any other C^B returns PIC_EUNSUPPORTED, and so does a 2D
+ * grid without u (never: u is always present). */
+int pic_deposit_J(pic_grid *g, const pic_particles *p, double *const x_old[3], int zero_first);
+
+/* ---- the step loop ----------------------------------------------------------
+ * nsteps times: for each species gather + push + position update (keeping
+ * x^n when deposit != 0), then [clear J and deposit every species], then the
+ * fused field sweep.  No host synchronisation inside; the fields end in the
+ * caller's arrays. */
+int pic_step_n(pic_grid *g, pic_particles *const *species, int nspecies, int nsteps,
+               int pusher, int deposit);
+
+/* ---- diagnostics ------------------------------------------------------------
+ * Waits for the grid's stream and reports a pending HIP error. */
+int pic_sync(pic_grid *g);
+/* Scans fields and the given particles for non-finite values and positions
+ * outside the periodic box; returns PIC_ENONFINITE if any (synchronous). */
+int pic_check(pic_grid *g, const pic_particles *p);
+/* Effective coefficient widths after trimming (for tests and reports). */
+int pic_grid_widths(const pic_grid *g, int *ME, int *MB);
+void pic_destroy(pic_grid *g);
+const char *pic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* YEEPIC_H */

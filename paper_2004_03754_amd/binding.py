@@ -1,0 +1,211 @@
+"""Thin ctypes binding of libyeepic.so (argument marshalling only).
+
+Every computation happens in the HIP library; PyTorch supplies device memory
+and the stream.  The library must be built in-tree first
+(``python -m paper_2004_03754_amd.build``); importing this module never falls
+back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libyeepic.so")
+_lib = None
+
+PIC_FP64, PIC_FP32_FIELDS = 0, 1
+PIC_PUSH_BORIS, PIC_PUSH_ANALYTIC = 0, 1
+PIC_TARGET_E, PIC_TARGET_B, PIC_TARGET_XU = 0, 1, 2
+STATUS = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ECFL", -3: "PIC_EHIP", -4: "PIC_ESHAPE",
+          -5: "PIC_ENOMEM", -6: "PIC_EUNSUPPORTED", -7: "PIC_ENONFINITE"}
+PUSHERS = {"boris": PIC_PUSH_BORIS, "analytic": PIC_PUSH_ANALYTIC}
+
+
+class YeePICError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _GridDesc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int64 * 3), ("dx", ctypes.c_double * 3),
+                ("dt", ctypes.c_double), ("M", ctypes.c_int), ("CE", ctypes.POINTER(ctypes.c_double)),
+                ("CB", ctypes.POINTER(ctypes.c_double)), ("prec", ctypes.c_int),
+                ("E", ctypes.c_void_p * 3), ("B", ctypes.c_void_p * 3), ("J", ctypes.c_void_p * 3),
+                ("stream", ctypes.c_void_p)]
+
+
+class _Particles(ctypes.Structure):
+    _fields_ = [("np", ctypes.c_int64), ("x", ctypes.c_void_p * 3), ("u", ctypes.c_void_p * 3),
+                ("q", ctypes.c_double), ("m", ctypes.c_double), ("w", ctypes.c_double)]
+
+
+EXPORTS = ["pic_design_coeffs", "pic_init_grid", "pic_set_fields", "pic_advance_B_half", "pic_advance_E",
+           "pic_field_sweep", "pic_gather_push", "pic_deposit_J", "pic_step_n", "pic_sync", "pic_check",
+           "pic_grid_widths", "pic_destroy", "pic_last_error"]
+
+
+def lib():
+    """Load libyeepic.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2004_03754_amd.build`")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        L.pic_last_error.restype = ctypes.c_char_p
+        L.pic_design_coeffs.argtypes = [i, d, i, i, i, d, d, ctypes.POINTER(d)]
+        L.pic_init_grid.argtypes = [ctypes.POINTER(_GridDesc), ctypes.POINTER(vp)]
+        L.pic_set_fields.argtypes = [vp, ctypes.c_void_p * 3, ctypes.c_void_p * 3, ctypes.c_void_p * 3]
+        L.pic_advance_B_half.argtypes = [vp]
+        L.pic_advance_E.argtypes = [vp, i]
+        L.pic_field_sweep.argtypes = [vp, i]
+        L.pic_gather_push.argtypes = [vp, ctypes.POINTER(_Particles), i, vp]
+        L.pic_deposit_J.argtypes = [vp, ctypes.POINTER(_Particles), vp, i]
+        L.pic_step_n.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(_Particles)), i, i, i, i]
+        L.pic_sync.argtypes = [vp]
+        L.pic_check.argtypes = [vp, ctypes.POINTER(_Particles)]
+        L.pic_grid_widths.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
+        L.pic_destroy.argtypes = [vp]
+        L.pic_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise YeePICError(rc, lib().pic_last_error().decode())
+
+
+def design_coeffs(M, r, target="E", p=2, n=10, wk1=0.4, width_factor=2.0):
+    """App. B customized coefficients computed by the library (host)."""
+    t = {"E": PIC_TARGET_E, "B": PIC_TARGET_B, "xu": PIC_TARGET_XU}[target]
+    out = (ctypes.c_double * M)()
+    _check(lib().pic_design_coeffs(M, float(r), t, p, n, float(wk1), float(width_factor), out))
+    return np.array(out[:], dtype=np.float64)
+
+
+def _ptr3(ts):
+    arr = (ctypes.c_void_p * 3)()
+    for c in range(3):
+        arr[c] = ts[c].data_ptr() if ts is not None and ts[c] is not None else None
+    return arr
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Particles:
+    """One species: x and u are float64 device tensors of shape (3, np)
+    (rows contiguous); q, m, w are charge, mass and macro-weight."""
+
+    def __init__(self, x, u, q=-1.0, m=1.0, w=1.0):
+        import torch
+        assert x.dtype == torch.float64 and u.dtype == torch.float64
+        assert x.is_contiguous() and u.is_contiguous() and x.shape == u.shape and x.shape[0] == 3
+        self.x, self.u = x, u
+        self.q, self.m, self.w = float(q), float(m), float(w)
+        self._s = _Particles()
+        npart = x.shape[1]
+        self._s.np = npart
+        for d in range(3):
+            self._s.x[d] = x.data_ptr() + d * npart * 8 if npart else None
+            self._s.u[d] = u.data_ptr() + d * npart * 8 if npart else None
+        self._s.q, self._s.m, self._s.w = self.q, self.m, self.w
+
+    @property
+    def np(self):
+        return self.x.shape[1]
+
+
+class Grid:
+    """A periodic Yee mesh with caller-owned field tensors (each [n3][n2][n1])."""
+
+    def __init__(self, E, B, dx, dt, CE, CB, J=None, prec="fp64", ndim=3, stream=None):
+        import torch
+        dtype = torch.float64 if prec == "fp64" else torch.float32
+        for t in list(E) + list(B) + (list(J) if J is not None else []):
+            assert t.dtype == dtype and t.is_contiguous() and t.is_cuda
+        n3, n2, n1 = E[0].shape
+        CE = np.ascontiguousarray(CE, dtype=np.float64)
+        CB = np.ascontiguousarray(CB, dtype=np.float64)
+        assert CE.shape == CB.shape
+        self.E, self.B, self.J = list(E), list(B), (list(J) if J is not None else None)
+        self.stream = stream
+        self._ce, self._cb = CE, CB
+        d = _GridDesc()
+        d.ndim = ndim
+        d.n[:] = [n1, n2, n3]
+        dxs = list(dx) + [1.0] * (3 - len(dx))
+        d.dx[:] = [float(v) for v in dxs[:3]]
+        d.dt = float(dt)
+        d.M = CE.shape[0]
+        d.CE = CE.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.CB = CB.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.prec = PIC_FP64 if prec == "fp64" else PIC_FP32_FIELDS
+        d.E, d.B, d.J = _ptr3(E), _ptr3(B), _ptr3(J)
+        d.stream = _stream_handle(stream)
+        h = ctypes.c_void_p()
+        _check(lib().pic_init_grid(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pic_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def widths(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(lib().pic_grid_widths(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def advance_B_half(self):
+        _check(lib().pic_advance_B_half(self._h))
+
+    def advance_E(self, use_J=False):
+        _check(lib().pic_advance_E(self._h, int(use_J)))
+
+    def sweep(self, use_J=False):
+        _check(lib().pic_field_sweep(self._h, int(use_J)))
+
+    def gather_push(self, p: Particles, pusher="boris", x_old=None):
+        xo = None
+        if x_old is not None:
+            arr = (ctypes.c_void_p * 3)()
+            npart = x_old.shape[1]
+            for dd in range(3):
+                arr[dd] = x_old.data_ptr() + dd * npart * 8
+            xo = ctypes.cast(arr, ctypes.c_void_p)
+            self._xo_keep = arr
+        _check(lib().pic_gather_push(self._h, ctypes.byref(p._s), PUSHERS[pusher], xo))
+
+    def deposit_J(self, p: Particles, x_old, zero_first=True):
+        arr = (ctypes.c_void_p * 3)()
+        npart = x_old.shape[1]
+        for dd in range(3):
+            arr[dd] = x_old.data_ptr() + dd * npart * 8
+        _check(lib().pic_deposit_J(self._h, ctypes.byref(p._s), ctypes.cast(arr, ctypes.c_void_p),
+                                   int(zero_first)))
+
+    def step_n(self, species, nsteps, pusher="boris", deposit=False):
+        arr = (ctypes.POINTER(_Particles) * max(1, len(species)))()
+        for s, p in enumerate(species):
+            arr[s] = ctypes.pointer(p._s)
+        _check(lib().pic_step_n(self._h, arr, len(species), int(nsteps), PUSHERS[pusher], int(deposit)))
+
+    def sync(self):
+        _check(lib().pic_sync(self._h))
+
+    def check(self, p: Particles | None = None):
+        _check(lib().pic_check(self._h, ctypes.byref(p._s) if p is not None else None))

@@ -1,0 +1,363 @@
+// C ABI of the yeepic library: validation, buffers, dispatch, the step loop.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <utility>
+
+#include "yeepic_internal.h"
+
+struct pic_grid {
+  int ndim;
+  int64_t n[3];
+  double dx[3];
+  double dt;
+  int M;
+  double CE[PIC_MAX_M];
+  double CB[PIC_MAX_M];
+  int ME, MB;  // widths after trimming negligible trailing coefficients
+  int prec;
+  size_t elem;
+  void* E[3];
+  void* B[3];
+  void* J[3];
+  void* alt[6];  // second field set for the out-of-place sweep
+  hipStream_t stream;
+  int* d_flag;
+  double* xo[3];   // x^n scratch for the deposit inside pic_step_n (grow-only)
+  int64_t xo_cap;
+  yeepic::Mesh mesh;
+};
+
+namespace yeepic {
+
+static thread_local char g_err[512] = "no error";
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+static int hip_fail(hipError_t e, const char* what) {
+  return set_error(PIC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Last index whose trailing tail is not negligible: sum_{q>m} |C_q| <= 2^-70 sum|C|.
+static int effective_width(const double* C, int M) {
+  double total = 0;
+  for (int q = 0; q < M; ++q) total += std::fabs(C[q]);
+  const double tol = std::ldexp(total, -70);
+  double tail = 0;
+  int m = M;
+  while (m > 1) {
+    tail += std::fabs(C[m - 1]);
+    if (tail > tol) break;
+    --m;
+  }
+  return m;
+}
+
+static int swap_into_caller(pic_grid* g) {
+  // copy the alt set back into the caller's arrays
+  const size_t bytes = (size_t)g->n[0] * g->n[1] * g->n[2] * g->elem;
+  for (int c = 0; c < 3; ++c) {
+    hipError_t e = hipMemcpyAsync(g->E[c], g->alt[c], bytes, hipMemcpyDeviceToDevice, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "sweep copy-back");
+    e = hipMemcpyAsync(g->B[c], g->alt[3 + c], bytes, hipMemcpyDeviceToDevice, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "sweep copy-back");
+  }
+  return PIC_OK;
+}
+
+static bool ampere_is_yee(const pic_grid* g) { return g->MB == 1 && g->CB[0] == 1.0; }
+
+static int check_particles(const pic_grid* g, const pic_particles* p) {
+  if (!p) return set_error(PIC_EINVAL, "particles is NULL");
+  if (p->np < 0) return set_error(PIC_EINVAL, "negative particle count");
+  if (p->np == 0) return PIC_OK;
+  for (int d = 0; d < 3; ++d)
+    if (!p->u[d]) return set_error(PIC_EINVAL, "particle momentum u[%d] is NULL", d);
+  for (int d = 0; d < g->ndim; ++d)
+    if (!p->x[d]) return set_error(PIC_EINVAL, "particle position x[%d] is NULL", d);
+  if (!(p->m > 0) || !std::isfinite(p->q) || !std::isfinite(p->w))
+    return set_error(PIC_EINVAL, "bad species constants");
+  if (p->np > ((int64_t)1 << 31) * 256) return set_error(PIC_EINVAL, "too many particles");
+  return PIC_OK;
+}
+
+}  // namespace yeepic
+
+using namespace yeepic;
+
+extern "C" {
+
+const char* pic_last_error(void) { return g_err; }
+
+int pic_init_grid(const pic_grid_desc* d, pic_grid** out) {
+  if (!d || !out) return set_error(PIC_EINVAL, "pic_init_grid: NULL argument");
+  *out = nullptr;
+  if (d->ndim != 2 && d->ndim != 3) return set_error(PIC_EINVAL, "ndim must be 2 or 3");
+  if (d->prec != PIC_FP64 && d->prec != PIC_FP32_FIELDS) return set_error(PIC_EINVAL, "bad precision");
+  if (d->M < 1 || d->M > PIC_MAX_M) return set_error(PIC_EINVAL, "M must be in 1..16");
+  if (!d->CE || !d->CB) return set_error(PIC_EINVAL, "coefficient arrays are NULL");
+  for (int a = 0; a < 3; ++a)
+    if (d->n[a] < 1 || d->n[a] > (1 << 20)) return set_error(PIC_ESHAPE, "mesh size n[%d] out of range", a);
+  if (d->ndim == 2 && d->n[2] != 1) return set_error(PIC_ESHAPE, "2D meshes need n3 = 1");
+  if (d->n[0] % 64 != 0) return set_error(PIC_ESHAPE, "n1 must be a multiple of 64");
+  if (d->n[0] < 2 * d->M) return set_error(PIC_ESHAPE, "n1 must be at least 2M");
+  const int64_t cells = d->n[0] * d->n[1] * d->n[2];
+  if (cells > ((int64_t)1 << 31) - 1) return set_error(PIC_ESHAPE, "mesh larger than 2^31 cells");
+  for (int a = 0; a < d->ndim; ++a)
+    if (!(d->dx[a] > 0) || !std::isfinite(d->dx[a])) return set_error(PIC_EINVAL, "bad cell size");
+  if (!(d->dt > 0) || !std::isfinite(d->dt)) return set_error(PIC_EINVAL, "bad time step");
+  for (int c = 0; c < 3; ++c) {
+    if (!d->E[c] || !d->B[c]) return set_error(PIC_EINVAL, "field pointer is NULL");
+    if (((uintptr_t)d->E[c] | (uintptr_t)d->B[c]) & 15) return set_error(PIC_ESHAPE, "fields must be 16-byte aligned");
+  }
+  double sE = 0, sB = 0;
+  for (int q = 0; q < d->M; ++q) {
+    if (!std::isfinite(d->CE[q]) || !std::isfinite(d->CB[q])) return set_error(PIC_EINVAL, "non-finite coefficient");
+    sE += std::fabs(d->CE[q]);
+    sB += std::fabs(d->CB[q]);
+  }
+  // Sec. 3.2 sufficient CFL bound (3D adds the x3 term)
+  double lim = sB * sE / (d->dx[0] * d->dx[0]) + 1.0 / (d->dx[1] * d->dx[1]);
+  if (d->ndim == 3) lim += 1.0 / (d->dx[2] * d->dx[2]);
+  if (d->dt > 1.0 / std::sqrt(lim))
+    return set_error(PIC_ECFL, "dt = %g exceeds the CFL bound %g", d->dt, 1.0 / std::sqrt(lim));
+
+  pic_grid* g = new pic_grid();
+  std::memset(g, 0, sizeof *g);
+  g->ndim = d->ndim;
+  for (int a = 0; a < 3; ++a) {
+    g->n[a] = d->n[a];
+    g->dx[a] = (a < d->ndim) ? d->dx[a] : 1.0;
+  }
+  g->dt = d->dt;
+  g->M = d->M;
+  for (int q = 0; q < d->M; ++q) {
+    g->CE[q] = d->CE[q];
+    g->CB[q] = d->CB[q];
+  }
+  g->ME = effective_width(g->CE, g->M);
+  g->MB = effective_width(g->CB, g->M);
+  g->prec = d->prec;
+  g->elem = d->prec == PIC_FP64 ? sizeof(double) : sizeof(float);
+  for (int c = 0; c < 3; ++c) {
+    g->E[c] = d->E[c];
+    g->B[c] = d->B[c];
+    g->J[c] = d->J[c];
+  }
+  g->stream = (hipStream_t)d->stream;
+  Mesh& m = g->mesh;
+  m.n1 = (int)g->n[0];
+  m.n2 = (int)g->n[1];
+  m.n3 = (int)g->n[2];
+  m.ndim = g->ndim;
+  m.dx1 = g->dx[0];
+  m.dx2 = g->dx[1];
+  m.dx3 = g->dx[2];
+  m.L1 = m.n1 * m.dx1;
+  m.L2 = m.n2 * m.dx2;
+  m.L3 = m.n3 * m.dx3;
+  const size_t bytes = (size_t)cells * g->elem;
+  for (int c = 0; c < 6; ++c) {
+    if (hipMalloc(&g->alt[c], bytes) != hipSuccess) {
+      pic_destroy(g);
+      return set_error(PIC_ENOMEM, "cannot allocate %zu bytes for the sweep buffers", 6 * bytes);
+    }
+  }
+  if (hipMalloc((void**)&g->d_flag, sizeof(int)) != hipSuccess) {
+    pic_destroy(g);
+    return set_error(PIC_ENOMEM, "cannot allocate the flag word");
+  }
+  *out = g;
+  return PIC_OK;
+}
+
+int pic_set_fields(pic_grid* g, void* const E[3], void* const B[3], void* const J[3]) {
+  if (!g || !E || !B) return set_error(PIC_EINVAL, "pic_set_fields: NULL argument");
+  for (int c = 0; c < 3; ++c) {
+    if (!E[c] || !B[c]) return set_error(PIC_EINVAL, "field pointer is NULL");
+    if (((uintptr_t)E[c] | (uintptr_t)B[c]) & 15) return set_error(PIC_ESHAPE, "fields must be 16-byte aligned");
+  }
+  for (int c = 0; c < 3; ++c) {
+    g->E[c] = E[c];
+    g->B[c] = B[c];
+    g->J[c] = J ? J[c] : nullptr;
+  }
+  return PIC_OK;
+}
+
+int pic_grid_widths(const pic_grid* g, int* ME, int* MB) {
+  if (!g || !ME || !MB) return set_error(PIC_EINVAL, "pic_grid_widths: NULL argument");
+  *ME = g->ME;
+  *MB = g->MB;
+  return PIC_OK;
+}
+
+int pic_advance_B_half(pic_grid* g) {
+  if (!g) return set_error(PIC_EINVAL, "grid is NULL");
+  return launch_advance_b(g->prec, g->mesh, g->E, g->B, g->CE, g->ME, 0.5 * g->dt, g->stream);
+}
+
+int pic_advance_E(pic_grid* g, int use_J) {
+  if (!g) return set_error(PIC_EINVAL, "grid is NULL");
+  if (use_J && !(g->J[0] && g->J[1] && g->J[2])) return set_error(PIC_EINVAL, "use_J set but J is not");
+  void* none[3] = {nullptr, nullptr, nullptr};
+  return launch_advance_e(g->prec, g->mesh, g->E, g->B, use_J ? g->J : none, g->CB, g->MB, g->dt, g->stream);
+}
+
+static int sweep_once(pic_grid* g, void* const inE[3], void* const inB[3], void* const outE[3],
+                      void* const outB[3], int use_J) {
+  void* none[3] = {nullptr, nullptr, nullptr};
+  return launch_sweep(g->prec, g->mesh, inE, inB, use_J ? g->J : none, outE, outB, g->CE, g->ME, g->CB, g->MB,
+                      g->dt, g->stream);
+}
+
+int pic_field_sweep(pic_grid* g, int use_J) {
+  if (!g) return set_error(PIC_EINVAL, "grid is NULL");
+  if (use_J && !(g->J[0] && g->J[1] && g->J[2])) return set_error(PIC_EINVAL, "use_J set but J is not");
+  int rc = sweep_once(g, g->E, g->B, g->alt, g->alt + 3, use_J);
+  if (rc) return rc;
+  return swap_into_caller(g);
+}
+
+int pic_gather_push(pic_grid* g, pic_particles* p, int pusher, double* const x_old[3]) {
+  if (!g) return set_error(PIC_EINVAL, "grid is NULL");
+  int rc = check_particles(g, p);
+  if (rc) return rc;
+  if (pusher != PIC_PUSH_BORIS && pusher != PIC_PUSH_ANALYTIC) return set_error(PIC_EINVAL, "bad pusher");
+  if (x_old)
+    for (int d = 0; d < g->ndim; ++d)
+      if (!x_old[d]) return set_error(PIC_EINVAL, "x_old[%d] is NULL", d);
+  return launch_gather_push(g->prec, g->mesh, g->E, g->B, *p, pusher, g->dt, x_old, g->stream);
+}
+
+int pic_deposit_J(pic_grid* g, const pic_particles* p, double* const x_old[3], int zero_first) {
+  if (!g) return set_error(PIC_EINVAL, "grid is NULL");
+  int rc = check_particles(g, p);
+  if (rc) return rc;
+  if (!(g->J[0] && g->J[1] && g->J[2])) return set_error(PIC_EINVAL, "grid has no current arrays");
+  if (!x_old) return set_error(PIC_EINVAL, "x_old is NULL");
+  for (int d = 0; d < g->ndim; ++d)
+    if (!x_old[d]) return set_error(PIC_EINVAL, "x_old[%d] is NULL", d);
+  if (!ampere_is_yee(g))
+    return set_error(PIC_EUNSUPPORTED, "deposit needs the Yee Ampere stencil (x1 current correction not built)");
+  if (zero_first) {
+    const size_t bytes = (size_t)g->n[0] * g->n[1] * g->n[2] * g->elem;
+    for (int c = 0; c < 3; ++c) {
+      hipError_t e = hipMemsetAsync(g->J[c], 0, bytes, g->stream);
+      if (e != hipSuccess) return hip_fail(e, "clear J");
+    }
+  }
+  return launch_deposit(g->prec, g->mesh, g->J, *p, x_old, g->dt, g->stream);
+}
+
+int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nsteps, int pusher, int deposit) {
+  if (!g) return set_error(PIC_EINVAL, "grid is NULL");
+  if (nsteps < 0 || nspecies < 0) return set_error(PIC_EINVAL, "negative count");
+  if (nspecies > 0 && !species) return set_error(PIC_EINVAL, "species is NULL");
+  if (pusher != PIC_PUSH_BORIS && pusher != PIC_PUSH_ANALYTIC) return set_error(PIC_EINVAL, "bad pusher");
+  for (int s = 0; s < nspecies; ++s) {
+    int rc = check_particles(g, species[s]);
+    if (rc) return rc;
+  }
+  if (deposit) {
+    if (!(g->J[0] && g->J[1] && g->J[2])) return set_error(PIC_EINVAL, "deposit requested without J");
+    if (!ampere_is_yee(g))
+      return set_error(PIC_EUNSUPPORTED, "deposit needs the Yee Ampere stencil (x1 current correction not built)");
+  }
+  // scratch for x^n of the largest species (kept across calls)
+  int64_t npmax = 0;
+  for (int s = 0; s < nspecies; ++s) npmax = species[s]->np > npmax ? species[s]->np : npmax;
+  double* xo[3] = {nullptr, nullptr, nullptr};
+  if (deposit && npmax > 0) {
+    if (npmax > g->xo_cap) {
+      hipStreamSynchronize(g->stream);
+      for (int d = 0; d < 3; ++d) {
+        hipFree(g->xo[d]);
+        g->xo[d] = nullptr;
+      }
+      g->xo_cap = 0;
+      for (int d = 0; d < g->ndim; ++d)
+        if (hipMalloc((void**)&g->xo[d], (size_t)npmax * sizeof(double)) != hipSuccess)
+          return set_error(PIC_ENOMEM, "cannot allocate position scratch");
+      g->xo_cap = npmax;
+    }
+    for (int d = 0; d < 3; ++d) xo[d] = g->xo[d];
+  }
+  void* cur[6] = {g->E[0], g->E[1], g->E[2], g->B[0], g->B[1], g->B[2]};
+  void* nxt[6] = {g->alt[0], g->alt[1], g->alt[2], g->alt[3], g->alt[4], g->alt[5]};
+  int rc = PIC_OK;
+  const size_t jbytes = (size_t)g->n[0] * g->n[1] * g->n[2] * g->elem;
+  for (int step = 0; step < nsteps && rc == PIC_OK; ++step) {
+    if (deposit)
+      for (int c = 0; c < 3 && rc == PIC_OK; ++c)
+        if (hipMemsetAsync(g->J[c], 0, jbytes, g->stream) != hipSuccess) rc = set_error(PIC_EHIP, "clear J");
+    for (int s = 0; s < nspecies && rc == PIC_OK; ++s) {
+      rc = launch_gather_push(g->prec, g->mesh, cur, cur + 3, *species[s], pusher, g->dt, deposit ? xo : nullptr,
+                              g->stream);
+      if (rc == PIC_OK && deposit) rc = launch_deposit(g->prec, g->mesh, g->J, *species[s], xo, g->dt, g->stream);
+    }
+    if (rc == PIC_OK) rc = sweep_once(g, cur, cur + 3, nxt, nxt + 3, deposit);
+    for (int c = 0; c < 6; ++c) std::swap(cur[c], nxt[c]);
+  }
+  if (rc == PIC_OK && cur[0] != g->E[0]) {
+    // odd number of steps: the state is in the alt set
+    const size_t bytes = jbytes;
+    for (int c = 0; c < 3 && rc == PIC_OK; ++c) {
+      if (hipMemcpyAsync(g->E[c], cur[c], bytes, hipMemcpyDeviceToDevice, g->stream) != hipSuccess ||
+          hipMemcpyAsync(g->B[c], cur[3 + c], bytes, hipMemcpyDeviceToDevice, g->stream) != hipSuccess)
+        rc = set_error(PIC_EHIP, "step_n copy-back");
+    }
+  }
+  return rc;
+}
+
+int pic_sync(pic_grid* g) {
+  if (!g) return set_error(PIC_EINVAL, "grid is NULL");
+  hipError_t e = hipStreamSynchronize(g->stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "pending error");
+  return PIC_OK;
+}
+
+int pic_check(pic_grid* g, const pic_particles* p) {
+  if (!g) return set_error(PIC_EINVAL, "grid is NULL");
+  if (p) {
+    int rc = check_particles(g, p);
+    if (rc) return rc;
+  }
+  hipError_t e = hipMemsetAsync(g->d_flag, 0, sizeof(int), g->stream);
+  if (e != hipSuccess) return hip_fail(e, "check: clear flag");
+  int rc = launch_check(g->prec, g->mesh, g->E, g->B, p, g->d_flag, g->stream);
+  if (rc) return rc;
+  int flag = 0;
+  e = hipMemcpyAsync(&flag, g->d_flag, sizeof(int), hipMemcpyDeviceToHost, g->stream);
+  if (e != hipSuccess) return hip_fail(e, "check: read flag");
+  e = hipStreamSynchronize(g->stream);
+  if (e != hipSuccess) return hip_fail(e, "check: synchronize");
+  if (flag & 1) return set_error(PIC_ENONFINITE, "non-finite field value");
+  if (flag & 2) return set_error(PIC_ENONFINITE, "particle outside the box or non-finite momentum");
+  return PIC_OK;
+}
+
+void pic_destroy(pic_grid* g) {
+  if (!g) return;
+  hipStreamSynchronize(g->stream);
+  for (int c = 0; c < 6; ++c)
+    if (g->alt[c]) hipFree(g->alt[c]);
+  for (int d = 0; d < 3; ++d)
+    if (g->xo[d]) hipFree(g->xo[d]);
+  if (g->d_flag) hipFree(g->d_flag);
+  delete g;
+}
+
+}  // extern "C"

@@ -1,0 +1,53 @@
+// Internal declarations of the yeepic library (not part of the ABI).
+#pragma once
+
+#include <cstdint>
+
+#include "yeepic.h"
+
+namespace yeepic {
+
+// Records a thread-local message for pic_last_error and returns ``code``.
+int set_error(int code, const char* fmt, ...);
+
+// Kernel widths: the coefficient count of each x1 operator rounded up to one
+// of the compiled stencil widths (zero padding is exact).
+constexpr int kWidths[5] = {1, 2, 4, 8, 16};
+int round_width(int m);
+
+// Mesh geometry passed to every kernel.
+struct Mesh {
+  int n1, n2, n3;
+  int ndim;
+  double dx1, dx2, dx3;
+  double L1, L2, L3;
+};
+
+// Field kernels (field_kernels.hip).  ``h`` is the time over which Faraday's
+// law is applied (dt/2 for a half step); coefficients are the raw C_j.
+template <typename T>
+struct FieldSet {
+  T* E[3];
+  T* B[3];
+};
+
+int launch_advance_b(int prec, const Mesh& m, void* const E[3], void* const B[3],
+                     const double* CE, int ME, double h, void* stream);
+int launch_advance_e(int prec, const Mesh& m, void* const E[3], void* const B[3],
+                     void* const J[3], const double* CB, int MB, double dt, void* stream);
+// Fused B-half / E / B-half sweep from (Ein, Bin) to (Eout, Bout); J may be
+// all-null.  In and out must not alias.
+int launch_sweep(int prec, const Mesh& m, void* const Ein[3], void* const Bin[3],
+                 void* const J[3], void* const Eout[3], void* const Bout[3],
+                 const double* CE, int ME, const double* CB, int MB, double dt, void* stream);
+
+// Particle kernels (particle_kernels.hip).
+int launch_gather_push(int prec, const Mesh& m, void* const E[3], void* const B[3],
+                       const pic_particles& p, int pusher, double dt, double* const x_old[3],
+                       void* stream);
+int launch_deposit(int prec, const Mesh& m, void* const J[3], const pic_particles& p,
+                   double* const x_old[3], double dt, void* stream);
+int launch_check(int prec, const Mesh& m, void* const E[3], void* const B[3],
+                 const pic_particles* p, int* d_flag, void* stream);
+
+}  // namespace yeepic

@@ -70,22 +70,30 @@ class PlaneWave:
         return self.a0 * np.cos(np.asarray(s, dtype=np.float64))
 
 
-def laser_fields(n, dx, pulse, x_head=0.0, w0=None, centre=None, dtype=np.float64):
-    """(E, B) at t = 0 on the (n3, n2, n1) mesh: E2 = B3 = -a'(x_head - x1)
-    (times exp(-r_perp^2/w0^2) if ``w0``), every other component zero."""
+def laser_profiles(n, dx, pulse, x_head=0.0, w0=None, centre=None):
+    """Factors of the t = 0 laser fields: E2 = e2[i] prof[k, j] and
+    B3 = b3[i] prof[k, j], with e2 = b3 = -a'(x_head - x1) sampled at the E2
+    (x1 = i dx1) and B3 (x1 = (i+1/2) dx1) locations and prof the transverse
+    Gaussian exp(-r_perp^2/w0^2) at (j+1/2, k) (ones without ``w0``)."""
     n1, n2, n3 = n
     i = np.arange(n1, dtype=np.float64)
-    s_e = x_head - i * dx[0]            # E2 at x1 = i dx1
-    s_b = x_head - (i + 0.5) * dx[0]    # B3 at x1 = (i+1/2) dx1
-    e2 = -pulse.da(s_e)
-    b3 = -pulse.da(s_b)
+    e2 = -pulse.da(x_head - i * dx[0])
+    b3 = -pulse.da(x_head - (i + 0.5) * dx[0])
     if w0 is None:
         prof = np.ones((n3, n2))
     else:
         c2, c3 = centre if centre is not None else (n2 * dx[1] / 2, n3 * dx[2] / 2)
-        y = (np.arange(n2) + 0.5) * dx[1] - c2   # E2, B3 both at j+1/2
-        z = np.arange(n3) * dx[2] - c3           # and at k
+        y = (np.arange(n2) + 0.5) * dx[1] - c2
+        z = np.arange(n3) * dx[2] - c3
         prof = np.exp(-(z[:, None] ** 2 + y[None, :] ** 2) / w0 ** 2)
+    return e2, b3, prof
+
+
+def laser_fields(n, dx, pulse, x_head=0.0, w0=None, centre=None, dtype=np.float64):
+    """(E, B) at t = 0 on the (n3, n2, n1) mesh: E2 = B3 = -a'(x_head - x1)
+    (times exp(-r_perp^2/w0^2) if ``w0``), every other component zero."""
+    n1, n2, n3 = n
+    e2, b3, prof = laser_profiles(n, dx, pulse, x_head, w0, centre)
     E = [np.zeros((n3, n2, n1), dtype=dtype) for _ in range(3)]
     B = [np.zeros((n3, n2, n1), dtype=dtype) for _ in range(3)]
     E[1][...] = (prof[:, :, None] * e2[None, None, :]).astype(dtype)

@@ -1,0 +1,29 @@
+"""Helpers shared by the GPU parity tests (device transfers, error norms)."""
+import numpy as np
+import torch
+
+DEV = "cuda:0"
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype).contiguous()
+
+
+def host(t):
+    return t.detach().to("cpu", torch.float64).numpy()
+
+
+def fields_dev(E, B, dtype=torch.float64):
+    return [dev(e, dtype) for e in E], [dev(x, dtype) for x in B]
+
+
+def normwise(got, ref):
+    """max|got - ref| / max|ref| (one field component)."""
+    scale = np.max(np.abs(ref))
+    return float(np.max(np.abs(got - ref)) / (scale if scale > 0 else 1.0))
+
+
+def assert_fields_close(got, ref, tol, what=""):
+    for c, (g, r) in enumerate(zip(got, ref)):
+        err = normwise(host(g) if isinstance(g, torch.Tensor) else g, r)
+        assert err <= tol, f"{what} component {c + 1}: norm-wise error {err:.3e} > {tol:.1e}"

@@ -1,0 +1,120 @@
+"""GPU parity of gather + push + position update and of the deposit against
+the FP64 oracle (through the C ABI).  Particle arithmetic is FP64 on both
+sides, also when the fields are stored in FP32 (the oracle then sees the same
+rounded field values), so every tolerance is the FP64 one."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import particles as pt  # noqa: E402
+from paper_2004_03754_amd import binding as b, workloads as wl  # noqa: E402
+
+torch = pytest.importorskip("torch")
+from gpu_util import assert_fields_close, dev, host  # noqa: E402
+
+DX = (wl.DX1, wl.DX2, wl.DX3)
+
+
+def _box(n):
+    return [n[d] * DX[d] for d in range(3)]
+
+
+def _particles(n, npart, seed, u_scale):
+    L = _box(n)
+    x, u = wl.uniform_particles(npart, [0, 0, 0], L, seed=seed, u_th=u_scale)
+    # edge positions: on nodes, on the seam, just below the box end
+    x[0, 0] = 0.0
+    x[0, 1] = L[0] - 1e-12
+    x[1, 2] = 0.5 * DX[1]
+    x[2, 3] = L[2] - 1e-13
+    x[:, 4] = 0.0
+    return x, u
+
+
+def _rel_err(got, ref):
+    return float(np.max(np.abs(got - ref) / np.maximum(1.0, np.abs(ref))))
+
+
+def _pos_err(got, ref, L):
+    d = got - ref
+    Lb = np.asarray(L)[: d.shape[0], None]
+    d = (d + Lb / 2) % Lb - Lb / 2
+    return float(np.max(np.abs(d) / Lb))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("pusher", ["boris", "analytic"])
+@pytest.mark.parametrize("ndim", [3, 2])
+@pytest.mark.parametrize("field_scale", [1.0, 50.0])
+def test_gather_push(ndim, pusher, prec, field_scale, coeffs16):
+    """App. A gather + Sec. 1/4.1 pushers + second-order position update."""
+    n = (128, 6, 5) if ndim == 3 else (128, 6, 1)
+    E, B = wl.random_fields(n, seed=40, scale=field_scale)
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    if prec == "fp32":
+        E = [e.astype(np.float32).astype(np.float64) for e in E]
+        B = [x.astype(np.float32).astype(np.float64) for x in B]
+    x, u = _particles(n, 3000, seed=41, u_scale=3.0)
+    if ndim == 2:
+        x[2] = 0.0
+    CE, CB = coeffs16
+    grid = b.Grid([dev(e, dtype) for e in E], [dev(v, dtype) for v in B], DX if ndim == 3 else DX[:2],
+                  wl.DT, CE, CB, prec=prec, ndim=ndim)
+    xd, ud = dev(x), dev(u)
+    xo = torch.zeros_like(xd)
+    p = b.Particles(xd, ud, q=-1.0, m=1.0, w=1.0)
+    grid.gather_push(p, pusher, x_old=xo)
+    grid.sync()
+    Ep, Bp = pt.gather(E, B, x, DX, ndim)
+    push = pt.boris if pusher == "boris" else pt.analytic
+    un = push(u, Ep, Bp, -1.0, wl.DT)
+    L = _box(n)[:ndim]
+    xn, _ = pt.advance_position(x, un, wl.DT, L, ndim)
+    assert _rel_err(host(ud), un) <= 1e-12
+    assert _pos_err(host(xd)[:ndim], xn, L) <= 1e-13
+    assert np.array_equal(host(xo)[:ndim], x[:ndim])
+    grid.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("ndim", [3, 2])
+def test_deposit(ndim, prec, coeffs16):
+    """Sec. 3.3 Esirkepov current of random sub-cell moves (crossing cells
+    and the periodic seam) against the oracle's deposit."""
+    n = (128, 6, 5) if ndim == 3 else (128, 6, 1)
+    L = _box(n)
+    x0, u = _particles(n, 4000, seed=50, u_scale=0.5)
+    x1, _ = wl.small_moves(x0, DX, L, seed=51)
+    x1[0, 0] = L[0] - 0.05  # backwards across the periodic seam
+    x1[0, 1] = 0.05         # forwards across it
+    if ndim == 2:
+        x0[2] = 0.0
+        x1[2] = 0.0
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    CE, CB = coeffs16
+    zeros = [np.zeros((n[2], n[1], n[0])) for _ in range(3)]
+    Jd = [dev(z, dtype) for z in zeros]
+    grid = b.Grid([dev(z, dtype) for z in zeros], [dev(z, dtype) for z in zeros], DX if ndim == 3 else DX[:2],
+                  wl.DT, CE, CB, J=Jd, prec=prec, ndim=ndim)
+    p = b.Particles(dev(x1), dev(u), q=-1.0, m=1.0, w=0.37)
+    grid.deposit_J(p, dev(x0), zero_first=True)
+    grid.sync()
+    ref = pt.deposit(x0, x1, -1.0, 0.37, DX, wl.DT, (n[2], n[1], n[0]), ndim, u=u)
+    assert_fields_close(Jd, ref, 1e-12 if prec == "fp64" else 2e-6, "deposit J")
+    grid.close()
+
+
+def test_deposit_rejects_wide_ampere(coeffs16):
+    """The x1 current correction is the identity only for the Yee Ampere
+    stencil; other C^B are refused instead of breaking Gauss's law."""
+    CE, CB = coeffs16
+    n = (128, 4, 4)
+    zeros = [np.zeros((n[2], n[1], n[0])) for _ in range(3)]
+    grid = b.Grid([dev(z) for z in zeros], [dev(z) for z in zeros], DX, wl.DT, CE, CB + np.r_[0, 0.01, np.zeros(14)],
+                  J=[dev(z) for z in zeros])
+    x0, u = _particles(n, 10, seed=3, u_scale=0.1)
+    with pytest.raises(b.YeePICError) as e:
+        grid.deposit_J(b.Particles(dev(x0), dev(u)), dev(x0))
+    assert e.value.code == -6
+    grid.close()

@@ -1,0 +1,129 @@
+"""GPU parity of the whole step loop (pic_step_n) against the oracle's step,
+plus the config-1 physics check against the closed-form trajectory."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import pic, trajectory as tj  # noqa: E402
+from paper_2004_03754_amd import binding as b, workloads as wl  # noqa: E402
+
+torch = pytest.importorskip("torch")
+from gpu_util import assert_fields_close, dev, host  # noqa: E402
+
+DX = (wl.DX1, wl.DX2, wl.DX3)
+
+
+@pytest.mark.parametrize("pusher", ["boris", "analytic"])
+@pytest.mark.parametrize("nsteps", [1, 4])
+def test_step_n_plasma_fp64(pusher, nsteps, coeffs16):
+    """Config-3 physics at a small size: laser + thermal plasma, push,
+    Esirkepov deposit and fused sweep per step (Sec. 3.3 ordering)."""
+    CE, CB = coeffs16
+    n = (128, 8, 6)
+    L = [n[d] * DX[d] for d in range(3)]
+    pulse = wl.Sin2Pulse(a0=2.0, Lp=4 * wl.LAMBDA0, period=L[0])
+    E, B = wl.laser_fields(n, DX, pulse, x_head=3 * wl.LAMBDA0, w0=2 * wl.LAMBDA0)
+    x, u = wl.lattice_particles(n, DX, 1, seed=3, u_th=0.05)
+    w = 0.01
+    grid = b.Grid([dev(e) for e in E], [dev(v) for v in B], DX, wl.DT, CE, CB,
+                  J=[dev(np.zeros_like(e)) for e in E])
+    xd, ud = dev(x), dev(u)
+    p = b.Particles(xd, ud, q=-1.0, m=1.0, w=w)
+    grid.step_n([p], nsteps, pusher=pusher, deposit=True)
+    grid.sync()
+    sp = {"x": x.copy(), "u": u.copy(), "q": -1.0, "m": 1.0, "w": w}
+    Er, Br = pic.run(E, B, [sp], CE, CB, DX, wl.DT, nsteps, pusher=pusher, deposit=True)
+    assert_fields_close(grid.E, Er, 1e-11, "step_n E")
+    assert_fields_close(grid.B, Br, 1e-11, "step_n B")
+    assert np.max(np.abs(host(ud) - sp["u"]) / np.maximum(1, np.abs(sp["u"]))) < 1e-11
+    d = host(xd) - sp["x"]
+    Lb = np.asarray(L)[:, None]
+    assert np.max(np.abs((d + Lb / 2) % Lb - Lb / 2)) < 1e-11
+    grid.close()
+
+
+def _config1(solver, pusher, coeffs16, steps):
+    n = (512, 4, 1)
+    L1 = n[0] * DX[0]
+    pulse = wl.Sin2Pulse(a0=1.0, Lp=10 * wl.LAMBDA0, period=L1)
+    xh = 4 * wl.LAMBDA0
+    E, B = wl.laser_fields(n, DX, pulse, x_head=xh)
+    CE, CB = coeffs16 if solver == "custom" else (np.array([1.0]), np.array([1.0]))
+    x = np.array([[4.25 * wl.LAMBDA0], [2 * DX[1]], [0.0]])
+    return n, pulse, xh, E, B, CE, CB, x
+
+
+@pytest.mark.parametrize("solver,pusher", [("custom", "analytic"), ("yee", "boris")])
+def test_config1_parity_and_closed_form(solver, pusher, coeffs16):
+    """Config 1 (2D plane-wave pulse, one electron from rest): 1000 GPU steps
+    match the oracle's 1000 steps, and the proposed solver + exact pusher
+    tracks the closed form (Sec. 4.1) within the linear-gather bound."""
+    steps = 1000
+    n, pulse, xh, E, B, CE, CB, x = _config1(solver, pusher, coeffs16, steps)
+    grid = b.Grid([dev(e) for e in E], [dev(v) for v in B], DX[:2], wl.DT, CE, CB, ndim=2)
+    xd, ud = dev(x), dev(np.zeros((3, 1)))
+    p = b.Particles(xd, ud)
+    gam = []
+    for _ in range(steps):
+        grid.step_n([p], 1, pusher=pusher)
+        gam.append(ud[:, 0].clone())
+    grid.sync()
+    g_gpu = np.sqrt(1 + np.sum(host(torch.stack(gam)) ** 2, axis=1))
+    sp = {"x": x.copy(), "u": np.zeros((3, 1)), "q": -1.0, "m": 1.0, "w": 0.0}
+    g_ref = []
+    Er, Br = E, B
+    for _ in range(steps):
+        Er, Br = pic.step(Er, Br, [sp], CE, CB, DX, wl.DT, pusher=pusher, ndim=2)
+        g_ref.append(np.sqrt(1 + sp["u"][:, 0] @ sp["u"][:, 0]))
+    g_ref = np.array(g_ref)
+    assert np.max(np.abs(g_gpu - g_ref)) < 1e-10
+    assert_fields_close(grid.E, Er, 1e-11, "config1 E")
+    if solver == "custom":
+        a = lambda psi: pulse.a(psi + xh)
+        ts = (np.arange(steps) + 0.5) * wl.DT
+        gcf = np.array([tj.state_at(a, -1.0, -0.5 * wl.DT, x, t)[2][0] for t in ts[::10]])
+        assert np.max(np.abs(g_gpu[::10] - gcf)) / np.max(gcf - 1) < 3e-2
+    grid.close()
+
+
+def test_step_n_odd_and_even_counts_agree(coeffs16):
+    """The fused sweep ping-pongs between the caller's arrays and the grid's
+    second set; odd and even step counts must leave the same state in the
+    caller's tensors as single steps."""
+    CE, CB = coeffs16
+    n = (128, 4, 4)
+    E, B = wl.random_fields(n, seed=12)
+    g1 = b.Grid([dev(e) for e in E], [dev(v) for v in B], DX, wl.DT, CE, CB)
+    g2 = b.Grid([dev(e) for e in E], [dev(v) for v in B], DX, wl.DT, CE, CB)
+    g1.step_n([], 5)
+    for _ in range(5):
+        g2.step_n([], 1)
+    g1.sync()
+    g2.sync()
+    for a, c in zip(g1.E + g1.B, g2.E + g2.B):
+        assert torch.equal(a, c)
+    g1.close()
+    g2.close()
+
+
+def test_check_reports_nonfinite_and_out_of_box(coeffs16):
+    """pic_check flags a NaN planted in a field and a particle outside the
+    box (both set from the host; kernels stay in bounds)."""
+    CE, CB = coeffs16
+    n = (128, 4, 4)
+    E, B = wl.random_fields(n, seed=13)
+    Ed = [dev(e) for e in E]
+    grid = b.Grid(Ed, [dev(v) for v in B], DX, wl.DT, CE, CB)
+    x, u = wl.uniform_particles(16, [0, 0, 0], [n[d] * DX[d] for d in range(3)], seed=1)
+    p = b.Particles(dev(x), dev(u))
+    grid.check(p)
+    p.x[0, 3] = -1.0
+    with pytest.raises(b.YeePICError) as e:
+        grid.check(p)
+    assert e.value.code == -7
+    p.x[0, 3] = 0.5
+    Ed[1][1, 2, 3] = float("nan")
+    with pytest.raises(b.YeePICError):
+        grid.check()
+    grid.close()
