@@ -7,6 +7,8 @@
 // Arrays are [n3][n2][n1], x1 contiguous, periodic in every direction.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "yeepic_internal.h"
 
 namespace yeepic {
@@ -171,10 +173,24 @@ int dispatch_e(const Mesh& m, void* const E[3], void* const B[3], void* const J[
 // ---------------------------------------------------------------------------
 template <typename T, int ME, int MB, int TX, int TY>
 struct SweepGeom {
-  static constexpr int HLE = 2 * ME + MB - 2, PXE = TX + 4 * ME + 2 * MB - 3, PYE = TY + 3;
-  static constexpr int HLB = ME + MB - 1, PXB = TX + 2 * ME + 2 * MB - 2, PYB = TY + 2;
-  static constexpr int HLF = ME - 1, PXF = TX + 2 * ME - 1, PYF = TY + 1;
+  // R consecutive x1 outputs per thread in the wide stages, read as 16-byte
+  // LDS vectors; NC vectors cover one R-output window of the 2ME-tap stencil
+  static constexpr int R = 16 / (int)sizeof(T);
+  static constexpr int NC = (R + 2 * ME - 1 + R - 1) / R;
+  static constexpr int rup(int v) { return (v + R - 1) / R * R; }
+  static constexpr int mx(int a, int b) { return a > b ? a : b; }
+  // left halos: HLE is a multiple of R (16-byte aligned global rows) and
+  // HLB = HLE - ME + 1, so every stage-1 window starts on a vector boundary
+  static constexpr int HLB = rup(ME + MB - 1 + ME - 1) - (ME - 1);
+  static constexpr int HLE = HLB + ME - 1;
+  static constexpr int HLF = ME - 1;
+  static constexpr int PYE = TY + 3, PYB = TY + 2, PYF = TY + 1;
+  static constexpr int PXB = rup(HLB + TX + ME + MB - 1);
+  static constexpr int PXE = rup(mx(PXB - R + R * NC, HLE + TX + 2 * ME + MB - 1));
+  static constexpr int PXF = rup(mx(TX - R + R * NC, TX + 2 * ME - 1));
   static constexpr int SE = PXE * PYE, SB = PXB * PYB, SF = PXF * PYF;  // one component, one plane
+  static constexpr int GB = PXB / R, G3 = TX / R;                         // vector groups per row
+  static constexpr int VE = PXE / R;                                      // vectors per E row
   static constexpr size_t lds_bytes = sizeof(T) * 2 * 3 * (size_t)(SE + SB + SF);
 };
 
@@ -187,7 +203,65 @@ struct SweepCoef {
   T dt;
 };
 
-template <typename T, int ME, int MB, int TX, int TY, int NT>
+// 16-byte native vectors (clang ext_vector_type keeps arrays of them in
+// registers, unlike the struct-based HIP vector types)
+typedef double v2f64 __attribute__((ext_vector_type(2)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Vec16 {
+  using type = typename std::conditional<sizeof(T) == 8, v2f64, v4f32>::type;
+};
+
+// load NC 16-byte vectors starting at an aligned LDS index
+template <typename T, int NC, int R>
+__device__ __forceinline__ void load_window(const T* __restrict__ src, T (&w)[NC * R]) {
+  using V = typename Vec16<T>::type;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const V v = *reinterpret_cast<const V*>(src + c * R);
+#pragma unroll
+    for (int e = 0; e < R; ++e) w[c * R + e] = v[e];
+  }
+}
+
+// R consecutive values starting OFF elements after an aligned LDS index,
+// read as one or two aligned 16-byte vectors (lanes then touch consecutive
+// 16-byte words: no bank conflicts)
+template <typename T, int R, int OFF>
+__device__ __forceinline__ void load_run(const T* __restrict__ aligned, T (&out)[R]) {
+  using V = typename Vec16<T>::type;
+  constexpr int q0 = OFF / R, rem = OFF % R;
+  const V v0 = *reinterpret_cast<const V*>(aligned + q0 * R);
+  if constexpr (rem == 0) {
+#pragma unroll
+    for (int e = 0; e < R; ++e) out[e] = v0[e];
+  } else {
+    const V v1 = *reinterpret_cast<const V*>(aligned + (q0 + 1) * R);
+#pragma unroll
+    for (int e = 0; e < R; ++e) out[e] = (e + rem < R) ? v0[e + rem] : v1[e + rem - R];
+  }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void store_vec(T* __restrict__ aligned, const T (&in)[R]) {
+  using V = typename Vec16<T>::type;
+  V v;
+#pragma unroll
+  for (int e = 0; e < R; ++e) v[e] = in[e];
+  *reinterpret_cast<V*>(aligned) = v;
+}
+
+// Faraday-form tap sum for output u of a window whose index 0 is the
+// output block start: sum_q a_q (w[u+ME-1+q] - w[u+ME-q])
+template <typename T, int ME, int NW>
+__device__ __forceinline__ T faraday_taps(const T (&w)[NW], const T (&a)[ME], int u) {
+  T acc = 0;
+#pragma unroll
+  for (int q = 1; q <= ME; ++q) acc += a[q - 1] * (w[u + ME - 1 + q] - w[u + ME - q]);
+  return acc;
+}
+
+template <typename T, int ME, int MB, int TX, int TY, int NT, bool HAS_J>
 __global__ __launch_bounds__(NT) void sweep_kernel(const T* __restrict__ iE1, const T* __restrict__ iE2,
                                                    const T* __restrict__ iE3, const T* __restrict__ iB1,
                                                    const T* __restrict__ iB2, const T* __restrict__ iB3,
@@ -195,28 +269,33 @@ __global__ __launch_bounds__(NT) void sweep_kernel(const T* __restrict__ iE1, co
                                                    const T* __restrict__ J3, T* __restrict__ oE1,
                                                    T* __restrict__ oE2, T* __restrict__ oE3, T* __restrict__ oB1,
                                                    T* __restrict__ oB2, T* __restrict__ oB3, Mesh m, int KZ,
-                                                   int tiles_x, SweepCoef<T, ME, MB> c) {
+                                                   int tiles_x, int tiles, SweepCoef<T, ME, MB> c) {
   using G = SweepGeom<T, ME, MB, TX, TY>;
+  constexpr int R = G::R, NC = G::NC;
+  // per-thread work slots of each phase (fixed for the whole march)
+  constexpr int NLE = (3 * G::PYE * G::VE + NT - 1) / NT;
+  constexpr int NG1 = G::PYB * G::GB;
+  constexpr int NS1 = (NG1 + NT - 1) / NT;
+  constexpr int NS2 = (G::SF + NT - 1) / NT;
+  constexpr int NG3 = TY * G::G3;
+  constexpr int NS3 = (NG3 + NT - 1) / NT;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* lds = reinterpret_cast<T*>(lds_raw);
-  // [buffer][component] planes
-  T* sE = lds;                       // 2 x 3 x SE
-  T* sB = sE + 2 * 3 * G::SE;        // 2 x 3 x SB
-  T* sF = sB + 2 * 3 * G::SB;        // 2 x 3 x SF
-  auto pE = [&](int plane, int comp) { return sE + ((plane & 1) * 3 + comp) * G::SE; };
-  auto pB = [&](int plane, int comp) { return sB + ((plane & 1) * 3 + comp) * G::SB; };
-  auto pF = [&](int plane, int comp) { return sF + ((plane & 1) * 3 + comp) * G::SF; };
+  T* sE = lds;                 // [plane parity][component] x SE
+  T* sB = sE + 2 * 3 * G::SE;  // [plane parity][component] x SB
+  T* sF = sB + 2 * 3 * G::SB;  // [plane parity][component] x SF
 
   const int tid = threadIdx.x;
-  const int tile = blockIdx.x;
+  // XCD-aware tile order: consecutive workgroup ids go round-robin to the 8
+  // XCDs, so give each XCD a contiguous block of tiles (halo reuse in its L2)
+  int tile = blockIdx.x;
+  if (tiles % 8 == 0) tile = (tile % 8) * (tiles / 8) + tile / 8;
   const int i0 = (tile % tiles_x) * TX;
   const int j0 = (tile / tiles_x) * TY;
   const int k0 = blockIdx.y * KZ;
   const int kend = min(k0 + KZ, m.n3);
   const size_t plane_sz = (size_t)m.n1 * m.n2;
-  const T* inE[3] = {iE1, iE2, iE3};
-
-  auto gi = [&](int rel) {  // tile-relative x1 -> global, periodic
+  auto gi = [&](int rel) {
     int i = (i0 + rel) % m.n1;
     return i < 0 ? i + m.n1 : i;
   };
@@ -224,79 +303,206 @@ __global__ __launch_bounds__(NT) void sweep_kernel(const T* __restrict__ iE1, co
     int j = (j0 + rel) % m.n2;
     return j < 0 ? j + m.n2 : j;
   };
-  auto gk = [&](int k) {
+  auto poff = [&](int k) {
     k %= m.n3;
-    return k < 0 ? k + m.n3 : k;
+    return (size_t)(k < 0 ? k + m.n3 : k) * plane_sz;
   };
 
-  auto load_E = [&](int plane) {
-    const size_t base = (size_t)gk(plane) * plane_sz;
-    for (int p = tid; p < 3 * G::SE; p += NT) {
-      const int comp = p / G::SE;
-      const int q = p - comp * G::SE;
-      const int r = q / G::PXE;
-      const int x = q - r * G::PXE;
-      pE(plane, comp)[q] = inE[comp][base + (size_t)gj(r - 1) * m.n1 + gi(x - G::HLE)];
+  // ---- slot tables (all modulo arithmetic happens here, once) ----
+  using V = typename Vec16<T>::type;
+  constexpr int NVE = 3 * G::PYE * G::VE;  // 16-byte vectors per E^n plane
+  // slot s of this thread: component le_c[s] (-1: idle), vector offset
+  // le_g[s] in the component's plane, LDS element index le_d[s]
+  int le_c[NLE], le_g[NLE], le_d[NLE];
+#pragma unroll
+  for (int s = 0; s < NLE; ++s) {
+    const int p = tid + s * NT;
+    const int comp = p / (G::PYE * G::VE);
+    const int q = p - comp * (G::PYE * G::VE);
+    const int r = q / G::VE;
+    const int x = (q - r * G::VE) * R;
+    le_c[s] = p < NVE ? comp : -1;
+    le_d[s] = comp * G::SE + r * G::PXE + x;
+    le_g[s] = p < NVE ? (gj(r - 1) * m.n1 + gi(x - G::HLE)) / R : 0;
+  }
+  const V* vE1 = reinterpret_cast<const V*>(iE1);
+  const V* vE2 = reinterpret_cast<const V*>(iE2);
+  const V* vE3 = reinterpret_cast<const V*>(iE3);
+  // stage 1: R-output groups over the B extent
+  int s1_w[NS1], s1_b[NS1], s1_row[NS1], s1_col[NS1];
+#pragma unroll
+  for (int s = 0; s < NS1; ++s) {
+    const int g = tid + s * NT;
+    const int r = g / G::GB, x = (g - r * G::GB) * R;
+    s1_w[s] = r * G::PXE + x;  // window start (aligned)
+    s1_b[s] = r * G::PXB + x;
+    s1_row[s] = g < NG1 ? gj(r - 1) * m.n1 : 0;
+    s1_col[s] = g < NG1 ? gi(x - G::HLB) : 0;
+  }
+  int s2_cb[NS2], s2_ce[NS2], s2_g[NS2];
+  bool s2_out[NS2];
+#pragma unroll
+  for (int s = 0; s < NS2; ++s) {
+    const int p = tid + s * NT;
+    const int r = p / G::PXF, x = p - (p / G::PXF) * G::PXF;
+    s2_cb[s] = (r + 1) * G::PXB + x + (G::HLB - G::HLF);
+    s2_ce[s] = (r + 1) * G::PXE + x + (G::HLE - G::HLF);
+    s2_g[s] = p < G::SF ? gj(r) * m.n1 + gi(x - G::HLF) : 0;
+    const int xr = x - G::HLF;
+    s2_out[s] = p < G::SF && xr >= 0 && xr < TX && r < TY && i0 + xr < m.n1 && j0 + r < m.n2;
+  }
+  // stage 3: R-output groups over the output tile
+  int s3_w[NS3], s3_b[NS3], s3_g[NS3], s3_n[NS3];
+#pragma unroll
+  for (int s = 0; s < NS3; ++s) {
+    const int g = tid + s * NT;
+    const int r = g / G::G3, x = (g - r * G::G3) * R;
+    s3_w[s] = r * G::PXF + x;
+    s3_b[s] = (r + 1) * G::PXB + x;  // aligned; the B position is HLB further
+    const bool rowok = g < NG3 && j0 + r < m.n2;
+    const int nx = m.n1 - (i0 + x);
+    s3_n[s] = rowok ? (nx < 0 ? 0 : (nx > R ? R : nx)) : 0;  // valid outputs in the group
+    s3_g[s] = s3_n[s] > 0 ? (j0 + r) * m.n1 + (i0 + x) : 0;
+  }
+
+  // ---- prologue: E^n planes k0-1, k0 into LDS; B^n and J of plane k0-1 ----
+#define YP_LOAD_PLANE(k)                                                        \
+  {                                                                             \
+    const size_t voff = poff(k) / R; /* plane offsets are multiples of R */     \
+    _Pragma("unroll") for (int s = 0; s < NLE; ++s) {                           \
+      const V* src = le_c[s] == 0 ? vE1 : (le_c[s] == 1 ? vE2 : vE3);           \
+      if (le_c[s] >= 0) pfE[s] = src[voff + le_g[s]];                           \
+    }                                                                           \
+  }
+#define YP_STORE_PLANE(k)                                                       \
+  {                                                                             \
+    T* dst = sE + ((k) & 1) * 3 * G::SE;                                        \
+    _Pragma("unroll") for (int s = 0; s < NLE; ++s) if (le_c[s] >= 0)           \
+        *reinterpret_cast<V*>(dst + le_d[s]) = pfE[s];                          \
+  }
+  V pfE[NLE];
+  YP_LOAD_PLANE(k0 - 1);
+  YP_STORE_PLANE(k0 - 1);
+  YP_LOAD_PLANE(k0);
+  YP_STORE_PLANE(k0);
+  T curB[NS1][R][3], nxtB[NS1][R][3];
+  constexpr int NJ = HAS_J ? NS2 : 1;  // current prefetch only when there is a current
+  T curJ[NJ][3], nxtJ[NJ][3];
+  auto load_B = [&](int k, T (&dst)[NS1][R][3]) {
+    const size_t off = poff(k);
+#pragma unroll
+    for (int s = 0; s < NS1; ++s)
+      if (tid + s * NT < NG1) {
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          int col = s1_col[s] + u;
+          col -= col >= m.n1 ? m.n1 : 0;
+          const size_t g = off + s1_row[s] + col;
+          dst[s][u][0] = iB1[g];
+          dst[s][u][1] = iB2[g];
+          dst[s][u][2] = iB3[g];
+        }
+      }
+  };
+  auto load_J = [&](int k, T (&dst)[NJ][3]) {
+    const size_t off = poff(k);
+#pragma unroll
+    for (int s = 0; s < NJ; ++s) {
+      dst[s][0] = dst[s][1] = dst[s][2] = 0;
+      if (HAS_J && tid + s * NT < G::SF) {
+        dst[s][0] = J1[off + s2_g[s]];
+        dst[s][1] = J2[off + s2_g[s]];
+        dst[s][2] = J3[off + s2_g[s]];
+      }
     }
   };
-
-  load_E(k0 - 1);
-  load_E(k0);
+  load_B(k0 - 1, curB);
+  load_J(k0 - 1, curJ);
   __syncthreads();
 
   for (int kk = k0 - 2; kk < kend; ++kk) {
     const int ka = kk + 1;  // plane of stages 1 and 2
-    // ---- stage 1: B^{n+1/2}(ka) over the B buffer extent ----
+    const bool more = kk + 1 < kend;
+    // prefetch for the next plane: E^n(kk+3) -> LDS at the end of this
+    // iteration; B^n, J of plane ka+1 for the next stages 1 and 2
+    if (more) {
+      YP_LOAD_PLANE(kk + 3);
+      load_B(ka + 1, nxtB);
+      load_J(ka + 1, nxtJ);
+    }
+    // ---- stage 1: B^{n+1/2}(ka) ----
     {
-      const T* e1 = pE(ka, 0);
-      const T* e2 = pE(ka, 1);
-      const T* e3 = pE(ka, 2);
-      const T* n1 = pE(ka + 1, 0);
-      const T* n2 = pE(ka + 1, 1);
-      T* b1 = pB(ka, 0);
-      T* b2 = pB(ka, 1);
-      T* b3 = pB(ka, 2);
-      const size_t base = (size_t)gk(ka) * plane_sz;
-      for (int p = tid; p < G::SB; p += NT) {
-        const int r = p / G::PXB;
-        const int x = p - r * G::PXB;
-        const int xe = x + (G::HLE - G::HLB);
-        const int ce = r * G::PXE + xe;  // E row r <-> B row r (both start at j-1)
-        T dE3 = 0, dE2 = 0;
+      const T* e1 = sE + (ka & 1) * 3 * G::SE;
+      const T* e2 = e1 + G::SE;
+      const T* e3 = e2 + G::SE;
+      const T* n1 = sE + ((ka + 1) & 1) * 3 * G::SE;
+      const T* n2 = n1 + G::SE;
+      T* b1 = sB + (ka & 1) * 3 * G::SB;
+      T* b2 = b1 + G::SB;
+      T* b3 = b2 + G::SB;
 #pragma unroll
-        for (int q = 1; q <= ME; ++q) {
-          dE3 += c.ae[q - 1] * (e3[ce + q] - e3[ce - q + 1]);
-          dE2 += c.ae[q - 1] * (e2[ce + q] - e2[ce - q + 1]);
+      for (int s = 0; s < NS1; ++s) {
+        if (tid + s * NT >= NG1) continue;
+        // one component's window at a time keeps register pressure down
+        T dE2[R], dE3[R], e2w[R], e3w[R];
+        {
+          T w[NC * R];
+          load_window<T, NC, R>(e2 + s1_w[s], w);
+#pragma unroll
+          for (int u = 0; u < R; ++u) {
+            dE2[u] = faraday_taps<T, ME>(w, c.ae, u);
+            e2w[u] = w[u + ME - 1];
+          }
         }
-        const size_t g = base + (size_t)gj(r - 1) * m.n1 + gi(x - G::HLB);
-        const T e1c = e1[ce], e2c = e2[ce], e3c = e3[ce];
-        b1[p] = iB1[g] - (c.hy * (e3[ce + G::PXE] - e3c) - c.hz * (n2[ce] - e2c));
-        b2[p] = iB2[g] - (c.hz * (n1[ce] - e1c) - dE3);
-        b3[p] = iB3[g] - (dE2 - c.hy * (e1[ce + G::PXE] - e1c));
+        {
+          T w[NC * R];
+          load_window<T, NC, R>(e3 + s1_w[s], w);
+#pragma unroll
+          for (int u = 0; u < R; ++u) {
+            dE3[u] = faraday_taps<T, ME>(w, c.ae, u);
+            e3w[u] = w[u + ME - 1];
+          }
+        }
+        // the B positions' own E values (index window start + ME - 1)
+        T e1c[R], e1n[R], e3n[R], n1c[R], n2c[R];
+        load_run<T, R, ME - 1>(e1 + s1_w[s], e1c);
+        load_run<T, R, ME - 1>(e1 + s1_w[s] + G::PXE, e1n);
+        load_run<T, R, ME - 1>(e3 + s1_w[s] + G::PXE, e3n);
+        load_run<T, R, ME - 1>(n1 + s1_w[s], n1c);
+        load_run<T, R, ME - 1>(n2 + s1_w[s], n2c);
+        T o1[R], o2[R], o3[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          o1[u] = curB[s][u][0] - (c.hy * (e3n[u] - e3w[u]) - c.hz * (n2c[u] - e2w[u]));
+          o2[u] = curB[s][u][1] - (c.hz * (n1c[u] - e1c[u]) - dE3[u]);
+          o3[u] = curB[s][u][2] - (dE2[u] - c.hy * (e1n[u] - e1c[u]));
+        }
+        store_vec<T, R>(b1 + s1_b[s], o1);
+        store_vec<T, R>(b2 + s1_b[s], o2);
+        store_vec<T, R>(b3 + s1_b[s], o3);
       }
     }
     __syncthreads();
-    // ---- stage 2: E^{n+1}(ka) over the F buffer extent ----
+    // ---- stage 2: E^{n+1}(ka) ----
     {
-      const T* b1 = pB(ka, 0);
-      const T* b2 = pB(ka, 1);
-      const T* b3 = pB(ka, 2);
-      const T* p1 = pB(ka - 1, 0);
-      const T* p2 = pB(ka - 1, 1);
-      const T* e1 = pE(ka, 0);
-      const T* e2 = pE(ka, 1);
-      const T* e3 = pE(ka, 2);
-      T* f1 = pF(ka, 0);
-      T* f2 = pF(ka, 1);
-      T* f3 = pF(ka, 2);
+      const T* b1 = sB + (ka & 1) * 3 * G::SB;
+      const T* b2 = b1 + G::SB;
+      const T* b3 = b2 + G::SB;
+      const T* p1 = sB + ((ka - 1) & 1) * 3 * G::SB;
+      const T* p2 = p1 + G::SB;
+      const T* e1 = sE + (ka & 1) * 3 * G::SE;
+      const T* e2 = e1 + G::SE;
+      const T* e3 = e2 + G::SE;
+      T* f1 = sF + (ka & 1) * 3 * G::SF;
+      T* f2 = f1 + G::SF;
+      T* f3 = f2 + G::SF;
       const bool out_plane = ka >= k0 && ka < kend;
-      const int kg = gk(ka);
-      const size_t base = (size_t)kg * plane_sz;
-      for (int p = tid; p < G::SF; p += NT) {
-        const int r = p / G::PXF;
-        const int x = p - r * G::PXF;
-        const int cb = (r + 1) * G::PXB + x + MB;             // B row of j is r+1
-        const int ce = (r + 1) * G::PXE + x + (ME + MB - 1);  // E row of j is r+1
+      const size_t off = poff(ka);
+#pragma unroll
+      for (int s = 0; s < NS2; ++s) {
+        const int p = tid + s * NT;
+        if (p >= G::SF) continue;
+        const int cb = s2_cb[s], ce = s2_ce[s];
         T dB3 = 0, dB2 = 0;
 #pragma unroll
         for (int q = 1; q <= MB; ++q) {
@@ -307,19 +513,17 @@ __global__ __launch_bounds__(NT) void sweep_kernel(const T* __restrict__ iE1, co
         T c1 = c.ty * (b3c - b3[cb - G::PXB]) - c.tz * (b2c - p2[cb]);
         T c2 = c.tz * (b1c - p1[cb]) - dB3;
         T c3 = dB2 - c.ty * (b1c - b1[cb - G::PXB]);
-        const int ig = gi(x - G::HLF), jg = gj(r);
-        const size_t g = base + (size_t)jg * m.n1 + ig;
-        if (J1) {
-          c1 -= c.dt * J1[g];
-          c2 -= c.dt * J2[g];
-          c3 -= c.dt * J3[g];
+        if constexpr (HAS_J) {
+          c1 -= c.dt * curJ[s][0];
+          c2 -= c.dt * curJ[s][1];
+          c3 -= c.dt * curJ[s][2];
         }
         const T v1 = e1[ce] + c1, v2 = e2[ce] + c2, v3 = e3[ce] + c3;
         f1[p] = v1;
         f2[p] = v2;
         f3[p] = v3;
-        const int xr = x - G::HLF;
-        if (out_plane && xr >= 0 && xr < TX && r < TY && i0 + xr < m.n1 && j0 + r < m.n2) {
+        if (out_plane && s2_out[s]) {
+          const size_t g = off + s2_g[s];
           oE1[g] = v1;
           oE2[g] = v2;
           oE3[g] = v3;
@@ -327,39 +531,88 @@ __global__ __launch_bounds__(NT) void sweep_kernel(const T* __restrict__ iE1, co
       }
     }
     __syncthreads();
-    // ---- stage 3: B^{n+1}(kk) on the output tile; refill E^n ----
+    // ---- stage 3: B^{n+1}(kk) on the output tile ----
     if (kk >= k0) {
-      const T* f1 = pF(kk, 0);
-      const T* f2 = pF(kk, 1);
-      const T* f3 = pF(kk, 2);
-      const T* g1 = pF(kk + 1, 0);
-      const T* g2 = pF(kk + 1, 1);
-      const T* b1 = pB(kk, 0);
-      const T* b2 = pB(kk, 1);
-      const T* b3 = pB(kk, 2);
-      const size_t base = (size_t)gk(kk) * plane_sz;
-      for (int p = tid; p < TX * TY; p += NT) {
-        const int r = p / TX;
-        const int x = p - r * TX;
-        if (i0 + x >= m.n1 || j0 + r >= m.n2) continue;
-        const int cf = r * G::PXF + x + G::HLF;
-        const int cb = (r + 1) * G::PXB + x + G::HLB;
-        T dF3 = 0, dF2 = 0;
+      const T* f1 = sF + (kk & 1) * 3 * G::SF;
+      const T* f2 = f1 + G::SF;
+      const T* f3 = f2 + G::SF;
+      const T* g1 = sF + ((kk + 1) & 1) * 3 * G::SF;
+      const T* g2 = g1 + G::SF;
+      const T* b1 = sB + (kk & 1) * 3 * G::SB;
+      const T* b2 = b1 + G::SB;
+      const T* b3 = b2 + G::SB;
+      const size_t off = poff(kk);
 #pragma unroll
-        for (int q = 1; q <= ME; ++q) {
-          dF3 += c.ae[q - 1] * (f3[cf + q] - f3[cf - q + 1]);
-          dF2 += c.ae[q - 1] * (f2[cf + q] - f2[cf - q + 1]);
+      for (int s = 0; s < NS3; ++s) {
+        if (s3_n[s] == 0) continue;
+        T dF2[R], dF3[R], f2w[R], f3w[R];
+        {
+          T w[NC * R];
+          load_window<T, NC, R>(f2 + s3_w[s], w);
+#pragma unroll
+          for (int u = 0; u < R; ++u) {
+            dF2[u] = faraday_taps<T, ME>(w, c.ae, u);
+            f2w[u] = w[u + ME - 1];
+          }
         }
-        const T f1c = f1[cf], f2c = f2[cf], f3c = f3[cf];
-        const size_t g = base + (size_t)(j0 + r) * m.n1 + (i0 + x);
-        oB1[g] = b1[cb] - (c.hy * (f3[cf + G::PXF] - f3c) - c.hz * (g2[cf] - f2c));
-        oB2[g] = b2[cb] - (c.hz * (g1[cf] - f1c) - dF3);
-        oB3[g] = b3[cb] - (dF2 - c.hy * (f1[cf + G::PXF] - f1c));
+        {
+          T w[NC * R];
+          load_window<T, NC, R>(f3 + s3_w[s], w);
+#pragma unroll
+          for (int u = 0; u < R; ++u) {
+            dF3[u] = faraday_taps<T, ME>(w, c.ae, u);
+            f3w[u] = w[u + ME - 1];
+          }
+        }
+        T f1c[R], f1n[R], f3n[R], g1c[R], g2c[R], hb1[R], hb2[R], hb3[R];
+        load_run<T, R, ME - 1>(f1 + s3_w[s], f1c);
+        load_run<T, R, ME - 1>(f1 + s3_w[s] + G::PXF, f1n);
+        load_run<T, R, ME - 1>(f3 + s3_w[s] + G::PXF, f3n);
+        load_run<T, R, ME - 1>(g1 + s3_w[s], g1c);
+        load_run<T, R, ME - 1>(g2 + s3_w[s], g2c);
+        load_run<T, R, G::HLB>(b1 + s3_b[s], hb1);
+        load_run<T, R, G::HLB>(b2 + s3_b[s], hb2);
+        load_run<T, R, G::HLB>(b3 + s3_b[s], hb3);
+        T o1[R], o2[R], o3[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          o1[u] = hb1[u] - (c.hy * (f3n[u] - f3w[u]) - c.hz * (g2c[u] - f2w[u]));
+          o2[u] = hb2[u] - (c.hz * (g1c[u] - f1c[u]) - dF3[u]);
+          o3[u] = hb3[u] - (dF2[u] - c.hy * (f1n[u] - f1c[u]));
+        }
+        const size_t g = off + s3_g[s];
+        if (s3_n[s] == R) {
+          store_vec<T, R>(oB1 + g, o1);
+          store_vec<T, R>(oB2 + g, o2);
+          store_vec<T, R>(oB3 + g, o3);
+        } else {
+#pragma unroll
+          for (int u = 0; u < R; ++u)
+            if (u < s3_n[s]) {
+              oB1[g + u] = o1[u];
+              oB2[g + u] = o2[u];
+              oB3[g + u] = o3[u];
+            }
+        }
       }
     }
-    if (kk + 1 < kend) load_E(kk + 3);
+    if (more) {
+      YP_STORE_PLANE(kk + 3);
+#pragma unroll
+      for (int s = 0; s < NS1; ++s)
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) curB[s][u][q] = nxtB[s][u][q];
+#pragma unroll
+      for (int s = 0; s < NJ; ++s)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) curJ[s][q] = nxtJ[s][q];
+    }
     __syncthreads();
   }
+#undef YP_LOAD_PLANE
+#undef YP_STORE_PLANE
 }
 
 template <typename T, int ME, int MB, int TX, int TY, int NT>
@@ -377,27 +630,26 @@ int run_sweep(const Mesh& m, void* const Ein[3], void* const Bin[3], void* const
   const int tiles_x = (m.n1 + TX - 1) / TX;
   const int tiles_y = (m.n2 + TY - 1) / TY;
   const int KZ = m.n3;
-  auto kern = sweep_kernel<T, ME, MB, TX, TY, NT>;
+  const bool hasJ = J && J[0];
+  auto kern = hasJ ? sweep_kernel<T, ME, MB, TX, TY, NT, true> : sweep_kernel<T, ME, MB, TX, TY, NT, false>;
   static_assert(G::lds_bytes <= 160 * 1024, "sweep tile exceeds LDS");
   if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G::lds_bytes) !=
       hipSuccess)
     return set_error(PIC_EHIP, "sweep: cannot reserve %zu bytes of LDS", G::lds_bytes);
-  const bool hasJ = J && J[0];
   hipLaunchKernelGGL(kern, dim3(tiles_x * tiles_y, (m.n3 + KZ - 1) / KZ), dim3(NT), G::lds_bytes, s,
                      (const T*)Ein[0], (const T*)Ein[1], (const T*)Ein[2], (const T*)Bin[0], (const T*)Bin[1],
                      (const T*)Bin[2], (const T*)(hasJ ? J[0] : nullptr), (const T*)(hasJ ? J[1] : nullptr),
                      (const T*)(hasJ ? J[2] : nullptr), (T*)Eout[0], (T*)Eout[1], (T*)Eout[2], (T*)Bout[0],
-                     (T*)Bout[1], (T*)Bout[2], m, KZ, tiles_x, c);
+                     (T*)Bout[1], (T*)Bout[2], m, KZ, tiles_x, tiles_x * tiles_y, c);
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "sweep launch failed");
 }
 
-template <typename T, int TXw, int TXn>
+template <typename T, int TXw, int TXn, int TY, int NT>
 int dispatch_sweep(const Mesh& m, void* const Ein[3], void* const Bin[3], void* const J[3], void* const Eout[3],
                    void* const Bout[3], const double* CE, int ME, const double* CB, int MB, double dt,
                    hipStream_t s) {
   const int we = round_width(ME), wb = round_width(MB);
   const int w = we > wb ? we : wb;
-  constexpr int TY = 4, NT = 512;
   // Ampere stencil either Yee (width 1) or padded to the Faraday width
   if (wb == 1) {
     switch (we) {
@@ -434,8 +686,8 @@ int launch_sweep(int prec, const Mesh& m, void* const Ein[3], void* const Bin[3]
                  void* const Eout[3], void* const Bout[3], const double* CE, int ME, const double* CB, int MB,
                  double dt, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  if (prec == PIC_FP64) return dispatch_sweep<double, 128, 64>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, MB, dt, s);
-  return dispatch_sweep<float, 128, 128>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, MB, dt, s);
+  if (prec == PIC_FP64) return dispatch_sweep<double, 128, 64, 4, 512>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, MB, dt, s);
+  return dispatch_sweep<float, 128, 128, 8, 512>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, MB, dt, s);
 }
 
 int launch_advance_e(int prec, const Mesh& m, void* const E[3], void* const B[3], void* const J[3],
