@@ -49,6 +49,43 @@ def _device_fields(n, dx, pulse, x_head, w0, dtype, torch):
     return E, B
 
 
+def _device_plane_wave(n, dx, a0, dtype, torch):
+    """Monochromatic plane wave a = a0 sin(t - x1) at t = 0, polarisation x2:
+    E2 = B3 = -a0 cos(x_head - x1) sampled at the staggered x1 locations."""
+    from paper_2004_03754_amd import workloads as wl
+    return _device_fields(n, dx, wl.PlaneWave(a0=a0), 0.0, None, dtype, torch)
+
+
+def _device_uniform_particles(npart, lo, hi, seed, torch):
+    """Uniform positions in [lo, hi) from a seeded device generator; at rest."""
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(seed)
+    lo = torch.tensor(lo, device="cuda:0", dtype=torch.float64)[:, None]
+    hi = torch.tensor(hi, device="cuda:0", dtype=torch.float64)[:, None]
+    x = lo + (hi - lo) * torch.rand((3, npart), generator=g, device="cuda:0", dtype=torch.float64)
+    return x.contiguous(), torch.zeros_like(x)
+
+
+def _device_plasma(n, dx, ppd, u_th, seed, torch):
+    """ppd^3 electrons per cell on a regular sub-lattice (cell-centred
+    offsets), momenta N(0, u_th^2) per component from a seeded generator."""
+    n1, n2, n3 = n
+    dev = "cuda:0"
+    off = (torch.arange(ppd, device=dev, dtype=torch.float64) + 0.5) / ppd
+    cx = ((torch.arange(n1, device=dev, dtype=torch.float64)[:, None] + off[None, :]).reshape(-1)) * dx[0]
+    cy = ((torch.arange(n2, device=dev, dtype=torch.float64)[:, None] + off[None, :]).reshape(-1)) * dx[1]
+    cz = ((torch.arange(n3, device=dev, dtype=torch.float64)[:, None] + off[None, :]).reshape(-1)) * dx[2]
+    npart = cx.numel() * cy.numel() * cz.numel()
+    x = torch.empty((3, npart), device=dev, dtype=torch.float64)
+    x[0].view(cz.numel(), cy.numel(), cx.numel()).copy_(cx[None, None, :].expand(cz.numel(), cy.numel(), -1))
+    x[1].view(cz.numel(), cy.numel(), cx.numel()).copy_(cy[None, :, None].expand(cz.numel(), -1, cx.numel()))
+    x[2].view(cz.numel(), cy.numel(), cx.numel()).copy_(cz[:, None, None].expand(-1, cy.numel(), cx.numel()))
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    u = u_th * torch.randn((3, npart), generator=g, device=dev, dtype=torch.float64)
+    return x, u
+
+
 def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -95,6 +132,90 @@ def run_vacuum(torch, b, wl, n, prec, pulse, x_head, w0, npart, box, steps, warm
                sweep_bytes=12 * elem * cells, push_bytes=96 * npart)
     grid.close()
     del E, B, xd, ud
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_plane_wave(torch, b, wl, CE, CB, steps):
+    """Mixed-precision workload: 2048 x 512 x 512 cells, plane wave a0 = 1e4
+    along x1 (exactly periodic over 64 lambda0), 4,194,304 electrons at rest
+    spread over the box, exact pusher; FP32 fields, then FP64 fields."""
+    dx = (wl.DX1, wl.DX2, wl.DX3)
+    n = (2048, 512, 512)
+    L = [n[d] * dx[d] for d in range(3)]
+    out = {}
+    for prec in ("fp32", "fp64"):
+        dtype = torch.float32 if prec == "fp32" else torch.float64
+        E, B = _device_plane_wave(n, dx, 1.0e4, dtype, torch)
+        xd, ud = _device_uniform_particles(1 << 22, [0, 0, 0], L, 5, torch)
+        grid = b.Grid(E, B, dx, wl.DT, CE, CB, prec=prec)
+        p = b.Particles(xd, ud, q=-1.0, m=1.0, w=1.0)
+        grid.step_n([p], 2, pusher="analytic")
+        torch.cuda.synchronize()
+        t0, t1 = _events(torch)
+        t0.record()
+        grid.step_n([p], steps, pusher="analytic")
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / steps
+        s0, s1 = _events(torch)
+        s0.record()
+        grid.step_n([], 4)
+        s1.record()
+        torch.cuda.synchronize()
+        ms_sweep = s0.elapsed_time(s1) / 4
+        cells = n[0] * n[1] * n[2]
+        elem = 4 if prec == "fp32" else 8
+        out[prec] = {"ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3),
+                     "particle_pushes_per_s": (1 << 22) / (ms * 1e-3), "sweep_ms": ms_sweep,
+                     "sweep_GBps": 12 * elem * cells / (ms_sweep * 1e-3) / 1e9}
+        grid.close()
+        del E, B, xd, ud, grid, p
+        torch.cuda.empty_cache()
+    out["fp32_speedup_step"] = out["fp64"]["ms_per_step"] / out["fp32"]["ms_per_step"]
+    out["fp32_speedup_sweep"] = out["fp64"]["sweep_ms"] / out["fp32"]["sweep_ms"]
+    return out
+
+
+def run_plasma(torch, b, wl, CE, CB, steps):
+    """Plasma workload: 512 x 256 x 256 cells, electrons at n = 0.01 n_c with
+    8 per cell (268,435,456), u_th = 0.01, Gaussian laser a0 = 10, w0 = 4
+    lambda0; Boris pusher, Esirkepov deposit; FP32 fields, FP64 particles."""
+    dx = (wl.DX1, wl.DX2, wl.DX3)
+    n = (512, 256, 256)
+    L0 = wl.LAMBDA0
+    pulse = wl.Sin2Pulse(a0=10.0, Lp=10 * L0, period=n[0] * dx[0])
+    E, B = _device_fields(n, dx, pulse, 12 * L0, 4 * L0, torch.float32, torch)
+    J = [torch.zeros_like(E[0]) for _ in range(3)]
+    xd, ud = _device_plasma(n, dx, 2, 0.01, 3, torch)
+    npart = xd.shape[1]
+    grid = b.Grid(E, B, dx, wl.DT, CE, CB, J=J, prec="fp32")
+    p = b.Particles(xd, ud, q=-1.0, m=1.0, w=0.01 / 8)
+    grid.step_n([p], 2, pusher="boris", deposit=True)
+    torch.cuda.synchronize()
+    t0, t1 = _events(torch)
+    t0.record()
+    grid.step_n([p], steps, pusher="boris", deposit=True)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    xo = torch.empty_like(xd)
+    q0, q1 = _events(torch)
+    q0.record()
+    grid.gather_push(p, "boris", x_old=xo)
+    q1.record()
+    torch.cuda.synchronize()
+    d0, d1 = _events(torch)
+    d0.record()
+    grid.deposit_J(p, xo, zero_first=True)
+    d1.record()
+    torch.cuda.synchronize()
+    grid.check(p)
+    out = {"ms_per_step": ms, "particles": npart, "particle_pushes_per_s": npart / (ms * 1e-3),
+           "cell_updates_per_s": n[0] * n[1] * n[2] / (ms * 1e-3),
+           "gather_push_ms": q0.elapsed_time(q1), "deposit_ms": d0.elapsed_time(d1)}
+    grid.close()
+    del E, B, J, xd, ud, xo, grid, p
     torch.cuda.empty_cache()
     return out
 
@@ -219,6 +340,8 @@ def main():
             "sweep_GBps": fp32["sweep_bytes"] / (fp32["ms_sweep"] * 1e-3) / 1e9,
             "speedup_vs_fp64_step": main_run["ms_step"] / fp32["ms_step"],
             "speedup_vs_fp64_sweep": main_run["ms_sweep"] / fp32["ms_sweep"]}
+        res["plane_wave_2048x512x512"] = run_plane_wave(torch, b, wl, CE, CB, steps=20)
+        res["plasma_512x256x256"] = run_plasma(torch, b, wl, CE, CB, steps=10)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res))
