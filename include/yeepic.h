@@ -77,6 +77,8 @@ typedef struct pic_particles {
   double *x[3];        /* device positions in [0, n_d dx_d); x[2] may be NULL in 2D */
   double *u[3];        /* device momenta gamma*beta (per unit mass) */
   double q, m, w;      /* charge, mass, macro-weight (density per particle) */
+  int64_t *id;         /* optional device labels (may be NULL), permuted together
+                          with x and u whenever a call reorders the particles */
 } pic_particles;
 
 typedef struct pic_grid pic_grid;   /* opaque */
@@ -146,12 +148,19 @@ int pic_gather_push(pic_grid *g, pic_particles *p, int pusher, double *const x_o
 int pic_deposit_J(pic_grid *g, const pic_particles *p, double *const x_old[3], int zero_first);
 
 /* ---- the step loop ----------------------------------------------------------
- * nsteps times: for each species gather + push + position update (keeping
- * x^n when deposit != 0), then [clear J and deposit every species], then the
- * fused field sweep.  No host synchronisation inside; the fields end in the
- * caller's arrays. */
+ * nsteps times: [clear J], for each species gather + push + position update
+ * [and charge-conserving deposit], then the fused field sweep.  No host
+ * synchronisation inside; the fields end in the caller's arrays.
+ * With deposit on a 3D grid the particles of every species are sorted by
+ * spatial tile (8^3 cells) at the first step and then every
+ * pic_set_sort_interval steps, and the current of each tile is accumulated in
+ * on-chip memory: such calls REORDER the particles (x, u and id together).
+ * Vacuum calls and 2D grids keep the order. */
 int pic_step_n(pic_grid *g, pic_particles *const *species, int nspecies, int nsteps,
                int pusher, int deposit);
+/* Steps between particle re-sorts in pic_step_n (1..64, default 4); the
+ * on-chip current tile grows with the interval (|v| < c bounds the drift). */
+int pic_set_sort_interval(pic_grid *g, int steps);
 
 /* ---- diagnostics ------------------------------------------------------------
  * Waits for the grid's stream and reports a pending HIP error. */

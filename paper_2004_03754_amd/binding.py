@@ -39,12 +39,13 @@ class _GridDesc(ctypes.Structure):
 
 class _Particles(ctypes.Structure):
     _fields_ = [("np", ctypes.c_int64), ("x", ctypes.c_void_p * 3), ("u", ctypes.c_void_p * 3),
-                ("q", ctypes.c_double), ("m", ctypes.c_double), ("w", ctypes.c_double)]
+                ("q", ctypes.c_double), ("m", ctypes.c_double), ("w", ctypes.c_double),
+                ("id", ctypes.c_void_p)]
 
 
 EXPORTS = ["pic_design_coeffs", "pic_init_grid", "pic_set_fields", "pic_advance_B_half", "pic_advance_E",
            "pic_field_sweep", "pic_gather_push", "pic_deposit_J", "pic_step_n", "pic_sync", "pic_check",
-           "pic_grid_widths", "pic_destroy", "pic_last_error"]
+           "pic_grid_widths", "pic_destroy", "pic_last_error", "pic_set_sort_interval"]
 
 
 def lib():
@@ -65,6 +66,7 @@ def lib():
         L.pic_gather_push.argtypes = [vp, ctypes.POINTER(_Particles), i, vp]
         L.pic_deposit_J.argtypes = [vp, ctypes.POINTER(_Particles), vp, i]
         L.pic_step_n.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(_Particles)), i, i, i, i]
+        L.pic_set_sort_interval.argtypes = [vp, i]
         L.pic_sync.argtypes = [vp]
         L.pic_check.argtypes = [vp, ctypes.POINTER(_Particles)]
         L.pic_grid_widths.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
@@ -104,11 +106,13 @@ class Particles:
     """One species: x and u are float64 device tensors of shape (3, np)
     (rows contiguous); q, m, w are charge, mass and macro-weight."""
 
-    def __init__(self, x, u, q=-1.0, m=1.0, w=1.0):
+    def __init__(self, x, u, q=-1.0, m=1.0, w=1.0, id=None):
         import torch
         assert x.dtype == torch.float64 and u.dtype == torch.float64
         assert x.is_contiguous() and u.is_contiguous() and x.shape == u.shape and x.shape[0] == 3
-        self.x, self.u = x, u
+        if id is not None:
+            assert id.dtype == torch.int64 and id.is_contiguous() and id.shape == (x.shape[1],)
+        self.x, self.u, self.id = x, u, id
         self.q, self.m, self.w = float(q), float(m), float(w)
         self._s = _Particles()
         npart = x.shape[1]
@@ -117,6 +121,7 @@ class Particles:
             self._s.x[d] = x.data_ptr() + d * npart * 8 if npart else None
             self._s.u[d] = u.data_ptr() + d * npart * 8 if npart else None
         self._s.q, self._s.m, self._s.w = self.q, self.m, self.w
+        self._s.id = id.data_ptr() if (id is not None and npart) else None
 
     @property
     def np(self):
@@ -203,6 +208,9 @@ class Grid:
         for s, p in enumerate(species):
             arr[s] = ctypes.pointer(p._s)
         _check(lib().pic_step_n(self._h, arr, len(species), int(nsteps), PUSHERS[pusher], int(deposit)))
+
+    def set_sort_interval(self, steps):
+        _check(lib().pic_set_sort_interval(self._h, int(steps)))
 
     def sync(self):
         _check(lib().pic_sync(self._h))

@@ -6,29 +6,45 @@
 #include <cstdio>
 #include <cstring>
 #include <utility>
+#include <vector>
 
 #include "yeepic_internal.h"
 
+// Per-species buffers of the tile-sorted plasma path (grow-only).
+struct SortState {
+  int64_t cap = 0;
+  int ntiles = 0;
+  int* keys = nullptr;
+  int* counts = nullptr;
+  int* offsets = nullptr;
+  int* cursors = nullptr;
+  double* xs[3] = {nullptr, nullptr, nullptr};
+  double* us[3] = {nullptr, nullptr, nullptr};
+  int64_t* ids = nullptr;
+};
+
 struct pic_grid {
-  int ndim;
-  int64_t n[3];
-  double dx[3];
-  double dt;
-  int M;
-  double CE[PIC_MAX_M];
-  double CB[PIC_MAX_M];
-  int ME, MB;  // widths after trimming negligible trailing coefficients
-  int prec;
-  size_t elem;
-  void* E[3];
-  void* B[3];
-  void* J[3];
-  void* alt[6];  // second field set for the out-of-place sweep
-  hipStream_t stream;
-  int* d_flag;
-  double* xo[3];   // x^n scratch for the deposit inside pic_step_n (grow-only)
-  int64_t xo_cap;
-  yeepic::Mesh mesh;
+  int ndim = 0;
+  int64_t n[3] = {0, 0, 0};
+  double dx[3] = {0, 0, 0};
+  double dt = 0;
+  int M = 0;
+  double CE[PIC_MAX_M] = {};
+  double CB[PIC_MAX_M] = {};
+  int ME = 0, MB = 0;  // widths after trimming negligible trailing coefficients
+  int prec = 0;
+  size_t elem = 0;
+  void* E[3] = {nullptr, nullptr, nullptr};
+  void* B[3] = {nullptr, nullptr, nullptr};
+  void* J[3] = {nullptr, nullptr, nullptr};
+  void* alt[6] = {};  // second field set for the out-of-place sweep
+  hipStream_t stream = nullptr;
+  int* d_flag = nullptr;
+  double* xo[3] = {nullptr, nullptr, nullptr};  // x^n scratch of the unsorted deposit path (grow-only)
+  int64_t xo_cap = 0;
+  int sort_every = 4;
+  std::vector<SortState> sorts;
+  yeepic::Mesh mesh = {};
 };
 
 namespace yeepic {
@@ -90,6 +106,36 @@ static int check_particles(const pic_grid* g, const pic_particles* p) {
   return PIC_OK;
 }
 
+static void free_sort(SortState& st) {
+  void* ptrs[] = {st.keys, st.counts, st.offsets, st.cursors, st.xs[0], st.xs[1], st.xs[2],
+                  st.us[0], st.us[1], st.us[2], st.ids};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  st = SortState();
+}
+
+static int ensure_sort(pic_grid* g, SortState& st, int64_t np, int ntiles, bool ids) {
+  if (np <= st.cap && ntiles == st.ntiles && (!ids || st.ids)) return PIC_OK;
+  (void)hipStreamSynchronize(g->stream);
+  free_sort(st);
+  const size_t n = (size_t)(np > 0 ? np : 1);
+  bool ok = hipMalloc((void**)&st.keys, n * sizeof(int)) == hipSuccess &&
+            hipMalloc((void**)&st.counts, (size_t)ntiles * sizeof(int)) == hipSuccess &&
+            hipMalloc((void**)&st.offsets, ((size_t)ntiles + 1) * sizeof(int)) == hipSuccess &&
+            hipMalloc((void**)&st.cursors, (size_t)ntiles * sizeof(int)) == hipSuccess;
+  for (int d = 0; d < 3 && ok; ++d)
+    ok = hipMalloc((void**)&st.xs[d], n * sizeof(double)) == hipSuccess &&
+         hipMalloc((void**)&st.us[d], n * sizeof(double)) == hipSuccess;
+  if (ok && ids) ok = hipMalloc((void**)&st.ids, n * sizeof(int64_t)) == hipSuccess;
+  if (!ok) {
+    free_sort(st);
+    return set_error(PIC_ENOMEM, "cannot allocate particle sort buffers for %lld particles", (long long)np);
+  }
+  st.cap = np;
+  st.ntiles = ntiles;
+  return PIC_OK;
+}
+
 }  // namespace yeepic
 
 using namespace yeepic;
@@ -132,7 +178,6 @@ int pic_init_grid(const pic_grid_desc* d, pic_grid** out) {
     return set_error(PIC_ECFL, "dt = %g exceeds the CFL bound %g", d->dt, 1.0 / std::sqrt(lim));
 
   pic_grid* g = new pic_grid();
-  std::memset(g, 0, sizeof *g);
   g->ndim = d->ndim;
   for (int a = 0; a < 3; ++a) {
     g->n[a] = d->n[a];
@@ -162,6 +207,9 @@ int pic_init_grid(const pic_grid_desc* d, pic_grid** out) {
   m.dx1 = g->dx[0];
   m.dx2 = g->dx[1];
   m.dx3 = g->dx[2];
+  m.idx1 = 1.0 / m.dx1;
+  m.idx2 = 1.0 / m.dx2;
+  m.idx3 = 1.0 / m.dx3;
   m.L1 = m.n1 * m.dx1;
   m.L2 = m.n2 * m.dx2;
   m.L3 = m.n3 * m.dx3;
@@ -277,11 +325,11 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
   int64_t npmax = 0;
   for (int s = 0; s < nspecies; ++s) npmax = species[s]->np > npmax ? species[s]->np : npmax;
   double* xo[3] = {nullptr, nullptr, nullptr};
-  if (deposit && npmax > 0) {
+  if (deposit && g->ndim != 3 && npmax > 0) {
     if (npmax > g->xo_cap) {
-      hipStreamSynchronize(g->stream);
+      (void)hipStreamSynchronize(g->stream);
       for (int d = 0; d < 3; ++d) {
-        hipFree(g->xo[d]);
+        (void)hipFree(g->xo[d]);
         g->xo[d] = nullptr;
       }
       g->xo_cap = 0;
@@ -296,11 +344,40 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
   void* nxt[6] = {g->alt[0], g->alt[1], g->alt[2], g->alt[3], g->alt[4], g->alt[5]};
   int rc = PIC_OK;
   const size_t jbytes = (size_t)g->n[0] * g->n[1] * g->n[2] * g->elem;
+  // 3D plasma: particles sorted by tile, current accumulated on chip
+  const bool tiled = deposit && g->ndim == 3;
+  TileGeom tg = {};
+  if (tiled) {
+    tg = make_tile_geom(g->mesh, g->dt, g->sort_every);
+    if ((int)g->sorts.size() < nspecies) g->sorts.resize(nspecies);
+    for (int s = 0; s < nspecies && rc == PIC_OK; ++s)
+      rc = ensure_sort(g, g->sorts[s], species[s]->np, tg.ntiles, species[s]->id != nullptr);
+    if (rc) return rc;
+  }
   for (int step = 0; step < nsteps && rc == PIC_OK; ++step) {
     if (deposit)
       for (int c = 0; c < 3 && rc == PIC_OK; ++c)
         if (hipMemsetAsync(g->J[c], 0, jbytes, g->stream) != hipSuccess) rc = set_error(PIC_EHIP, "clear J");
     for (int s = 0; s < nspecies && rc == PIC_OK; ++s) {
+      if (tiled) {
+        SortState& st = g->sorts[s];
+        pic_particles src = *species[s];
+        if (step % g->sort_every == 0) {
+          pic_particles scr = *species[s];
+          for (int d = 0; d < 3; ++d) {
+            scr.x[d] = st.xs[d];
+            scr.u[d] = st.us[d];
+          }
+          scr.id = species[s]->id ? st.ids : nullptr;
+          rc = launch_tile_sort(g->mesh, tg, *species[s], scr, st.keys, st.counts, st.offsets, st.cursors,
+                                g->stream);
+          src = scr;
+        }
+        if (rc == PIC_OK)
+          rc = launch_tile_push(g->prec, g->mesh, tg, cur, cur + 3, g->J, st.offsets, src, *species[s], pusher,
+                                g->dt, g->stream);
+        continue;
+      }
       rc = launch_gather_push(g->prec, g->mesh, cur, cur + 3, *species[s], pusher, g->dt, deposit ? xo : nullptr,
                               g->stream);
       if (rc == PIC_OK && deposit) rc = launch_deposit(g->prec, g->mesh, g->J, *species[s], xo, g->dt, g->stream);
@@ -318,6 +395,13 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
     }
   }
   return rc;
+}
+
+int pic_set_sort_interval(pic_grid* g, int steps) {
+  if (!g) return set_error(PIC_EINVAL, "grid is NULL");
+  if (steps < 1 || steps > 64) return set_error(PIC_EINVAL, "sort interval must be in 1..64");
+  g->sort_every = steps;
+  return PIC_OK;
 }
 
 int pic_sync(pic_grid* g) {
@@ -351,12 +435,13 @@ int pic_check(pic_grid* g, const pic_particles* p) {
 
 void pic_destroy(pic_grid* g) {
   if (!g) return;
-  hipStreamSynchronize(g->stream);
+  (void)hipStreamSynchronize(g->stream);
   for (int c = 0; c < 6; ++c)
-    if (g->alt[c]) hipFree(g->alt[c]);
+    if (g->alt[c]) (void)hipFree(g->alt[c]);
   for (int d = 0; d < 3; ++d)
-    if (g->xo[d]) hipFree(g->xo[d]);
-  if (g->d_flag) hipFree(g->d_flag);
+    if (g->xo[d]) (void)hipFree(g->xo[d]);
+  for (SortState& st : g->sorts) free_sort(st);
+  if (g->d_flag) (void)hipFree(g->d_flag);
   delete g;
 }
 

@@ -3,220 +3,13 @@
 // All particle arithmetic is double precision; field values are promoted.
 #include <hip/hip_runtime.h>
 
-#include "yeepic_internal.h"
+#include "particle_common.h"
 
 namespace yeepic {
 namespace {
 
-// Linear-shape nodes and weights along one direction for the component
-// offset ``off`` (0 or 1/2 cell): u = x/dx - off, i0 = floor(u),
-// w1 = u - i0 (App. A).  The index is clamped into [-1, n] before the
-// periodic wrap so that no input can address outside the mesh.
-struct Axis {
-  int i0, i1;
-  double w0, w1;
-};
+using namespace pdev;
 
-__device__ __forceinline__ Axis axis(double x, double dx, double off, int n) {
-  const double u = x / dx - off;
-  double fl = floor(u);
-  fl = fmin(fmax(fl, -1.0), (double)n);
-  Axis a;
-  a.w1 = u - fl;
-  a.w0 = 1.0 - a.w1;
-  int i = (int)fl;
-  i += (i < 0) ? n : 0;
-  i -= (i >= n) ? n : 0;
-  a.i0 = i;
-  a.i1 = (i + 1 == n) ? 0 : i + 1;
-  return a;
-}
-
-template <typename T>
-__device__ __forceinline__ double interp3(const T* __restrict__ f, const Axis& a, const Axis& b, const Axis& c,
-                                          int n1, size_t plane) {
-  const size_t r00 = (size_t)c.i0 * plane + (size_t)b.i0 * n1;
-  const size_t r01 = (size_t)c.i0 * plane + (size_t)b.i1 * n1;
-  const size_t r10 = (size_t)c.i1 * plane + (size_t)b.i0 * n1;
-  const size_t r11 = (size_t)c.i1 * plane + (size_t)b.i1 * n1;
-  const double f000 = f[r00 + a.i0], f001 = f[r00 + a.i1];
-  const double f010 = f[r01 + a.i0], f011 = f[r01 + a.i1];
-  const double f100 = f[r10 + a.i0], f101 = f[r10 + a.i1];
-  const double f110 = f[r11 + a.i0], f111 = f[r11 + a.i1];
-  return c.w0 * (b.w0 * (a.w0 * f000 + a.w1 * f001) + b.w1 * (a.w0 * f010 + a.w1 * f011)) +
-         c.w1 * (b.w0 * (a.w0 * f100 + a.w1 * f101) + b.w1 * (a.w0 * f110 + a.w1 * f111));
-}
-
-template <typename T>
-__device__ __forceinline__ double interp2(const T* __restrict__ f, const Axis& a, const Axis& b, int n1) {
-  const size_t r0 = (size_t)b.i0 * n1, r1 = (size_t)b.i1 * n1;
-  return b.w0 * (a.w0 * (double)f[r0 + a.i0] + a.w1 * (double)f[r0 + a.i1]) +
-         b.w1 * (a.w0 * (double)f[r1 + a.i0] + a.w1 * (double)f[r1 + a.i1]);
-}
-
-// ---------------------------------------------------------------------------
-// Boris (Sec. 1): half E kick, rotation about B, half E kick.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void boris(double u[3], const double E[3], const double B[3], double qm, double dt) {
-  const double eps = 0.5 * qm * dt;
-  double um[3] = {u[0] + eps * E[0], u[1] + eps * E[1], u[2] + eps * E[2]};
-  const double g = sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
-  const double t[3] = {eps * B[0] / g, eps * B[1] / g, eps * B[2] / g};
-  const double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
-  const double s[3] = {2 * t[0] / (1 + tt), 2 * t[1] / (1 + tt), 2 * t[2] / (1 + tt)};
-  const double up[3] = {um[0] + (um[1] * t[2] - um[2] * t[1]), um[1] + (um[2] * t[0] - um[0] * t[2]),
-                        um[2] + (um[0] * t[1] - um[1] * t[0])};
-  u[0] = um[0] + (up[1] * s[2] - up[2] * s[1]) + eps * E[0];
-  u[1] = um[1] + (up[2] * s[0] - up[0] * s[2]) + eps * E[1];
-  u[2] = um[2] + (up[0] * s[1] - up[1] * s[0]) + eps * E[2];
-}
-
-// ---------------------------------------------------------------------------
-// Exact push for fields constant over the step (Sec. 1, Sec. 4.1).
-//
-// With F = (q/m) Lambda(E, B) acting on U = (gamma, u), U(tau) = exp(F tau) U0
-// in proper time.  F has eigenvalues +-kappa, +-i omega with
-//   kappa^2 - omega^2 = (q/m)^2 (E^2 - B^2),  kappa omega = (q/m)^2 |E.B|,
-// so by Cayley-Hamilton exp(F tau) = a0 + a1 F + a2 F^2 + a3 F^3 and the
-// lab time is t(tau) = e0 . (A0 + A1 F + A2 F^2 + A3 F^3) U0 with
-// A_k = int_0^tau a_k.  With X = (kappa tau)^2, Y = (omega tau)^2 every
-// coefficient is an entire function of (X, -Y):
-//   a0 = 1 + XY G4, a1 = tau (1 + XY G5), a2 = tau^2 G2, a3 = tau^3 G3,
-//   A0 = a1, A1 = tau^2 (1/2 + XY G6), A2 = a3, A3 = tau^4 G4,
-//   G_m = sum_k h_k(X, -Y)/(2k+m)!,  h_k = complete homogeneous polynomial.
-// For max(X, Y) <= 1 the series is summed; otherwise the hyperbolic /
-// trigonometric closed forms are used, written without cancellation where a
-// cancellation-free form exists.  t(tau) = dt is solved by safeguarded Newton
-// (t increases with dt/dtau = gamma >= 1, root between 0 and dt).
-// ---------------------------------------------------------------------------
-struct ExpCoef {
-  double a0, a1, a2, a3, A1, A3;  // A0 = a1, A2 = a3
-};
-
-__device__ __forceinline__ ExpCoef exp_coef(double k2, double w2, double tau) {
-  const double t2 = tau * tau;
-  const double X = k2 * t2, Y = w2 * t2;
-  ExpCoef e;
-  if (X <= 1.0 && Y <= 1.0) {
-    // G_m for m = 2..6 from h_k(X, Z), Z = -Y; 14 terms reach below 1e-19
-    const double Z = -Y;
-    double h = 1.0, zk = 1.0;
-    double G[7] = {0, 0, 0, 0, 0, 0, 0};
-    // inverse factorials 1/(2k+m)! built incrementally per m
-    double f2 = 1.0 / 2, f3 = 1.0 / 6, f4 = 1.0 / 24, f5 = 1.0 / 120, f6 = 1.0 / 720;
-    for (int k = 0; k < 14; ++k) {
-      G[2] += h * f2;
-      G[3] += h * f3;
-      G[4] += h * f4;
-      G[5] += h * f5;
-      G[6] += h * f6;
-      zk *= Z;
-      h = X * h + zk;  // h_{k+1} = X h_k + Z^{k+1}
-      const double n2 = 2.0 * k + 2;
-      f2 /= (n2 + 1) * (n2 + 2);
-      f3 /= (n2 + 2) * (n2 + 3);
-      f4 /= (n2 + 3) * (n2 + 4);
-      f5 /= (n2 + 4) * (n2 + 5);
-      f6 /= (n2 + 5) * (n2 + 6);
-    }
-    const double XY = X * Y;
-    e.a0 = 1.0 + XY * G[4];
-    e.a1 = tau * (1.0 + XY * G[5]);
-    e.a2 = t2 * G[2];
-    e.a3 = t2 * tau * G[3];
-    e.A1 = t2 * (0.5 + XY * G[6]);
-    e.A3 = t2 * t2 * G[4];
-    return e;
-  }
-  const double kap = sqrt(k2), om = sqrt(w2);
-  const double x = kap * tau, y = om * tau;
-  // sinh(x)/kappa, (cosh x - 1)/kappa^2, sin(y)/omega, (1 - cos y)/omega^2
-  double sh, ch1, sn, cs1;
-  if (fabs(x) < 1e-4) {
-    sh = tau * (1.0 + X / 6.0 * (1.0 + X / 20.0));
-    ch1 = t2 * 0.5 * (1.0 + X / 12.0 * (1.0 + X / 30.0));
-  } else {
-    sh = sinh(x) / kap;
-    const double s = sinh(0.5 * x) / kap;
-    ch1 = 2.0 * s * s;
-  }
-  if (fabs(y) < 1e-4) {
-    sn = tau * (1.0 - Y / 6.0 * (1.0 - Y / 20.0));
-    cs1 = t2 * 0.5 * (1.0 - Y / 12.0 * (1.0 - Y / 30.0));
-  } else {
-    sn = sin(y) / om;
-    const double s = sin(0.5 * y) / om;
-    cs1 = 2.0 * s * s;
-  }
-  const double inv = 1.0 / (k2 + w2);
-  const double chx = 1.0 + k2 * ch1, cy = 1.0 - w2 * cs1;  // cosh x, cos y
-  e.a0 = (w2 * chx + k2 * cy) * inv;
-  e.a1 = (w2 * sh + k2 * sn) * inv;
-  e.a2 = (k2 * ch1 + w2 * cs1) * inv;
-  e.a3 = (sh - sn) * inv;
-  e.A1 = (w2 * ch1 + k2 * cs1) * inv;
-  e.A3 = (ch1 - cs1) * inv;
-  return e;
-}
-
-__device__ __forceinline__ void apply_F(const double E[3], const double B[3], double qm, const double v[4],
-                                        double o[4]) {
-  o[0] = qm * (E[0] * v[1] + E[1] * v[2] + E[2] * v[3]);
-  o[1] = qm * (E[0] * v[0] + B[2] * v[2] - B[1] * v[3]);
-  o[2] = qm * (E[1] * v[0] - B[2] * v[1] + B[0] * v[3]);
-  o[3] = qm * (E[2] * v[0] + B[1] * v[1] - B[0] * v[2]);
-}
-
-__device__ __forceinline__ void analytic(double u[3], const double E[3], const double B[3], double qm,
-                                         double dt) {
-  const double E2 = E[0] * E[0] + E[1] * E[1] + E[2] * E[2];
-  const double B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
-  const double EB = E[0] * B[0] + E[1] * B[1] + E[2] * B[2];
-  const double q2 = qm * qm;
-  const double P = 0.5 * (E2 - B2);
-  const double Q = sqrt(P * P + EB * EB);
-  double k2, w2;  // kappa^2, omega^2 without cancellation
-  if (P >= 0) {
-    k2 = q2 * (P + Q);
-    w2 = (P + Q) > 0 ? q2 * (EB * EB) / (P + Q) : 0.0;
-  } else {
-    w2 = q2 * (Q - P);
-    k2 = q2 * (EB * EB) / (Q - P);
-  }
-  double U0[4] = {sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]), u[0], u[1], u[2]};
-  double V1[4], V2[4], V3[4];
-  apply_F(E, B, qm, U0, V1);
-  apply_F(E, B, qm, V1, V2);
-  apply_F(E, B, qm, V2, V3);
-  double lo = fmin(0.0, dt), hi = fmax(0.0, dt);
-  double tau = dt / U0[0];
-  for (int it = 0; it < 100; ++it) {
-    const ExpCoef e = exp_coef(k2, w2, tau);
-    const double t = e.a1 * U0[0] + e.A1 * V1[0] + e.a3 * V2[0] + e.A3 * V3[0];
-    const double g = e.a0 * U0[0] + e.a1 * V1[0] + e.a2 * V2[0] + e.a3 * V3[0];
-    const double f = t - dt;
-    if (fabs(f) <= 1e-16 * fabs(dt)) break;
-    if (!(f <= 0.0)) hi = tau; else lo = tau;
-    double nx = tau - f / g;
-    if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
-    const bool small = fabs(nx - tau) <= 1e-15 * fabs(tau);
-    tau = nx;
-    if (small) break;
-  }
-  const ExpCoef e = exp_coef(k2, w2, tau);
-  for (int d = 0; d < 3; ++d) u[d] = e.a0 * U0[d + 1] + e.a1 * V1[d + 1] + e.a2 * V2[d + 1] + e.a3 * V3[d + 1];
-}
-
-// periodic wrap of an advanced position (the oracle's rule)
-__device__ __forceinline__ double wrap_pos(double x, double L) {
-  if (x < 0.0) {
-    x += L;
-    if (x >= L) x = 0.0;
-  } else if (x >= L) {
-    x -= L;
-  }
-  return x;
-}
 
 template <typename T, int PUSH, int NDIM>
 __global__ __launch_bounds__(256) void gather_push_kernel(const T* __restrict__ E1, const T* __restrict__ E2,
@@ -233,84 +26,23 @@ __global__ __launch_bounds__(256) void gather_push_kernel(const T* __restrict__ 
   double x[3] = {x1[p], x2[p], NDIM == 3 ? x3[p] : 0.0};
   double u[3] = {u1[p], u2[p], u3[p]};
   double E[3], B[3];
-  const Axis a0 = axis(x[0], m.dx1, 0.0, m.n1), ah = axis(x[0], m.dx1, 0.5, m.n1);
-  const Axis b0 = axis(x[1], m.dx2, 0.0, m.n2), bh = axis(x[1], m.dx2, 0.5, m.n2);
-  if (NDIM == 3) {
-    const Axis c0 = axis(x[2], m.dx3, 0.0, m.n3), ch = axis(x[2], m.dx3, 0.5, m.n3);
-    const size_t pl = (size_t)m.n1 * m.n2;
-    E[0] = interp3(E1, ah, b0, c0, m.n1, pl);
-    E[1] = interp3(E2, a0, bh, c0, m.n1, pl);
-    E[2] = interp3(E3, a0, b0, ch, m.n1, pl);
-    B[0] = interp3(B1, a0, bh, ch, m.n1, pl);
-    B[1] = interp3(B2, ah, b0, ch, m.n1, pl);
-    B[2] = interp3(B3, ah, bh, c0, m.n1, pl);
-  } else {
-    E[0] = interp2(E1, ah, b0, m.n1);
-    E[1] = interp2(E2, a0, bh, m.n1);
-    E[2] = interp2(E3, a0, b0, m.n1);
-    B[0] = interp2(B1, a0, bh, m.n1);
-    B[1] = interp2(B2, ah, b0, m.n1);
-    B[2] = interp2(B3, ah, bh, m.n1);
-  }
+  gather6<T, NDIM>(E1, E2, E3, B1, B2, B3, m, x, E, B);
   if (PUSH == PIC_PUSH_BORIS)
     boris(u, E, B, qm, dt);
   else
     analytic(u, E, B, qm, dt);
-  const double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  const double ig = dt / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   if (o1) {
     o1[p] = x[0];
     o2[p] = x[1];
     if (NDIM == 3 && o3) o3[p] = x[2];
   }
-  x1[p] = wrap_pos(x[0] + dt * u[0] / g, m.L1);
-  x2[p] = wrap_pos(x[1] + dt * u[1] / g, m.L2);
-  if (NDIM == 3) x3[p] = wrap_pos(x[2] + dt * u[2] / g, m.L3);
+  x1[p] = wrap_pos(x[0] + ig * u[0], m.L1);
+  x2[p] = wrap_pos(x[1] + ig * u[1], m.L2);
+  if (NDIM == 3) x3[p] = wrap_pos(x[2] + ig * u[2], m.L3);
   u1[p] = u[0];
   u2[p] = u[1];
   u3[p] = u[2];
-}
-
-// ---------------------------------------------------------------------------
-// Esirkepov deposit, linear shape (Sec. 3.3).  Local 3-node stencils per
-// direction starting at min(floor(X0), floor(X1)); J_d is the running sum of
-// W_d along d times -q w dx_d/dt.
-// ---------------------------------------------------------------------------
-struct Shape3 {
-  int base;
-  double s0[3], ds[3];
-};
-
-__device__ __forceinline__ Shape3 shape3(double xo, double xn, double dx, double L) {
-  double d = xn - xo;  // minimum image
-  if (d > 0.5 * L) d -= L;
-  if (d < -0.5 * L) d += L;
-  const double X0 = xo / dx, X1 = (xo + d) / dx;
-  const double f0 = floor(X0), f1 = floor(X1);
-  const double b = fmin(f0, f1);
-  const double r0 = X0 - f0, r1 = X1 - f1;
-  int a0 = (int)(f0 - b), a1 = (int)(f1 - b);
-  a0 = a0 < 0 ? 0 : (a0 > 1 ? 1 : a0);
-  a1 = a1 < 0 ? 0 : (a1 > 1 ? 1 : a1);
-  Shape3 s;
-  double s1[3] = {0, 0, 0};
-  s.s0[0] = s.s0[1] = s.s0[2] = 0;
-  s.s0[a0] = 1.0 - r0;
-  s.s0[a0 + 1] = r0;
-  s1[a1] = 1.0 - r1;
-  s1[a1 + 1] = r1;
-  for (int q = 0; q < 3; ++q) s.ds[q] = s1[q] - s.s0[q];
-  s.base = (int)fmin(fmax(b, -2.0), 1e9);
-  return s;
-}
-
-__device__ __forceinline__ int wrapn(int i, int n) {
-  i %= n;
-  return i < 0 ? i + n : i;
-}
-
-template <typename T>
-__device__ __forceinline__ void atomic_add(T* p, double v) {
-  unsafeAtomicAdd(p, (T)v);
 }
 
 template <typename T, int NDIM>
@@ -325,12 +57,12 @@ __global__ __launch_bounds__(256) void deposit_kernel(T* __restrict__ J1, T* __r
                                                       double dt) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= np) return;
-  const Shape3 sx = shape3(xo1[p], x1[p], m.dx1, m.L1);
-  const Shape3 sy = shape3(xo2[p], x2[p], m.dx2, m.L2);
+  const Shape3 sx = shape3(xo1[p], x1[p], m.idx1, m.L1);
+  const Shape3 sy = shape3(xo2[p], x2[p], m.idx2, m.L2);
   const size_t pl = (size_t)m.n1 * m.n2;
   const double c1 = -qw * m.dx1 / dt, c2 = -qw * m.dx2 / dt;
   if (NDIM == 3) {
-    const Shape3 sz = shape3(xo3[p], x3[p], m.dx3, m.L3);
+    const Shape3 sz = shape3(xo3[p], x3[p], m.idx3, m.L3);
     const double c3 = -qw * m.dx3 / dt;
     int ia[3], jb[3], kc[3];
     for (int q = 0; q < 3; ++q) {
@@ -338,37 +70,10 @@ __global__ __launch_bounds__(256) void deposit_kernel(T* __restrict__ J1, T* __r
       jb[q] = wrapn(sy.base + q, m.n2);
       kc[q] = wrapn(sz.base + q, m.n3);
     }
-    // J1: running sum over a of W1[a][b][c]
-    for (int b = 0; b < 3; ++b)
-      for (int c = 0; c < 3; ++c) {
-        const double w = sy.s0[b] * sz.s0[c] + 0.5 * sy.ds[b] * sz.s0[c] + 0.5 * sy.s0[b] * sz.ds[c] +
-                         sy.ds[b] * sz.ds[c] / 3.0;
-        double run = 0;
-        for (int a = 0; a < 2; ++a) {
-          run += sx.ds[a] * w;
-          if (run != 0.0) atomic_add(&J1[(size_t)kc[c] * pl + (size_t)jb[b] * m.n1 + ia[a]], c1 * run);
-        }
-      }
-    for (int a = 0; a < 3; ++a)
-      for (int c = 0; c < 3; ++c) {
-        const double w = sx.s0[a] * sz.s0[c] + 0.5 * sx.ds[a] * sz.s0[c] + 0.5 * sx.s0[a] * sz.ds[c] +
-                         sx.ds[a] * sz.ds[c] / 3.0;
-        double run = 0;
-        for (int b = 0; b < 2; ++b) {
-          run += sy.ds[b] * w;
-          if (run != 0.0) atomic_add(&J2[(size_t)kc[c] * pl + (size_t)jb[b] * m.n1 + ia[a]], c2 * run);
-        }
-      }
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) {
-        const double w = sx.s0[a] * sy.s0[b] + 0.5 * sx.ds[a] * sy.s0[b] + 0.5 * sx.s0[a] * sy.ds[b] +
-                         sx.ds[a] * sy.ds[b] / 3.0;
-        double run = 0;
-        for (int c = 0; c < 2; ++c) {
-          run += sz.ds[c] * w;
-          if (run != 0.0) atomic_add(&J3[(size_t)kc[c] * pl + (size_t)jb[b] * m.n1 + ia[a]], c3 * run);
-        }
-      }
+    T* Jg[3] = {J1, J2, J3};
+    esirkepov3(sx, sy, sz, c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
+      atomic_add(&Jg[comp][(size_t)kc[c] * pl + (size_t)jb[b] * m.n1 + ia[a]], v);
+    });
   } else {
     int ia[3], jb[3];
     for (int q = 0; q < 3; ++q) {
@@ -397,7 +102,7 @@ __global__ __launch_bounds__(256) void deposit_kernel(T* __restrict__ J1, T* __r
       for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) {
           const double w = sx.s0[a] * sy.s0[b] + 0.5 * sx.ds[a] * sy.s0[b] + 0.5 * sx.s0[a] * sy.ds[b] +
-                           sx.ds[a] * sy.ds[b] / 3.0;
+                           sx.ds[a] * sy.ds[b] * (1.0 / 3.0);
           if (w != 0.0) atomic_add(&J3[(size_t)jb[b] * m.n1 + ia[a]], c3 * w);
         }
   }

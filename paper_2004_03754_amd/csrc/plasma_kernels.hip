@@ -1,0 +1,275 @@
+// Plasma step kernels (gfx950): particles sorted by spatial tile so that the
+// charge-conserving current (Sec. 3.3) is accumulated in LDS per tile.
+//
+//   tile_count   tile key of every particle, counts per tile (wave-aggregated)
+//   tile_scan    exclusive scan of the counts (one workgroup)
+//   tile_scatter counting-sort scatter of x, u (and ids) into scratch
+//   tile_push    per tile: gather + push + position update of its particles,
+//                Esirkepov current into an LDS tile, one atomic flush per node
+//
+// A tile is tx x ty x tz cells.  Particles stay sorted for S steps; since
+// |v| < c a particle drifts at most ceil((S-1) dt/dx_d) cells (the margin m_d)
+// out of its tile, so the LDS current tile spans t_d + 2 m_d + 3 nodes per
+// direction.  A particle found outside that span (only possible for invalid
+// input) deposits through global atomics instead.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "particle_common.h"
+
+namespace yeepic {
+namespace {
+
+using namespace pdev;
+
+__device__ __forceinline__ int cell_of(double x, double idx, int n) {
+  double f = floor(x * idx);
+  f = fmin(fmax(f, 0.0), (double)(n - 1));
+  return (int)f;
+}
+
+__device__ __forceinline__ int tile_key(const double* const* x, int64_t p, const Mesh& m, const TileGeom& tg) {
+  const int cx = cell_of(x[0][p], m.idx1, m.n1) / tg.t[0];
+  const int cy = cell_of(x[1][p], m.idx2, m.n2) / tg.t[1];
+  const int cz = cell_of(x[2][p], m.idx3, m.n3) / tg.t[2];
+  return (cz * tg.nt[1] + cy) * tg.nt[0] + cx;
+}
+
+// lanes with equal consecutive keys form runs; returns the run leader lane
+// of this lane and the run length (for leaders)
+__device__ __forceinline__ void key_runs(int key, int& leader_lane, int& runlen) {
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(key, 1);
+  const bool leader = lane == 0 || prev != key;
+  const unsigned long long lead = __ballot(leader);
+  const unsigned long long upto = lead & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
+  leader_lane = 63 - __clzll(upto);
+  const unsigned long long above = lane == 63 ? 0ull : (lead >> (lane + 1));
+  const int next = above ? lane + __ffsll((long long)above) : 64;
+  runlen = next - lane;
+}
+
+__global__ __launch_bounds__(256) void tile_count_kernel(const double* __restrict__ x1, const double* __restrict__ x2,
+                                                         const double* __restrict__ x3, int64_t np, Mesh m,
+                                                         TileGeom tg, int* __restrict__ keys,
+                                                         int* __restrict__ counts) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double* x[3] = {x1, x2, x3};
+  int key = -1;
+  if (p < np) {
+    key = tile_key(x, p, m, tg);
+    keys[p] = key;
+  }
+  int leader_lane, runlen;
+  key_runs(key, leader_lane, runlen);
+  if (leader_lane == (int)(threadIdx.x & 63) && key >= 0) atomicAdd(&counts[key], runlen);
+}
+
+// exclusive scan of n counts by one workgroup of 1024 threads; also clears
+// the scatter cursors and writes offsets[n] = total
+__global__ __launch_bounds__(1024) void tile_scan_kernel(const int* __restrict__ counts, int* __restrict__ offsets,
+                                                         int* __restrict__ cursors, int n) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int chunk = (n + 1023) / 1024;
+  const int lo = t * chunk, hi = min(n, lo + chunk);
+  int sum = 0;
+  for (int i = lo; i < hi; ++i) sum += counts[i];
+  part[t] = sum;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
+    const int v = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - sum;
+  for (int i = lo; i < hi; ++i) {
+    offsets[i] = run;
+    run += counts[i];
+    cursors[i] = 0;
+  }
+  if (t == 1023) offsets[n] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void tile_scatter_kernel(const double* __restrict__ x1, const double* __restrict__ x2,
+                                                           const double* __restrict__ x3, const double* __restrict__ u1,
+                                                           const double* __restrict__ u2, const double* __restrict__ u3,
+                                                           const int64_t* __restrict__ id, const int* __restrict__ keys,
+                                                           const int* __restrict__ offsets, int* __restrict__ cursors,
+                                                           int64_t np, double* __restrict__ sx1, double* __restrict__ sx2,
+                                                           double* __restrict__ sx3, double* __restrict__ su1,
+                                                           double* __restrict__ su2, double* __restrict__ su3,
+                                                           int64_t* __restrict__ sid) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int key = p < np ? keys[p] : -1;
+  int leader_lane, runlen;
+  key_runs(key, leader_lane, runlen);
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+  if (leader_lane == lane && key >= 0) base = atomicAdd(&cursors[key], runlen);
+  base = __shfl(base, leader_lane);
+  if (p >= np) return;
+  const int64_t q = (int64_t)offsets[key] + base + (lane - leader_lane);
+  sx1[q] = x1[p];
+  sx2[q] = x2[p];
+  sx3[q] = x3[p];
+  su1[q] = u1[p];
+  su2[q] = u2[p];
+  su3[q] = u3[p];
+  if (id) sid[q] = id[p];
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_add(T* p, double v) {
+  atomicAdd(p, (T)v);
+}
+
+template <typename T, int PUSH>
+__global__ __launch_bounds__(256) void tile_push_kernel(
+    const T* __restrict__ E1, const T* __restrict__ E2, const T* __restrict__ E3, const T* __restrict__ B1,
+    const T* __restrict__ B2, const T* __restrict__ B3, T* __restrict__ J1, T* __restrict__ J2, T* __restrict__ J3,
+    Mesh m, TileGeom tg, const int* __restrict__ offsets, const double* sx1, const double* sx2, const double* sx3,
+    const double* su1, const double* su2, const double* su3, const int64_t* sid, double* dx1, double* dx2,
+    double* dx3, double* du1, double* du2, double* du3, int64_t* did, double qm, double qw, double dt) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* jl = reinterpret_cast<T*>(lds_raw);  // current tile, 3 x r0 r1 r2
+  const int r0 = tg.r[0], r1 = tg.r[1], r2 = tg.r[2];
+  const int R = r0 * r1 * r2;
+  const int tile = blockIdx.x;
+  const int beg = offsets[tile], end = offsets[tile + 1];
+  if (end == beg) return;  // uniform: no particles, nothing to add
+  const int tx = tile % tg.nt[0], ty = (tile / tg.nt[0]) % tg.nt[1], tz = tile / (tg.nt[0] * tg.nt[1]);
+  const int lo[3] = {tx * tg.t[0], ty * tg.t[1], tz * tg.t[2]};
+  const int n[3] = {m.n1, m.n2, m.n3};
+  const size_t pl = (size_t)m.n1 * m.n2;
+  for (int i = threadIdx.x; i < 3 * R; i += blockDim.x) jl[i] = 0;
+  __syncthreads();
+  const double c1 = -qw * m.dx1 / dt, c2 = -qw * m.dx2 / dt, c3 = -qw * m.dx3 / dt;
+  T* Jg[3] = {J1, J2, J3};
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    const double x[3] = {sx1[i], sx2[i], sx3[i]};
+    double u[3] = {su1[i], su2[i], su3[i]};
+    double E[3], B[3];
+    gather6<T, 3>(E1, E2, E3, B1, B2, B3, m, x, E, B);
+    if (PUSH == PIC_PUSH_BORIS)
+      boris(u, E, B, qm, dt);
+    else
+      analytic(u, E, B, qm, dt);
+    const double ig = dt / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const double xn[3] = {wrap_pos(x[0] + ig * u[0], m.L1), wrap_pos(x[1] + ig * u[1], m.L2),
+                          wrap_pos(x[2] + ig * u[2], m.L3)};
+    dx1[i] = xn[0];
+    dx2[i] = xn[1];
+    dx3[i] = xn[2];
+    du1[i] = u[0];
+    du2[i] = u[1];
+    du3[i] = u[2];
+    if (sid && sid != did) did[i] = sid[i];
+    const Shape3 sh[3] = {shape3(x[0], xn[0], m.idx1, m.L1), shape3(x[1], xn[1], m.idx2, m.L2),
+                          shape3(x[2], xn[2], m.idx3, m.L3)};
+    // stencil origin relative to the LDS current tile (periodic images folded in)
+    int rel[3];
+    bool inside = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int bb = sh[d].base - lo[d];
+      if (bb < -(n[d] / 2)) bb += n[d];
+      if (bb > n[d] / 2) bb -= n[d];
+      rel[d] = bb + tg.m[d] + 1;
+      inside = inside && rel[d] >= 0 && rel[d] + 2 < tg.r[d];
+    }
+    if (inside) {
+      const int o = (rel[2] * r1 + rel[1]) * r0 + rel[0];
+      esirkepov3(sh[0], sh[1], sh[2], c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
+        lds_add(&jl[comp * R + o + (c * r1 + b) * r0 + a], v);
+      });
+    } else {
+      esirkepov3(sh[0], sh[1], sh[2], c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
+        const size_t gidx = (size_t)wrapn(sh[2].base + c, m.n3) * pl + (size_t)wrapn(sh[1].base + b, m.n2) * m.n1 +
+                            wrapn(sh[0].base + a, m.n1);
+        atomic_add(&Jg[comp][gidx], v);
+      });
+    }
+  }
+  __syncthreads();
+  // flush: one global atomic per non-zero LDS node
+  for (int i = threadIdx.x; i < 3 * R; i += blockDim.x) {
+    const T v = jl[i];
+    if (v == (T)0) continue;
+    const int comp = i / R;
+    const int q = i - comp * R;
+    const int a = q % r0, b = (q / r0) % r1, c = q / (r0 * r1);
+    const int gx = wrapn(lo[0] + a - tg.m[0] - 1, m.n1);
+    const int gy = wrapn(lo[1] + b - tg.m[1] - 1, m.n2);
+    const int gz = wrapn(lo[2] + c - tg.m[2] - 1, m.n3);
+    unsafeAtomicAdd(&Jg[comp][(size_t)gz * pl + (size_t)gy * m.n1 + gx], v);
+  }
+}
+
+template <typename T>
+int run_tile_push(const Mesh& m, const TileGeom& tg, void* const E[3], void* const B[3], void* const J[3],
+                  const int* offsets, const pic_particles& src, const pic_particles& dst, int pusher, double dt,
+                  hipStream_t s) {
+  const size_t lds = sizeof(T) * 3 * (size_t)tg.r[0] * tg.r[1] * tg.r[2];
+  if (lds > 160 * 1024) return set_error(PIC_EUNSUPPORTED, "plasma tile needs %zu bytes of LDS", lds);
+  auto k = pusher == PIC_PUSH_BORIS ? tile_push_kernel<T, PIC_PUSH_BORIS> : tile_push_kernel<T, PIC_PUSH_ANALYTIC>;
+  if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return set_error(PIC_EHIP, "tile push: cannot reserve %zu bytes of LDS", lds);
+  const double qm = src.q / src.m, qw = src.q * src.w;
+#define YP_TP(PUSH)                                                                                               \
+  hipLaunchKernelGGL((tile_push_kernel<T, PUSH>), dim3(tg.ntiles), dim3(256), lds, s, (const T*)E[0],          \
+                     (const T*)E[1], (const T*)E[2], (const T*)B[0], (const T*)B[1], (const T*)B[2], (T*)J[0],  \
+                     (T*)J[1], (T*)J[2], m, tg, offsets, src.x[0], src.x[1], src.x[2], src.u[0], src.u[1],     \
+                     src.u[2], src.id, dst.x[0], dst.x[1], dst.x[2], dst.u[0], dst.u[1], dst.u[2], dst.id, qm, qw, \
+                     dt)
+  if (pusher == PIC_PUSH_BORIS) YP_TP(PIC_PUSH_BORIS); else YP_TP(PIC_PUSH_ANALYTIC);
+#undef YP_TP
+  return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "tile push launch failed");
+}
+
+}  // namespace
+
+TileGeom make_tile_geom(const Mesh& m, double dt, int sort_every) {
+  TileGeom tg;
+  const int n[3] = {m.n1, m.n2, m.n3};
+  const double dx[3] = {m.dx1, m.dx2, m.dx3};
+  tg.ntiles = 1;
+  for (int d = 0; d < 3; ++d) {
+    tg.t[d] = n[d] < 8 ? n[d] : 8;
+    tg.nt[d] = (n[d] + tg.t[d] - 1) / tg.t[d];
+    // |v| < 1: at most (S-1) dt/dx cells of drift before the next sort
+    tg.m[d] = (int)std::ceil((sort_every - 1) * dt / dx[d] - 1e-12);
+    if (tg.m[d] < 0) tg.m[d] = 0;
+    tg.r[d] = tg.t[d] + 2 * tg.m[d] + 3;
+    tg.ntiles *= tg.nt[d];
+  }
+  return tg;
+}
+
+int launch_tile_sort(const Mesh& m, const TileGeom& tg, const pic_particles& p, const pic_particles& scratch,
+                     int* keys, int* counts, int* offsets, int* cursors, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (p.np == 0) return PIC_OK;
+  if (hipMemsetAsync(counts, 0, sizeof(int) * tg.ntiles, s) != hipSuccess)
+    return set_error(PIC_EHIP, "tile sort: clear counts");
+  const dim3 grid((unsigned)((p.np + 255) / 256));
+  hipLaunchKernelGGL(tile_count_kernel, grid, dim3(256), 0, s, p.x[0], p.x[1], p.x[2], p.np, m, tg, keys, counts);
+  hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, counts, offsets, cursors, tg.ntiles);
+  hipLaunchKernelGGL(tile_scatter_kernel, grid, dim3(256), 0, s, p.x[0], p.x[1], p.x[2], p.u[0], p.u[1], p.u[2],
+                     p.id, keys, offsets, cursors, p.np, scratch.x[0], scratch.x[1], scratch.x[2], scratch.u[0],
+                     scratch.u[1], scratch.u[2], scratch.id);
+  return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "tile sort launch failed");
+}
+
+int launch_tile_push(int prec, const Mesh& m, const TileGeom& tg, void* const E[3], void* const B[3],
+                     void* const J[3], const int* offsets, const pic_particles& src, const pic_particles& dst,
+                     int pusher, double dt, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (src.np == 0) return PIC_OK;
+  return prec == PIC_FP64 ? run_tile_push<double>(m, tg, E, B, J, offsets, src, dst, pusher, dt, s)
+                          : run_tile_push<float>(m, tg, E, B, J, offsets, src, dst, pusher, dt, s);
+}
+
+}  // namespace yeepic

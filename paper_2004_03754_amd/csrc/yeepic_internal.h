@@ -20,6 +20,7 @@ struct Mesh {
   int n1, n2, n3;
   int ndim;
   double dx1, dx2, dx3;
+  double idx1, idx2, idx3;  // 1/dx: positions become cell coordinates by a multiply
   double L1, L2, L3;
 };
 
@@ -47,6 +48,21 @@ int launch_gather_push(int prec, const Mesh& m, void* const E[3], void* const B[
                        void* stream);
 int launch_deposit(int prec, const Mesh& m, void* const J[3], const pic_particles& p,
                    double* const x_old[3], double dt, void* stream);
+// Spatial tiles of the sorted plasma path (plasma_kernels.hip).
+struct TileGeom {
+  int t[3];   // tile size in cells
+  int nt[3];  // tiles per direction
+  int m[3];   // drift margin in cells
+  int r[3];   // nodes of the on-chip current tile per direction
+  int ntiles;
+};
+TileGeom make_tile_geom(const Mesh& m, double dt, int sort_every);
+int launch_tile_sort(const Mesh& m, const TileGeom& tg, const pic_particles& p, const pic_particles& scratch,
+                     int* keys, int* counts, int* offsets, int* cursors, void* stream);
+int launch_tile_push(int prec, const Mesh& m, const TileGeom& tg, void* const E[3], void* const B[3],
+                     void* const J[3], const int* offsets, const pic_particles& src, const pic_particles& dst,
+                     int pusher, double dt, void* stream);
+
 int launch_check(int prec, const Mesh& m, void* const E[3], void* const B[3],
                  const pic_particles* p, int* d_flag, void* stream);
 

@@ -14,32 +14,74 @@ from gpu_util import assert_fields_close, dev, host  # noqa: E402
 DX = (wl.DX1, wl.DX2, wl.DX3)
 
 
+def _by_id(t, ids):
+    """Columns of a (3, np) device tensor ordered by particle id."""
+    order = np.argsort(host(ids).astype(np.int64))
+    return host(t)[:, order]
+
+
 @pytest.mark.parametrize("pusher", ["boris", "analytic"])
-@pytest.mark.parametrize("nsteps", [1, 4])
-def test_step_n_plasma_fp64(pusher, nsteps, coeffs16):
+@pytest.mark.parametrize("nsteps", [1, 4, 9])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_step_n_plasma(pusher, nsteps, prec, coeffs16):
     """Config-3 physics at a small size: laser + thermal plasma, push,
-    Esirkepov deposit and fused sweep per step (Sec. 3.3 ordering)."""
+    Esirkepov deposit and fused sweep per step (Sec. 3.3 ordering).  The GPU
+    sorts the particles by tile (re-sorting every 4 steps, so 9 steps cross
+    two re-sorts); they are matched to the oracle's through their ids.  FP64
+    to 1e-11; FP32 fields to 1e-5 (fields) with FP64 particles (momenta
+    1e-6: FP32 field values differ from the oracle's FP64 ones)."""
     CE, CB = coeffs16
-    n = (128, 8, 6)
+    n = (128, 16, 12)
     L = [n[d] * DX[d] for d in range(3)]
     pulse = wl.Sin2Pulse(a0=2.0, Lp=4 * wl.LAMBDA0, period=L[0])
     E, B = wl.laser_fields(n, DX, pulse, x_head=3 * wl.LAMBDA0, w0=2 * wl.LAMBDA0)
     x, u = wl.lattice_particles(n, DX, 1, seed=3, u_th=0.05)
+    # a few particles right at tile faces and the periodic seam
+    x[0, :4] = [0.0, L[0] - 1e-12, 8 * DX[0], 8 * DX[0] - 1e-13]
     w = 0.01
-    grid = b.Grid([dev(e) for e in E], [dev(v) for v in B], DX, wl.DT, CE, CB,
-                  J=[dev(np.zeros_like(e)) for e in E])
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    grid = b.Grid([dev(e, dtype) for e in E], [dev(v, dtype) for v in B], DX, wl.DT, CE, CB,
+                  J=[dev(np.zeros_like(e), dtype) for e in E], prec=prec)
     xd, ud = dev(x), dev(u)
-    p = b.Particles(xd, ud, q=-1.0, m=1.0, w=w)
+    ids = torch.arange(x.shape[1], device="cuda:0", dtype=torch.int64)
+    p = b.Particles(xd, ud, q=-1.0, m=1.0, w=w, id=ids)
     grid.step_n([p], nsteps, pusher=pusher, deposit=True)
     grid.sync()
+    if prec == "fp32":
+        E = [e.astype(np.float32).astype(np.float64) for e in E]
+        B = [v.astype(np.float32).astype(np.float64) for v in B]
     sp = {"x": x.copy(), "u": u.copy(), "q": -1.0, "m": 1.0, "w": w}
     Er, Br = pic.run(E, B, [sp], CE, CB, DX, wl.DT, nsteps, pusher=pusher, deposit=True)
-    assert_fields_close(grid.E, Er, 1e-11, "step_n E")
-    assert_fields_close(grid.B, Br, 1e-11, "step_n B")
-    assert np.max(np.abs(host(ud) - sp["u"]) / np.maximum(1, np.abs(sp["u"]))) < 1e-11
-    d = host(xd) - sp["x"]
+    ftol, ptol = (1e-11, 1e-11) if prec == "fp64" else (1e-5, 1e-6)
+    assert_fields_close(grid.E, Er, ftol, "step_n E", joint=prec == "fp32")
+    assert_fields_close(grid.B, Br, ftol, "step_n B", joint=prec == "fp32")
+    assert sorted(host(ids).astype(np.int64).tolist()) == list(range(x.shape[1]))
+    ug, xg = _by_id(ud, ids), _by_id(xd, ids)
+    assert np.max(np.abs(ug - sp["u"]) / np.maximum(1, np.abs(sp["u"]))) < ptol
+    d = xg - sp["x"]
     Lb = np.asarray(L)[:, None]
-    assert np.max(np.abs((d + Lb / 2) % Lb - Lb / 2)) < 1e-11
+    assert np.max(np.abs((d + Lb / 2) % Lb - Lb / 2)) < ptol
+    grid.close()
+
+
+@pytest.mark.parametrize("interval", [1, 3])
+def test_sort_interval(interval, coeffs16):
+    """Other re-sort intervals (larger on-chip current tiles) give the same
+    fields as the oracle."""
+    CE, CB = coeffs16
+    n = (64, 16, 16)
+    E, B = wl.random_fields(n, seed=21, scale=0.2)
+    x, u = wl.lattice_particles(n, DX, 1, seed=4, u_th=0.3)
+    grid = b.Grid([dev(e) for e in E], [dev(v) for v in B], DX, wl.DT, CE, CB,
+                  J=[dev(np.zeros_like(e)) for e in E])
+    grid.set_sort_interval(interval)
+    p = b.Particles(dev(x), dev(u), q=-1.0, m=1.0, w=0.02)
+    grid.step_n([p], 5, pusher="boris", deposit=True)
+    grid.sync()
+    sp = {"x": x.copy(), "u": u.copy(), "q": -1.0, "m": 1.0, "w": 0.02}
+    Er, Br = pic.run(E, B, [sp], CE, CB, DX, wl.DT, 5, pusher="boris", deposit=True)
+    assert_fields_close(grid.E, Er, 1e-11, "E")
+    assert_fields_close(grid.B, Br, 1e-11, "B")
     grid.close()
 
 
