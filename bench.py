@@ -241,7 +241,7 @@ def cpu_baseline_child():
     x, u = wl.uniform_particles(npart, lo, hi, seed=2)
     sp = {"x": x, "u": u, "q": -1.0, "m": 1.0, "w": 1.0}
     E, B = pic.step(E, B, [sp], CE, CB, dx, wl.DT, pusher="analytic")  # warm-up
-    steps = 8
+    steps = 48
     t = time.perf_counter()
     for _ in range(steps):
         E, B = pic.step(E, B, [sp], CE, CB, dx, wl.DT, pusher="analytic")
@@ -266,6 +266,20 @@ def cpu_baseline():
                       f"{d['steps']} steps after 1 warm-up, {d['seconds']:.1f} s, NumPy FP64 single thread"}
 
 
+def copy_calibration(nbytes=1 << 29, reps=3):
+    """A plain device-to-device copy of ``nbytes`` (reads nbytes, writes
+    nbytes), repeated ``reps`` times: the known traffic against which the HBM
+    byte counters of a profiler run are scaled."""
+    import torch
+
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,9 +288,14 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-baseline-child", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args()
     if args.cpu_baseline_child:
         cpu_baseline_child()
+        return
+    if args.copy_calibration:
+        copy_calibration()
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
