@@ -129,7 +129,8 @@ def advance_position(x, u, dt, L, ndim):
     for d in range(ndim):
         v = x[d] + dt * u[d] / g
         vd = v.detach()
-        shift = torch.where(vd < 0, -L[d], torch.where(vd >= L[d], L[d], 0.0)).to(v.dtype)
+        Ld = torch.tensor(L[d], dtype=v.dtype)
+        shift = torch.where(vd < 0, -Ld, torch.where(vd >= Ld, Ld, torch.zeros_like(Ld)))
         v = v - shift
         v = torch.where((vd < 0) & (v.detach() >= L[d]), v - v.detach(), v)
         rows.append(v)

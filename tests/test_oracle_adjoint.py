@@ -31,13 +31,21 @@ def _case(n, seed, npart, ndim, scale=0.3, u_th=0.2):
 @pytest.mark.parametrize("ndim,n", [(3, (20, 6, 5)), (2, (32, 8, 1))])
 def test_torch_forward_matches_numpy_oracle(ndim, n, coeffs16):
     """The torch restatement reproduces the NumPy oracle's step (fields,
-    positions and momenta) to roundoff, Boris pusher, 3 steps."""
+    positions and momenta) to roundoff, Boris pusher, 10 steps, with
+    electrons crossing the periodic seam of every direction both ways (the
+    wrap must be exact in FP64)."""
     CE, CB = coeffs16
-    E, B, x, u = _case(n, 71, 50, ndim)
+    E, B, x, u = _case(n, 71, 50, ndim, u_th=0.5)
+    L = [n[d] * DX[d] for d in range(3)]
+    for d in range(ndim):
+        x[d, 2 * d] = L[d] - 1e-3 * DX[d]
+        u[d, 2 * d] = 2.0
+        x[d, 2 * d + 1] = 1e-3 * DX[d]
+        u[d, 2 * d + 1] = -2.0
     sp = {"x": x.copy(), "u": u.copy(), "q": -1.0, "m": 1.0, "w": 1.0}
-    Er, Br = pic.run(E, B, [sp], CE, CB, DX, wl.DT, 3, pusher="boris", ndim=ndim)
+    Er, Br = pic.run(E, B, [sp], CE, CB, DX, wl.DT, 10, pusher="boris", ndim=ndim)
     Et, Bt, xt, ut = ad.run([_t(e) for e in E], [_t(b) for b in B], _t(x), _t(u), _t(CE), _t(CB), DX, wl.DT,
-                            -1.0, 3, ndim)
+                            -1.0, 10, ndim)
     for a, r in zip(list(Et) + list(Bt), list(Er) + list(Br)):
         assert np.max(np.abs(a.numpy() - r)) <= 1e-13 * max(1.0, np.max(np.abs(r)))
     assert np.max(np.abs(xt.numpy() - sp["x"])) < 1e-12
