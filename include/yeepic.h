@@ -12,7 +12,10 @@
  *   Index (k, j, i) holds the component at its own staggered location:
  *     E1 (i+1/2, j, k)  E2 (i, j+1/2, k)  E3 (i, j, k+1/2)
  *     B1 (i, j+1/2, k+1/2)  B2 (i+1/2, j, k+1/2)  B3 (i+1/2, j+1/2, k)
- *   J has the E staggering.  A 2D mesh is ndim = 2 with n3 = 1.
+ *   J has the E staggering.  A 2D mesh is ndim = 2 (no x3 derivatives).
+ *   With n3 > 1 a 2D grid is a stack of n3 independent 2D meshes (a batch):
+ *   plane k holds one mesh, and a particle belongs to the plane floor(x3)
+ *   (its x3 holds the plane index, clamped into [0, n3); dx3 is 1 in 2D).
  * Time levels: between calls E^n and B^n are both at integer time t^n
  *   (Eq. pusher: the magnetic field seen by the particles is the average of
  *   the two half-step values, which the half-step B update produces).
@@ -59,7 +62,7 @@ typedef enum { PIC_TARGET_E = 0, PIC_TARGET_B = 1, PIC_TARGET_XU = 2 } pic_targe
 
 typedef struct pic_grid_desc {
   int ndim;            /* 2 or 3 */
-  int64_t n[3];        /* cells n1, n2, n3; n3 must be 1 when ndim == 2 */
+  int64_t n[3];        /* cells n1, n2, n3; in 2D n3 is the number of stacked planes */
   double dx[3];        /* cell sizes; dx[2] unused when ndim == 2 */
   double dt;           /* time step */
   int M;               /* number of x1 coefficients, 1..PIC_MAX_M */
@@ -74,7 +77,8 @@ typedef struct pic_grid_desc {
 
 typedef struct pic_particles {
   int64_t np;          /* number of particles (0 allowed) */
-  double *x[3];        /* device positions in [0, n_d dx_d); x[2] may be NULL in 2D */
+  double *x[3];        /* device positions in [0, n_d dx_d); in 2D x[2] is the plane
+                          index (may be NULL when n3 == 1) */
   double *u[3];        /* device momenta gamma*beta (per unit mass) */
   double q, m, w;      /* charge, mass, macro-weight (density per particle) */
   int64_t *id;         /* optional device labels (may be NULL), permuted together
@@ -82,6 +86,14 @@ typedef struct pic_particles {
 } pic_particles;
 
 typedef struct pic_grid pic_grid;   /* opaque */
+
+/* Cotangents for pic_adjoint_step (FP64 grids). */
+typedef struct pic_adjoint {
+  void *lE[3];         /* device, caller-owned, layout of E: dL/dE (in: at t^{n+1}, out: at t^n) */
+  void *lB[3];         /* device, caller-owned, layout of B: dL/dB (same) */
+  double *gCE;         /* device, PIC_MAX_M doubles: dL/dC^E_j, accumulated (+=) for j < M */
+  double *gCB;         /* device, PIC_MAX_M doubles: dL/dC^B_j, accumulated (+=) for j < M */
+} pic_adjoint;
 
 /* ---- coefficient design (host only; App. B) ------------------------------
  * Customized x1 coefficients C (length M) fitting the Eq. (new_op) target
@@ -161,6 +173,29 @@ int pic_step_n(pic_grid *g, pic_particles *const *species, int nspecies, int nst
 /* Steps between particle re-sorts in pic_step_n (1..64, default 4); the
  * on-chip current tile grows with the interval (|v| < c bounds the drift). */
 int pic_set_sort_interval(pic_grid *g, int steps);
+
+/* ---- adjoint of one vacuum step ---------------------------------------------
+ * Reverse mode of one step of pic_step_n without deposit and with the Boris
+ * pusher: gather (App. A) + push (Sec. 1) + position update (Sec. 4.1) of
+ * each species, then the field sweep of Eq. maxwell with the App. B
+ * operators.  The forward state at t^n is read, not modified: the grid's
+ * fields E^n, B^n and species[s] (x^n, u^{n-1/2}).  lambda[s] has the same
+ * np; its x and u arrays hold dL/dx^{n+1}, dL/du^{n+1/2} on entry and
+ * dL/dx^n, dL/du^{n-1/2} on exit (its q, m, w, id are ignored; in 2D
+ * x[2] is left alone, the plane index having no derivative).  adj->lE, lB
+ * map dL/d(E,B)^{n+1} to dL/d(E,B)^n, and dL/dC^E_j and dL/dC^B_j (every
+ * j < M, also where C_j = 0) are added to adj->gCE, gCB.
+ * The field part uses the transposition of the App. B operators
+ * (curl_E[C]^T = curl_B[C]) and recomputes E^{n+1} and B^{n+1/2} in the
+ * grid's second field set.  The position wrap is a constant shift (derivative
+ * the identity); at a cell face the shape function has a kink, and the
+ * derivative taken is the one of the cell the particle is in.
+ * PIC_EUNSUPPORTED for FP32-field grids and the analytic pusher; the
+ * coefficient reduction allocates a scratch of 16 doubles per 256 cells of
+ * x1 row at the first call (PIC_ENOMEM if that fails).  Scatter into lE, lB
+ * uses atomics, so the field cotangents vary in the last bits between runs. */
+int pic_adjoint_step(pic_grid *g, const pic_adjoint *adj, const pic_particles *const *species,
+                     pic_particles *const *lambda, int nspecies, int pusher);
 
 /* ---- diagnostics ------------------------------------------------------------
  * Waits for the grid's stream and reports a pending HIP error. */

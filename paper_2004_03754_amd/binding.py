@@ -16,6 +16,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libyeepic.
 _lib = None
 
 PIC_FP64, PIC_FP32_FIELDS = 0, 1
+PIC_MAX_M = 16
 PIC_PUSH_BORIS, PIC_PUSH_ANALYTIC = 0, 1
 PIC_TARGET_E, PIC_TARGET_B, PIC_TARGET_XU = 0, 1, 2
 STATUS = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ECFL", -3: "PIC_EHIP", -4: "PIC_ESHAPE",
@@ -43,9 +44,14 @@ class _Particles(ctypes.Structure):
                 ("id", ctypes.c_void_p)]
 
 
+class _Adjoint(ctypes.Structure):
+    _fields_ = [("lE", ctypes.c_void_p * 3), ("lB", ctypes.c_void_p * 3), ("gCE", ctypes.c_void_p),
+                ("gCB", ctypes.c_void_p)]
+
+
 EXPORTS = ["pic_design_coeffs", "pic_init_grid", "pic_set_fields", "pic_advance_B_half", "pic_advance_E",
            "pic_field_sweep", "pic_gather_push", "pic_deposit_J", "pic_step_n", "pic_sync", "pic_check",
-           "pic_grid_widths", "pic_destroy", "pic_last_error", "pic_set_sort_interval"]
+           "pic_grid_widths", "pic_destroy", "pic_last_error", "pic_set_sort_interval", "pic_adjoint_step"]
 
 
 def lib():
@@ -67,6 +73,8 @@ def lib():
         L.pic_deposit_J.argtypes = [vp, ctypes.POINTER(_Particles), vp, i]
         L.pic_step_n.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(_Particles)), i, i, i, i]
         L.pic_set_sort_interval.argtypes = [vp, i]
+        PP = ctypes.POINTER(ctypes.POINTER(_Particles))
+        L.pic_adjoint_step.argtypes = [vp, ctypes.POINTER(_Adjoint), PP, PP, i, i]
         L.pic_sync.argtypes = [vp]
         L.pic_check.argtypes = [vp, ctypes.POINTER(_Particles)]
         L.pic_grid_widths.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
@@ -169,6 +177,28 @@ class Grid:
             self.close()
         except Exception:
             pass
+
+    def set_fields(self, E, B, J=None):
+        """Point the grid at other field arrays of the same shape and precision."""
+        self.E, self.B, self.J = list(E), list(B), (list(J) if J is not None else None)
+        _check(lib().pic_set_fields(self._h, _ptr3(E), _ptr3(B), _ptr3(J)))
+
+    def adjoint_step(self, lE, lB, gCE, gCB, species=(), lambdas=(), pusher="boris"):
+        """Reverse of one vacuum step from the grid's current state (see
+        pic_adjoint_step): lE, lB (FP64, field layout) and the particle
+        cotangents in ``lambdas`` are mapped from t^{n+1} to t^n in place;
+        gCE, gCB (16 doubles on the device) are accumulated."""
+        adj = _Adjoint()
+        adj.lE, adj.lB = _ptr3(lE), _ptr3(lB)
+        adj.gCE, adj.gCB = gCE.data_ptr(), gCB.data_ptr()
+        ns = len(species)
+        assert len(lambdas) == ns
+        a = (ctypes.POINTER(_Particles) * max(1, ns))()
+        b = (ctypes.POINTER(_Particles) * max(1, ns))()
+        for s_, (p, lam) in enumerate(zip(species, lambdas)):
+            a[s_] = ctypes.pointer(p._s)
+            b[s_] = ctypes.pointer(lam._s)
+        _check(lib().pic_adjoint_step(self._h, ctypes.byref(adj), a, b, ns, PUSHERS[pusher]))
 
     def widths(self):
         a, b = ctypes.c_int(), ctypes.c_int()

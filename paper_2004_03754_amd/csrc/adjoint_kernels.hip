@@ -1,0 +1,301 @@
+// Adjoint (reverse-mode) kernels of one vacuum step (gfx950, FP64).
+//
+// Field step.  With the App. B operators, the transpose of the Faraday x1
+// operator with coefficients C is minus the Ampere operator with the same C,
+// and the transpose of a Yee forward difference is minus the backward one.
+// Hence curl_E[C]^T = curl_B[C] and curl_B[C]^T = curl_E[C], and the reverse
+// of  B' = B - dt/2 curl_E[C^E] E,  E' = E + dt curl_B[C^B] B',
+//     B'' = B' - dt/2 curl_E[C^E] E'  is, on cotangents (lE, lB),
+//   lE += -dt/2 curl_B[C^E] lB ;  lB += dt curl_E[C^B] lE ;
+//   lE += -dt/2 curl_B[C^E] lB,
+// three single-stage launches of the forward kernels with the coefficient
+// roles swapped (api.hip).  This file holds the rest:
+//
+// * dL/dC_j.  C_j enters the x1 derivative through the differences
+//   f_{i+j} - f_{i-j+1} (Faraday) or f_{i+j-1} - f_{i-j} (Ampere), so each
+//   stage contributes a sum over cells of (cotangent of the stage output) x
+//   (difference of the stage input): coef_partial + coef_finalize, a
+//   deterministic two-pass reduction (per-block partial sums, then one block
+//   per coefficient).
+// * the particle adjoint: reverse of gather (App. A), Boris push (Sec. 1) and
+//   the position update (Sec. 4.1).  The gather's reverse scatters the
+//   cotangent of each interpolated field value into the field cotangent with
+//   the same linear-shape weights, and adds the weights' x derivative to the
+//   position cotangent.
+#include <hip/hip_runtime.h>
+
+#include "particle_common.h"
+
+namespace yeepic {
+namespace {
+
+using namespace pdev;
+
+constexpr int kLags = PIC_MAX_M;  // every coefficient of the vector gets a gradient
+constexpr int kRow = 256;         // cells of x1 per block of the coefficient reduction
+
+// Partial sums  acc_j = sum_i la_i D_j(fa)_i - lb_i D_j(fb)_i  over kRow cells
+// of one x1 row, for j = 1..kLags;  D_j f_i = f_{i+j} - f_{i-j+1} (FORM 0,
+// Faraday) or f_{i+j-1} - f_{i-j} (FORM 1, Ampere).  Block b covers row
+// b / nbx, cells [(b % nbx) kRow, +kRow).
+template <int FORM>
+__global__ __launch_bounds__(kRow) void coef_partial_kernel(const double* __restrict__ la,
+                                                            const double* __restrict__ fa,
+                                                            const double* __restrict__ lb,
+                                                            const double* __restrict__ fb, int n1, int nbx,
+                                                            double* __restrict__ partial) {
+  __shared__ double sa[kRow + 2 * kLags], sb[kRow + 2 * kLags];
+  __shared__ double red[kRow / 64][kLags];
+  const int rowi = blockIdx.x / nbx;
+  const int i0 = (blockIdx.x % nbx) * kRow;
+  const size_t row = (size_t)rowi * n1;
+  for (int t = threadIdx.x; t < kRow + 2 * kLags; t += kRow) {
+    int i = (i0 - kLags + t) % n1;
+    i += (i < 0) ? n1 : 0;
+    sa[t] = fa[row + i];
+    sb[t] = fb[row + i];
+  }
+  __syncthreads();
+  double acc[kLags];
+  const int i = i0 + (int)threadIdx.x;
+  const double a = (i < n1) ? la[row + i] : 0.0;
+  const double b = (i < n1) ? lb[row + i] : 0.0;
+  const int c = threadIdx.x + kLags;  // LDS slot of cell i
+#pragma unroll
+  for (int j = 1; j <= kLags; ++j) {
+    const int hi = FORM == 0 ? c + j : c + j - 1;
+    const int lo = FORM == 0 ? c - j + 1 : c - j;
+    acc[j - 1] = a * (sa[hi] - sa[lo]) - b * (sb[hi] - sb[lo]);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < kLags; ++j) {
+    double v = acc[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[wave][j] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kLags) {
+    double s = 0;
+#pragma unroll
+    for (int w = 0; w < kRow / 64; ++w) s += red[w][threadIdx.x];
+    partial[(size_t)blockIdx.x * kLags + threadIdx.x] = s;
+  }
+}
+
+// g[j] += scale * sum_b partial[b][j] for j < M; one block per coefficient.
+__global__ __launch_bounds__(256) void coef_finalize_kernel(const double* __restrict__ partial, int nblocks,
+                                                            double scale, double* __restrict__ g) {
+  __shared__ double red[4];
+  const int j = blockIdx.x;
+  double s = 0;
+  for (int b = threadIdx.x; b < nblocks; b += 256) s += partial[(size_t)b * kLags + j];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) g[j] += scale * (((red[0] + red[1]) + red[2]) + red[3]);
+}
+
+// Reverse of boris(): u is the input momentum, lun the cotangent of the
+// output momentum; returns the cotangents of u, E and B.
+__device__ __forceinline__ void boris_vjp(const double u[3], const double E[3], const double B[3], double qm,
+                                          double dt, const double lun[3], double lu[3], double lE[3],
+                                          double lB[3]) {
+  const double eps = 0.5 * qm * dt;
+  const double um[3] = {u[0] + eps * E[0], u[1] + eps * E[1], u[2] + eps * E[2]};
+  const double g = sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+  const double eg = eps / g;
+  const double t[3] = {eg * B[0], eg * B[1], eg * B[2]};
+  const double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+  const double f = 2.0 / (1.0 + tt);
+  const double s[3] = {f * t[0], f * t[1], f * t[2]};
+  const double up[3] = {um[0] + (um[1] * t[2] - um[2] * t[1]), um[1] + (um[2] * t[0] - um[0] * t[2]),
+                        um[2] + (um[0] * t[1] - um[1] * t[0])};
+  // u' = um + up x s + eps E
+  double lum[3] = {lun[0], lun[1], lun[2]};
+  const double lup[3] = {s[1] * lun[2] - s[2] * lun[1], s[2] * lun[0] - s[0] * lun[2],
+                         s[0] * lun[1] - s[1] * lun[0]};  // s x lun
+  const double ls[3] = {lun[1] * up[2] - lun[2] * up[1], lun[2] * up[0] - lun[0] * up[2],
+                        lun[0] * up[1] - lun[1] * up[0]};  // lun x up
+  // s = f t, f = 2/(1 + t.t)
+  const double st = t[0] * ls[0] + t[1] * ls[1] + t[2] * ls[2];
+  double lt[3];
+  for (int d = 0; d < 3; ++d) lt[d] = f * ls[d] - f * f * st * t[d];
+  // up = um + um x t
+  lum[0] += lup[0] + (t[1] * lup[2] - t[2] * lup[1]);
+  lum[1] += lup[1] + (t[2] * lup[0] - t[0] * lup[2]);
+  lum[2] += lup[2] + (t[0] * lup[1] - t[1] * lup[0]);
+  lt[0] += lup[1] * um[2] - lup[2] * um[1];
+  lt[1] += lup[2] * um[0] - lup[0] * um[2];
+  lt[2] += lup[0] * um[1] - lup[1] * um[0];
+  // t = (eps/g) B,  g = sqrt(1 + um.um)
+  const double bl = B[0] * lt[0] + B[1] * lt[1] + B[2] * lt[2];
+  const double lg = -(eg / g) * bl;
+  for (int d = 0; d < 3; ++d) {
+    lB[d] = eg * lt[d];
+    lum[d] += (lg / g) * um[d];
+  }
+  // um = u + eps E, and the last half kick
+  for (int d = 0; d < 3; ++d) {
+    lu[d] = lum[d];
+    lE[d] = eps * (lum[d] + lun[d]);
+  }
+}
+
+// Reverse of one 3D linear-shape interpolation: scatter lv W into lf at the
+// eight nodes and add lv dv/dx to lx.
+__device__ __forceinline__ void interp3_vjp(const double* __restrict__ f, double* lf, const Axis& a,
+                                            const Axis& b, const Axis& c, const Mesh& m, double lv,
+                                            double lx[3]) {
+  if (lv == 0.0) return;
+  const size_t pl = (size_t)m.n1 * m.n2;
+  const size_t r00 = (size_t)c.i0 * pl + (size_t)b.i0 * m.n1;
+  const size_t r01 = (size_t)c.i0 * pl + (size_t)b.i1 * m.n1;
+  const size_t r10 = (size_t)c.i1 * pl + (size_t)b.i0 * m.n1;
+  const size_t r11 = (size_t)c.i1 * pl + (size_t)b.i1 * m.n1;
+  const double f000 = f[r00 + a.i0], f001 = f[r00 + a.i1];
+  const double f010 = f[r01 + a.i0], f011 = f[r01 + a.i1];
+  const double f100 = f[r10 + a.i0], f101 = f[r10 + a.i1];
+  const double f110 = f[r11 + a.i0], f111 = f[r11 + a.i1];
+  lx[0] += lv * m.idx1 *
+           (c.w0 * (b.w0 * (f001 - f000) + b.w1 * (f011 - f010)) + c.w1 * (b.w0 * (f101 - f100) + b.w1 * (f111 - f110)));
+  lx[1] += lv * m.idx2 *
+           (c.w0 * (a.w0 * (f010 - f000) + a.w1 * (f011 - f001)) + c.w1 * (a.w0 * (f110 - f100) + a.w1 * (f111 - f101)));
+  lx[2] += lv * m.idx3 *
+           (b.w0 * (a.w0 * (f100 - f000) + a.w1 * (f101 - f001)) + b.w1 * (a.w0 * (f110 - f010) + a.w1 * (f111 - f011)));
+  atomic_add(&lf[r00 + a.i0], lv * c.w0 * b.w0 * a.w0);
+  atomic_add(&lf[r00 + a.i1], lv * c.w0 * b.w0 * a.w1);
+  atomic_add(&lf[r01 + a.i0], lv * c.w0 * b.w1 * a.w0);
+  atomic_add(&lf[r01 + a.i1], lv * c.w0 * b.w1 * a.w1);
+  atomic_add(&lf[r10 + a.i0], lv * c.w1 * b.w0 * a.w0);
+  atomic_add(&lf[r10 + a.i1], lv * c.w1 * b.w0 * a.w1);
+  atomic_add(&lf[r11 + a.i0], lv * c.w1 * b.w1 * a.w0);
+  atomic_add(&lf[r11 + a.i1], lv * c.w1 * b.w1 * a.w1);
+}
+
+// 2D form: four nodes in the particle's plane (``f`` and ``lf`` already
+// point at it).
+__device__ __forceinline__ void interp2_vjp(const double* __restrict__ f, double* lf, const Axis& a,
+                                            const Axis& b, const Mesh& m, double lv, double lx[3]) {
+  if (lv == 0.0) return;
+  const size_t r0 = (size_t)b.i0 * m.n1, r1 = (size_t)b.i1 * m.n1;
+  const double f00 = f[r0 + a.i0], f01 = f[r0 + a.i1], f10 = f[r1 + a.i0], f11 = f[r1 + a.i1];
+  lx[0] += lv * m.idx1 * (b.w0 * (f01 - f00) + b.w1 * (f11 - f10));
+  lx[1] += lv * m.idx2 * (a.w0 * (f10 - f00) + a.w1 * (f11 - f01));
+  atomic_add(&lf[r0 + a.i0], lv * b.w0 * a.w0);
+  atomic_add(&lf[r0 + a.i1], lv * b.w0 * a.w1);
+  atomic_add(&lf[r1 + a.i0], lv * b.w1 * a.w0);
+  atomic_add(&lf[r1 + a.i1], lv * b.w1 * a.w1);
+}
+
+struct AdjFields {
+  const double* f[6];  // forward E1 E2 E3 B1 B2 B3 at t^n
+  double* l[6];        // their cotangents (accumulated)
+};
+
+// One thread per particle: reverse of gather + Boris + position update.
+// In: x^n, u^{n-1/2}, lx = dL/dx^{n+1}, lu = dL/du^{n+1/2}.
+// Out: lx = dL/dx^n, lu = dL/du^{n-1/2}; field cotangents accumulated.
+template <int NDIM>
+__global__ __launch_bounds__(256) void adjoint_boris_kernel(AdjFields F, Mesh m, const double* __restrict__ x1,
+                                                            const double* __restrict__ x2,
+                                                            const double* __restrict__ x3,
+                                                            const double* __restrict__ u1,
+                                                            const double* __restrict__ u2,
+                                                            const double* __restrict__ u3, double* __restrict__ lx1,
+                                                            double* __restrict__ lx2, double* __restrict__ lx3,
+                                                            double* __restrict__ lu1, double* __restrict__ lu2,
+                                                            double* __restrict__ lu3, int64_t np, double qm,
+                                                            double dt) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const bool stacked = NDIM == 2 && m.n3 > 1;
+  const double x[3] = {x1[p], x2[p], (NDIM == 3 || stacked) ? x3[p] : 0.0};
+  const double u[3] = {u1[p], u2[p], u3[p]};
+  double E[3], B[3];
+  gather6<double, NDIM>(F.f[0], F.f[1], F.f[2], F.f[3], F.f[4], F.f[5], m, x, E, B);
+  // forward push (recomputed) for the position update's Jacobian
+  double un[3] = {u[0], u[1], u[2]};
+  boris(un, E, B, qm, dt);
+  const double gn = sqrt(1.0 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+  double lx[3] = {lx1[p], lx2[p], NDIM == 3 ? lx3[p] : 0.0};
+  // x_d' = x_d + dt u'_d/gamma' for d < NDIM (the wrap is a constant shift)
+  double ux = 0;
+  for (int d = 0; d < NDIM; ++d) ux += un[d] * lx[d];
+  const double ig = dt / gn, ig3 = ig / (gn * gn);
+  double lun[3] = {lu1[p], lu2[p], lu3[p]};
+  for (int d = 0; d < 3; ++d) lun[d] += (d < NDIM ? ig * lx[d] : 0.0) - ig3 * un[d] * ux;
+  double lu[3], lE[3], lB[3];
+  boris_vjp(u, E, B, qm, dt, lun, lu, lE, lB);
+  // reverse of the gather
+  const Axis a0 = axis(x[0], m.idx1, 0.0, m.n1), ah = axis(x[0], m.idx1, 0.5, m.n1);
+  const Axis b0 = axis(x[1], m.idx2, 0.0, m.n2), bh = axis(x[1], m.idx2, 0.5, m.n2);
+  if (NDIM == 3) {
+    const Axis c0 = axis(x[2], m.idx3, 0.0, m.n3), ch = axis(x[2], m.idx3, 0.5, m.n3);
+    interp3_vjp(F.f[0], F.l[0], ah, b0, c0, m, lE[0], lx);
+    interp3_vjp(F.f[1], F.l[1], a0, bh, c0, m, lE[1], lx);
+    interp3_vjp(F.f[2], F.l[2], a0, b0, ch, m, lE[2], lx);
+    interp3_vjp(F.f[3], F.l[3], a0, bh, ch, m, lB[0], lx);
+    interp3_vjp(F.f[4], F.l[4], ah, b0, ch, m, lB[1], lx);
+    interp3_vjp(F.f[5], F.l[5], ah, bh, c0, m, lB[2], lx);
+    lx3[p] = lx[2];
+  } else {
+    const size_t off = plane_offset(m, x[2]);
+    interp2_vjp(F.f[0] + off, F.l[0] + off, ah, b0, m, lE[0], lx);
+    interp2_vjp(F.f[1] + off, F.l[1] + off, a0, bh, m, lE[1], lx);
+    interp2_vjp(F.f[2] + off, F.l[2] + off, a0, b0, m, lE[2], lx);
+    interp2_vjp(F.f[3] + off, F.l[3] + off, a0, bh, m, lB[0], lx);
+    interp2_vjp(F.f[4] + off, F.l[4] + off, ah, b0, m, lB[1], lx);
+    interp2_vjp(F.f[5] + off, F.l[5] + off, ah, bh, m, lB[2], lx);
+  }
+  lx1[p] = lx[0];
+  lx2[p] = lx[1];
+  lu1[p] = lu[0];
+  lu2[p] = lu[1];
+  lu3[p] = lu[2];
+}
+
+}  // namespace
+
+int coef_partial_blocks(const Mesh& m) {
+  const int nbx = (m.n1 + kRow - 1) / kRow;
+  return nbx * m.n2 * m.n3;
+}
+
+int launch_coef_grad(const Mesh& m, int form, const double* la, const double* fa, const double* lb,
+                     const double* fb, double scale, int M, double* partial, double* g, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const int nbx = (m.n1 + kRow - 1) / kRow;
+  const int nblocks = coef_partial_blocks(m);
+  if (form == 0)
+    hipLaunchKernelGGL(coef_partial_kernel<0>, dim3(nblocks), dim3(kRow), 0, s, la, fa, lb, fb, m.n1, nbx, partial);
+  else
+    hipLaunchKernelGGL(coef_partial_kernel<1>, dim3(nblocks), dim3(kRow), 0, s, la, fa, lb, fb, m.n1, nbx, partial);
+  hipLaunchKernelGGL(coef_finalize_kernel, dim3(M), dim3(256), 0, s, (const double*)partial, nblocks, scale, g);
+  return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "coefficient-gradient launch failed");
+}
+
+int launch_adjoint_push(const Mesh& m, void* const E[3], void* const B[3], void* const lE[3], void* const lB[3],
+                        const pic_particles& p, const pic_particles& lam, double dt, void* stream) {
+  if (p.np == 0) return PIC_OK;
+  hipStream_t s = (hipStream_t)stream;
+  AdjFields F;
+  for (int c = 0; c < 3; ++c) {
+    F.f[c] = (const double*)E[c];
+    F.f[3 + c] = (const double*)B[c];
+    F.l[c] = (double*)lE[c];
+    F.l[3 + c] = (double*)lB[c];
+  }
+  const dim3 grid((unsigned)((p.np + 255) / 256)), block(256);
+  const double qm = p.q / p.m;
+  if (m.ndim == 3)
+    hipLaunchKernelGGL(adjoint_boris_kernel<3>, grid, block, 0, s, F, m, p.x[0], p.x[1], p.x[2], p.u[0], p.u[1],
+                       p.u[2], lam.x[0], lam.x[1], lam.x[2], lam.u[0], lam.u[1], lam.u[2], p.np, qm, dt);
+  else
+    hipLaunchKernelGGL(adjoint_boris_kernel<2>, grid, block, 0, s, F, m, p.x[0], p.x[1], p.x[2], p.u[0], p.u[1],
+                       p.u[2], lam.x[0], lam.x[1], lam.x[2], lam.u[0], lam.u[1], lam.u[2], p.np, qm, dt);
+  return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "adjoint push launch failed");
+}
+
+}  // namespace yeepic

@@ -44,6 +44,8 @@ struct pic_grid {
   int64_t xo_cap = 0;
   int sort_every = 4;
   std::vector<SortState> sorts;
+  double* partial = nullptr;  // per-block partial sums of the coefficient gradients
+  int64_t partial_cap = 0;
   yeepic::Mesh mesh = {};
 };
 
@@ -100,6 +102,8 @@ static int check_particles(const pic_grid* g, const pic_particles* p) {
     if (!p->u[d]) return set_error(PIC_EINVAL, "particle momentum u[%d] is NULL", d);
   for (int d = 0; d < g->ndim; ++d)
     if (!p->x[d]) return set_error(PIC_EINVAL, "particle position x[%d] is NULL", d);
+  if (g->ndim == 2 && g->n[2] > 1 && !p->x[2])
+    return set_error(PIC_EINVAL, "a stack of 2D meshes needs x[2] (the plane index)");
   if (!(p->m > 0) || !std::isfinite(p->q) || !std::isfinite(p->w))
     return set_error(PIC_EINVAL, "bad species constants");
   if (p->np > ((int64_t)1 << 31) * 256) return set_error(PIC_EINVAL, "too many particles");
@@ -153,7 +157,6 @@ int pic_init_grid(const pic_grid_desc* d, pic_grid** out) {
   if (!d->CE || !d->CB) return set_error(PIC_EINVAL, "coefficient arrays are NULL");
   for (int a = 0; a < 3; ++a)
     if (d->n[a] < 1 || d->n[a] > (1 << 20)) return set_error(PIC_ESHAPE, "mesh size n[%d] out of range", a);
-  if (d->ndim == 2 && d->n[2] != 1) return set_error(PIC_ESHAPE, "2D meshes need n3 = 1");
   if (d->n[0] % 64 != 0) return set_error(PIC_ESHAPE, "n1 must be a multiple of 64");
   if (d->n[0] < 2 * d->M) return set_error(PIC_ESHAPE, "n1 must be at least 2M");
   const int64_t cells = d->n[0] * d->n[1] * d->n[2];
@@ -397,6 +400,69 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
   return rc;
 }
 
+int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* const* species,
+                     pic_particles* const* lambda, int nspecies, int pusher) {
+  if (!g || !adj) return set_error(PIC_EINVAL, "pic_adjoint_step: NULL argument");
+  if (g->prec != PIC_FP64) return set_error(PIC_EUNSUPPORTED, "the adjoint is built for FP64 grids only");
+  if (pusher != PIC_PUSH_BORIS) return set_error(PIC_EUNSUPPORTED, "the adjoint is built for the Boris pusher only");
+  if (nspecies < 0) return set_error(PIC_EINVAL, "negative count");
+  if (nspecies > 0 && (!species || !lambda)) return set_error(PIC_EINVAL, "species or lambda is NULL");
+  for (int c = 0; c < 3; ++c) {
+    if (!adj->lE[c] || !adj->lB[c]) return set_error(PIC_EINVAL, "adjoint field pointer is NULL");
+    if (((uintptr_t)adj->lE[c] | (uintptr_t)adj->lB[c]) & 15)
+      return set_error(PIC_ESHAPE, "adjoint fields must be 16-byte aligned");
+  }
+  if (!adj->gCE || !adj->gCB) return set_error(PIC_EINVAL, "coefficient-gradient pointer is NULL");
+  for (int s = 0; s < nspecies; ++s) {
+    int rc = check_particles(g, species[s]);
+    if (rc) return rc;
+    const pic_particles* l = lambda[s];
+    if (!l || l->np != species[s]->np) return set_error(PIC_ESHAPE, "lambda[%d] does not match species[%d]", s, s);
+    if (l->np > 0)
+      for (int d = 0; d < 3; ++d)
+        if (!l->u[d] || (d < g->ndim && !l->x[d]))
+          return set_error(PIC_EINVAL, "lambda[%d] has a NULL array", s);
+  }
+  const Mesh& m = g->mesh;
+  const int64_t need = (int64_t)coef_partial_blocks(m) * PIC_MAX_M;
+  if (need > g->partial_cap) {
+    (void)hipStreamSynchronize(g->stream);
+    if (g->partial) (void)hipFree(g->partial);
+    g->partial = nullptr;
+    g->partial_cap = 0;
+    if (hipMalloc((void**)&g->partial, (size_t)need * sizeof(double)) != hipSuccess)
+      return set_error(PIC_ENOMEM, "cannot allocate the coefficient-gradient scratch");
+    g->partial_cap = need;
+  }
+  const double dt = g->dt;
+  void* none[3] = {nullptr, nullptr, nullptr};
+  void* const* aE = g->alt;
+  void* const* aB = g->alt + 3;
+  auto d = [](void* p) { return (const double*)p; };
+  void* const* lE = adj->lE;
+  void* const* lB = adj->lB;
+  // forward intermediates: E' = E^{n+1} and B' = B^{n+1/2} (recomputed as
+  // B^{n+1} + dt/2 curl_E E^{n+1}) in the second field set
+  int rc = sweep_once(g, g->E, g->B, g->alt, g->alt + 3, 0);
+  if (!rc) rc = launch_advance_b(g->prec, m, aE, aB, g->CE, g->ME, -0.5 * dt, g->stream);
+  // third stage B'' = B' - dt/2 curl_E[C^E] E': dC^E from (lB, E')
+  if (!rc) rc = launch_coef_grad(m, 0, d(lB[1]), d(aE[2]), d(lB[2]), d(aE[1]), 0.5 * dt / m.dx1, g->M, g->partial,
+                                 adj->gCE, g->stream);
+  if (!rc) rc = launch_advance_e(g->prec, m, lE, lB, none, g->CE, g->ME, -0.5 * dt, g->stream);
+  // second stage E' = E + dt curl_B[C^B] B': dC^B from (lE', B')
+  if (!rc) rc = launch_coef_grad(m, 1, d(lE[2]), d(aB[1]), d(lE[1]), d(aB[2]), dt / m.dx1, g->M, g->partial,
+                                 adj->gCB, g->stream);
+  if (!rc) rc = launch_advance_b(g->prec, m, lE, lB, g->CB, g->MB, -dt, g->stream);
+  // first stage B' = B - dt/2 curl_E[C^E] E: dC^E from (lB', E^n)
+  if (!rc) rc = launch_coef_grad(m, 0, d(lB[1]), d(g->E[2]), d(lB[2]), d(g->E[1]), 0.5 * dt / m.dx1, g->M,
+                                 g->partial, adj->gCE, g->stream);
+  if (!rc) rc = launch_advance_e(g->prec, m, lE, lB, none, g->CE, g->ME, -0.5 * dt, g->stream);
+  // particles: reverse of position update, push and gather at t^n
+  for (int s = 0; s < nspecies && !rc; ++s)
+    rc = launch_adjoint_push(m, g->E, g->B, lE, lB, *species[s], *lambda[s], dt, g->stream);
+  return rc;
+}
+
 int pic_set_sort_interval(pic_grid* g, int steps) {
   if (!g) return set_error(PIC_EINVAL, "grid is NULL");
   if (steps < 1 || steps > 64) return set_error(PIC_EINVAL, "sort interval must be in 1..64");
@@ -442,6 +508,7 @@ void pic_destroy(pic_grid* g) {
     if (g->xo[d]) (void)hipFree(g->xo[d]);
   for (SortState& st : g->sorts) free_sort(st);
   if (g->d_flag) (void)hipFree(g->d_flag);
+  if (g->partial) (void)hipFree(g->partial);
   delete g;
 }
 

@@ -51,6 +51,15 @@ __device__ __forceinline__ double interp3(const T* __restrict__ f, const Axis& a
          c.w1 * (b.w0 * (a.w0 * f100 + a.w1 * f101) + b.w1 * (a.w0 * f110 + a.w1 * f111));
 }
 
+// A 2D mesh with n3 > 1 is a stack of n3 independent 2D meshes (no coupling
+// along x3); in 2D a particle's x3 holds the index of its plane (dx3 = 1 in
+// 2D), floor(x3) clamped into [0, n3).  Returns the plane's element offset.
+__device__ __forceinline__ size_t plane_offset(const Mesh& m, double x3) {
+  if (m.n3 == 1) return 0;
+  const double k = fmin(fmax(floor(x3), 0.0), (double)(m.n3 - 1));
+  return (size_t)k * m.n1 * m.n2;
+}
+
 template <typename T>
 __device__ __forceinline__ double interp2(const T* __restrict__ f, const Axis& a, const Axis& b, int n1) {
   const size_t r0 = (size_t)b.i0 * n1, r1 = (size_t)b.i1 * n1;
@@ -291,12 +300,13 @@ __device__ __forceinline__ void gather6(const T* __restrict__ E1, const T* __res
     B[1] = interp3(B2, ah, b0, ch, m.n1, pl);
     B[2] = interp3(B3, ah, bh, c0, m.n1, pl);
   } else {
-    E[0] = interp2(E1, ah, b0, m.n1);
-    E[1] = interp2(E2, a0, bh, m.n1);
-    E[2] = interp2(E3, a0, b0, m.n1);
-    B[0] = interp2(B1, a0, bh, m.n1);
-    B[1] = interp2(B2, ah, b0, m.n1);
-    B[2] = interp2(B3, ah, bh, m.n1);
+    const size_t o = plane_offset(m, x[2]);
+    E[0] = interp2(E1 + o, ah, b0, m.n1);
+    E[1] = interp2(E2 + o, a0, bh, m.n1);
+    E[2] = interp2(E3 + o, a0, b0, m.n1);
+    B[0] = interp2(B1 + o, a0, bh, m.n1);
+    B[1] = interp2(B2 + o, ah, b0, m.n1);
+    B[2] = interp2(B3 + o, ah, bh, m.n1);
   }
 }
 

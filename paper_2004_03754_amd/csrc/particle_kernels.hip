@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void gather_push_kernel(const T* __restrict__ 
                                                           double* __restrict__ o3) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= np) return;
-  double x[3] = {x1[p], x2[p], NDIM == 3 ? x3[p] : 0.0};
+  double x[3] = {x1[p], x2[p], (NDIM == 3 || m.n3 > 1) ? x3[p] : 0.0};
   double u[3] = {u1[p], u2[p], u3[p]};
   double E[3], B[3];
   gather6<T, NDIM>(E1, E2, E3, B1, B2, B3, m, x, E, B);
@@ -79,6 +79,12 @@ __global__ __launch_bounds__(256) void deposit_kernel(T* __restrict__ J1, T* __r
     for (int q = 0; q < 3; ++q) {
       ia[q] = wrapn(sx.base + q, m.n1);
       jb[q] = wrapn(sy.base + q, m.n2);
+    }
+    if (m.n3 > 1) {  // the particle's plane of a stack of 2D meshes
+      const size_t o = plane_offset(m, x3[p]);
+      J1 += o;
+      J2 += o;
+      J3 += o;
     }
     const double g = sqrt(1.0 + u1[p] * u1[p] + u2[p] * u2[p] + u3[p] * u3[p]);
     const double c3 = qw * u3[p] / g;
@@ -194,7 +200,7 @@ int launch_check(int prec, const Mesh& m, void* const E[3], void* const B[3], co
   if (p && p->np > 0) {
     const double L[3] = {m.L1, m.L2, m.L3};
     for (int d = 0; d < 3; ++d) {
-      const double* x = (d < m.ndim) ? p->x[d] : nullptr;
+      const double* x = (d < m.ndim || (d == 2 && m.n3 > 1)) ? p->x[d] : nullptr;
       hipLaunchKernelGGL(check_particles_kernel, grid, block, 0, s, x, p->u[d], p->np, L[d], d_flag);
     }
   }

@@ -63,6 +63,16 @@ int launch_tile_push(int prec, const Mesh& m, const TileGeom& tg, void* const E[
                      void* const J[3], const int* offsets, const pic_particles& src, const pic_particles& dst,
                      int pusher, double dt, void* stream);
 
+// Adjoint kernels (adjoint_kernels.hip).  launch_coef_grad adds
+// scale * sum_i (la_i D_j fa_i - lb_i D_j fb_i) to g[j], j < M, where D_j is
+// the Faraday (form 0) or Ampere (form 1) difference of lag j; ``partial``
+// holds coef_partial_blocks(m) * PIC_MAX_M doubles.
+int coef_partial_blocks(const Mesh& m);
+int launch_coef_grad(const Mesh& m, int form, const double* la, const double* fa, const double* lb,
+                     const double* fb, double scale, int M, double* partial, double* g, void* stream);
+int launch_adjoint_push(const Mesh& m, void* const E[3], void* const B[3], void* const lE[3], void* const lB[3],
+                        const pic_particles& p, const pic_particles& lam, double dt, void* stream);
+
 int launch_check(int prec, const Mesh& m, void* const E[3], void* const B[3],
                  const pic_particles* p, int* d_flag, void* stream);
 

@@ -83,7 +83,7 @@ def _desc(**kw):
     (dict(prec=7), -1),
     (dict(M=0), -1),
     (dict(n=[100, 8, 8]), -4),              # PIC_ESHAPE: n1 not a multiple of 64
-    (dict(ndim=2, n=[128, 8, 2]), -4),      # 2D needs n3 = 1
+    (dict(n=[1 << 20, 1 << 12, 1]), -4),    # more than 2^31 cells
     (dict(ptr=4100), -4),                   # misaligned fields
     (dict(ptr=0), -1),                      # NULL fields
     (dict(dt=0.5), -2),                     # PIC_ECFL (Sec. 3.2)
