@@ -220,6 +220,69 @@ def run_plasma(torch, b, wl, CE, CB, steps):
     return out
 
 
+def run_adjoint(torch, b, wl, CE, CB, steps, K=64):
+    """Adjoint workload: a batch of 16 2D meshes of 2048 x 256 cells (stacked
+    planes of one grid), one sin^2 envelope per plane with a0 = 10^U(0,3)
+    (seed 4), L_p = 10 lambda0, head at 12 lambda0; 64 electrons per plane at
+    rest, evenly spaced over 2 lambda0 ahead of the head on the middle x2
+    line; Boris pusher, FP64, checkpoints every K steps.  Losses: mean final
+    gamma and the vacuum phase error of E2 against the initial pulse moved on
+    by the elapsed time; gradients of each with respect to C^E, C^B and
+    (a0, L_p, head) of every plane.  Returns ms per step of the forward pass
+    and of each backward pass (recomputation + adjoint)."""
+    from paper_2004_03754_amd import autograd as pa
+
+    n1, n2, nb, npb = 2048, 256, 16, 64
+    dx = (wl.DX1, wl.DX2, wl.DX3)
+    L0 = wl.LAMBDA0
+    g = wl.rng(4)
+    a0 = torch.tensor(10.0 ** (3.0 * g.random(nb)), dtype=torch.float64, requires_grad=True)
+    Lp = torch.full((nb,), 10 * L0, dtype=torch.float64, requires_grad=True)
+    head = torch.full((nb,), 12 * L0, dtype=torch.float64, requires_grad=True)
+    x = torch.zeros((3, nb * npb), dtype=torch.float64)
+    x[0] = (12.5 * L0 + torch.arange(npb, dtype=torch.float64) * (2 * L0 / npb)).repeat(nb)
+    x[1] = 0.5 * n2 * dx[1]
+    x[2] = torch.arange(nb, dtype=torch.float64).repeat_interleave(npb) + 0.5
+    xd = x.to("cuda:0").contiguous()
+    ud = torch.zeros_like(xd)
+    ce = torch.tensor(CE, dtype=torch.float64, requires_grad=True)
+    cb = torch.tensor(CB, dtype=torch.float64, requires_grad=True)
+    cfg = pa.RunConfig(dx, wl.DT, steps, K=K, ndim=2)
+    with torch.no_grad():
+        Eref, _ = pa.sin2_pulse_fields(n1, n2, nb, dx, a0, Lp, head + steps * wl.DT)
+    torch.cuda.synchronize()
+    f0, f1 = _events(torch)
+    f0.record()
+    E0, B0 = pa.sin2_pulse_fields(n1, n2, nb, dx, a0, Lp, head)
+    Ef, Bf, xf, uf = pa.run(ce, cb, E0, B0, xd, ud, cfg)
+    f1.record()
+    gam = torch.sqrt(1.0 + torch.sum(uf * uf, 0))
+    L_gamma = torch.mean(gam)
+    L_phase = torch.sum((Ef[1] - Eref[1]) ** 2) / torch.sum(Eref[1] ** 2)
+    leaves = [ce, cb, a0, Lp, head]
+    out = {"steps": steps, "checkpoint_every": K, "planes": nb, "cells_per_plane": n1 * n2, "electrons": nb * npb}
+    times = []
+    for name, loss in (("gamma", L_gamma), ("phase", L_phase)):
+        torch.cuda.synchronize()
+        b0, b1 = _events(torch)
+        b0.record()
+        grads = torch.autograd.grad(loss, leaves, retain_graph=(name == "gamma"))
+        b1.record()
+        torch.cuda.synchronize()
+        times.append(b0.elapsed_time(b1))
+        out[f"L_{name}"] = float(loss)
+        out[f"grad_{name}"] = {k: [float(v) for v in gr.flatten()[:4]] + (["..."] if gr.numel() > 4 else [])
+                               for k, gr in zip(("CE", "CB", "a0", "Lp", "head"), grads)}
+        assert all(bool(torch.isfinite(gr).all()) for gr in grads), "non-finite gradient"
+    ms_fwd = f0.elapsed_time(f1) / steps
+    out.update({"fwd_ms_per_step": ms_fwd, "adjoint_ms_per_step": times[0] / steps,
+                "fwd_plus_adjoint_ms_per_step": ms_fwd + times[0] / steps,
+                "second_adjoint_ms_per_step": times[1] / steps})
+    del Ef, Bf, xf, uf, E0, B0, Eref, grads
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline_child():
     """Runs in a child process with one thread: the oracle's step on a
     sample of the default workload (a 1024 x 32 x 32 column of the mesh with
@@ -288,6 +351,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-baseline-child", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=2048,
+                    help="steps of the differentiated 2D batch run (checkpoint every 64)")
+    ap.add_argument("--adjoint-only", action="store_true", help="run only the adjoint workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args()
@@ -311,6 +377,9 @@ def main():
     r = 0.5
     CE = b.design_coeffs(16, r, "E")
     CB = b.design_coeffs(16, r, "B")
+    if args.adjoint_only:
+        print(json.dumps({"adjoint_2d_2048x256_x16": run_adjoint(torch, b, wl, CE, CB, steps=args.adjoint_steps)}))
+        return
     L = wl.LAMBDA0
     n = (1024, 256, 256)
     dx = (wl.DX1, wl.DX2, wl.DX3)
@@ -361,6 +430,7 @@ def main():
             "speedup_vs_fp64_sweep": main_run["ms_sweep"] / fp32["ms_sweep"]}
         res["plane_wave_2048x512x512"] = run_plane_wave(torch, b, wl, CE, CB, steps=20)
         res["plasma_512x256x256"] = run_plasma(torch, b, wl, CE, CB, steps=10)
+        res["adjoint_2d_2048x256_x16"] = run_adjoint(torch, b, wl, CE, CB, steps=args.adjoint_steps)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res))
