@@ -123,10 +123,12 @@ def _exp_and_integral(F, tau):
     return ex[:, :4, :4], ex[:, :4, 4:]
 
 
-def analytic(u, Ep, Bp, qm, dt, max_iter=200):
+def analytic(u, Ep, Bp, qm, dt, max_iter=20000):
     """Exact push for E, B constant over the step (plain definition, see the
     module docstring): proper-time exponential plus a safeguarded Newton
-    solve of t(tau) = dt between 0 and dt."""
+    solve of t(tau) = dt between 0 and dt.  A non-finite t(tau) (overflow of
+    the exponential far above the root) counts as an overshoot; the solve
+    raises if some root is not found."""
     npart = u.shape[1]
     F = qm * field_tensor(Ep, Bp)
     g0 = np.sqrt(1.0 + np.sum(u * u, axis=0))
@@ -142,17 +144,23 @@ def analytic(u, Ep, Bp, qm, dt, max_iter=200):
         tval = np.einsum("pj,pj->p", it[:, 0, :], U0)
         gam = np.einsum("pj,pj->p", ex[:, 0, :], U0)
         f = tval - dt
-        hit = np.abs(f) <= 1e-16 * abs(dt)      # root found: keep tau
-        hi = np.where(f > 0, tau, hi)
-        lo = np.where(f <= 0, tau, lo)
-        newt = tau - f / gam
-        bad = ~((newt > lo) & (newt < hi))
+        finite = np.isfinite(f) & np.isfinite(gam)
+        hit = finite & (np.abs(f) <= 1e-16 * abs(dt))      # root found: keep tau
+        # a non-finite t(tau) lies beyond the root, on the far side from 0
+        over = np.where(finite, f > 0, dt > 0)
+        hi = np.where(over, tau, hi)
+        lo = np.where(over, lo, tau)
+        with np.errstate(invalid="ignore"):
+            newt = tau - f / gam
+        bad = ~finite | ~((newt > lo) & (newt < hi))
         nxt = np.where(bad, 0.5 * (lo + hi), newt)
         small = np.abs(nxt - tau) <= 1e-15 * np.abs(tau)
         tau = np.where(done | hit, tau, nxt)
         done |= hit | small
         if done.all():
             break
+    if not done.all():
+        raise RuntimeError("exact pusher: t(tau) = dt not solved")
     ex, _ = _exp_and_integral(F, tau)
     U = np.einsum("pij,pj->pi", ex, U0)
     return U[:, 1:].T.copy()

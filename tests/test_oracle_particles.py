@@ -81,6 +81,33 @@ def test_pure_electric_field(push):
     assert np.allclose(push(u, E, B, qm, dt), u + qm * E * dt, rtol=1e-12, atol=1e-12)
 
 
+def test_exact_pusher_strong_fields():
+    """The exact pusher's lab-time root t(tau) = dt in the strong-field
+    regime, where t(tau) grows like exp(kappa tau) with kappa dt up to 1e4
+    (the first guess tau = dt/gamma overflows): from rest a pure E field gives
+    u = q E dt exactly, and near-null crossed fields of 1e4 (E along x2, B
+    along x3 slightly weaker) keep the semigroup and time-reversal
+    properties of an exact map."""
+    E0 = np.array([1e2, 1e3, 1e4, 1e5])
+    E = np.zeros((3, 4))
+    E[0] = E0
+    u = np.zeros((3, 4))
+    qm, dt = -1.0, 0.1
+    assert np.allclose(pt.analytic(u, E, np.zeros_like(E), qm, dt), qm * E * dt, rtol=1e-12, atol=0)
+    delta = np.array([1e-4, 1e-3, 1e-2, 0.1, 0.5])
+    E = np.zeros((3, 5))
+    B = np.zeros((3, 5))
+    E[1] = 1e4
+    B[2] = 1e4 * (1 - delta)
+    u = np.zeros((3, 5))
+    dt = np.pi / 32
+    one = pt.analytic(u, E, B, qm, dt)
+    two = pt.analytic(pt.analytic(u, E, B, qm, dt / 2), E, B, qm, dt / 2)
+    assert np.allclose(one, two, rtol=1e-9, atol=0)
+    back = pt.analytic(one, E, B, qm, -dt)
+    assert np.max(np.abs(back - u)) <= 1e-9 * np.max(np.abs(one))
+
+
 def test_pure_magnetic_field_rotation():
     """|u| is conserved; the rotation angle is q B dt/gamma for the exact
     pusher and 2 arctan(q B dt/(2 gamma)) for Boris."""
