@@ -102,7 +102,8 @@ __device__ __forceinline__ void boris(double u[3], const double E[3], const doub
 // For max(X, Y) <= 1 the series is summed; otherwise the hyperbolic /
 // trigonometric closed forms are used, written without cancellation where a
 // cancellation-free form exists.  t(tau) = dt is solved by safeguarded Newton
-// (t increases with dt/dtau = gamma >= 1, root between 0 and dt).
+// (t increases with dt/dtau = gamma >= 1, root between 0 and dt) applied to
+// log(t/dt).
 // ---------------------------------------------------------------------------
 struct ExpCoef {
   double a0, a1, a2, a3, A1, A3;  // A0 = a1, A2 = a3
@@ -204,15 +205,25 @@ __device__ __forceinline__ void analytic(double u[3], const double E[3], const d
   apply_F(E, B, qm, V1, V2);
   apply_F(E, B, qm, V2, V3);
   double lo = fmin(0.0, dt), hi = fmax(0.0, dt);
+  // first guess dt/gamma, pulled in so that exp(sqrt(k2 + w2) tau) stays finite
+  const double kw = sqrt(k2 + w2);
   double tau = dt / U0[0];
+  if (kw * fabs(tau) > 50.0) tau = copysign(50.0 / kw, dt);
   for (int it = 0; it < 100; ++it) {
     const ExpCoef e = exp_coef(k2, w2, tau);
     const double t = e.a1 * U0[0] + e.A1 * V1[0] + e.a3 * V2[0] + e.A3 * V3[0];
     const double g = e.a0 * U0[0] + e.a1 * V1[0] + e.a2 * V2[0] + e.a3 * V3[0];
+    const bool fin = isfinite(t) && isfinite(g) && g > 0.0;
     const double f = t - dt;
-    if (fabs(f) <= 1e-16 * fabs(dt)) break;
-    if (!(f <= 0.0)) hi = tau; else lo = tau;
-    double nx = tau - f / g;
+    if (fin && fabs(f) <= 1e-16 * fabs(dt)) break;
+    // keep the root bracketed; a non-finite value lies beyond it, away from 0
+    if (fin ? f > 0.0 : dt > 0.0) hi = tau; else lo = tau;
+    // Newton on log(t/dt): where t grows exponentially log t is close to
+    // linear, and for a particle accelerated from rest it is concave, so the
+    // steps do not overshoot (a plain Newton step on the steep, convex t does,
+    // far past the root); the bracket guards every other case
+    const double ratio = t / dt;
+    double nx = (fin && ratio > 0.0) ? tau - log(ratio) * (t / g) : 0.5 * (lo + hi);
     if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
     const bool small = fabs(nx - tau) <= 1e-15 * fabs(tau);
     tau = nx;

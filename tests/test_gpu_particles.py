@@ -77,6 +77,42 @@ def test_gather_push(ndim, pusher, prec, field_scale, coeffs16):
     grid.close()
 
 
+def test_exact_pusher_strong_uniform_fields(coeffs16):
+    """The exact pusher where t(tau) grows like exp(kappa tau) with kappa dt
+    up to 1e4: a stack of 2D planes, each holding one constant (E, B), with
+    electrons at rest (the gather of a constant field is exact).  Pure E from
+    1e2 to 1e5, near-null crossed fields of 1e4 and random fields of 1e4,
+    against the oracle."""
+    cases = [(np.array([e, 0, 0.0]), np.zeros(3)) for e in (1e2, 1e3, 1e4, 1e5)]
+    cases += [(np.array([0, 1e4, 0.0]), np.array([0, 0, 1e4 * (1 - d)])) for d in (1e-4, 1e-3, 1e-2, 0.1, 0.5)]
+    g = np.random.default_rng(17)
+    cases += [(1e4 * g.standard_normal(3), 1e4 * g.standard_normal(3)) for _ in range(4)]
+    nb, n1, n2, per = len(cases), 64, 4, 8
+    E = [np.zeros((nb, n2, n1)) for _ in range(3)]
+    B = [np.zeros((nb, n2, n1)) for _ in range(3)]
+    for k, (e, bb) in enumerate(cases):
+        for c in range(3):
+            E[c][k] = e[c]
+            B[c][k] = bb[c]
+    x = np.zeros((3, nb * per))
+    x[0] = np.tile(np.linspace(0.1, 0.9, per) * n1 * DX[0], nb)
+    x[1] = 0.3 * n2 * DX[1]
+    x[2] = np.repeat(np.arange(nb) + 0.5, per)
+    u = np.zeros_like(x)
+    u[:, 1::2] = g.standard_normal((3, nb * per // 2)) * 10
+    CE, CB = coeffs16
+    grid = b.Grid([dev(e) for e in E], [dev(v) for v in B], DX[:2], wl.DT, CE, CB, ndim=2)
+    xd, ud = dev(x), dev(u)
+    grid.gather_push(b.Particles(xd, ud, q=-1.0, m=1.0), "analytic")
+    grid.sync()
+    Ep = np.repeat(np.array([c[0] for c in cases]).T, per, axis=1)
+    Bp = np.repeat(np.array([c[1] for c in cases]).T, per, axis=1)
+    un = pt.analytic(u, Ep, Bp, -1.0, wl.DT)
+    err = np.max(np.abs(host(ud) - un), axis=0) / np.maximum(1.0, np.max(np.abs(un), axis=0))
+    assert err.max() <= 1e-11, (err.max(), int(np.argmax(err)))
+    grid.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("ndim", [3, 2])
 def test_deposit(ndim, prec, coeffs16):
