@@ -93,6 +93,8 @@ typedef struct pic_adjoint {
   void *lB[3];         /* device, caller-owned, layout of B: dL/dB (same) */
   double *gCE;         /* device, PIC_MAX_M doubles: dL/dC^E_j, accumulated (+=) for j < M */
   double *gCB;         /* device, PIC_MAX_M doubles: dL/dC^B_j, accumulated (+=) for j < M */
+  const void *En[3];   /* optional (all six or none): the forward state at t^{n+1}, E ... */
+  const void *Bn[3];   /* ... and B, read only; when given the step recomputes no sweep */
 } pic_adjoint;
 
 /* ---- coefficient design (host only; App. B) ------------------------------
@@ -170,6 +172,15 @@ int pic_deposit_J(pic_grid *g, const pic_particles *p, double *const x_old[3], i
  * Vacuum calls and 2D grids keep the order. */
 int pic_step_n(pic_grid *g, pic_particles *const *species, int nspecies, int nsteps,
                int pusher, int deposit);
+/* One vacuum step (no deposit) out of place: gather + push + position update
+ * of each species at the grid's fields (particles advanced in place), then
+ * the fused sweep (Eq. maxwell, App. B operators) from the grid's fields
+ * into Eout, Bout (device, same shape and precision, 16-byte aligned, not
+ * the grid's own arrays: PIC_EINVAL).  The grid's fields are not modified.
+ * For callers that keep a sequence of states (e.g. recomputation between
+ * adjoint checkpoints) without copying them. */
+int pic_step_to(pic_grid *g, pic_particles *const *species, int nspecies, int pusher,
+                void *const Eout[3], void *const Bout[3]);
 /* Steps between particle re-sorts in pic_step_n (1..64, default 4); the
  * on-chip current tile grows with the interval (|v| < c bounds the drift). */
 int pic_set_sort_interval(pic_grid *g, int steps);
@@ -186,8 +197,11 @@ int pic_set_sort_interval(pic_grid *g, int steps);
  * map dL/d(E,B)^{n+1} to dL/d(E,B)^n, and dL/dC^E_j and dL/dC^B_j (every
  * j < M, also where C_j = 0) are added to adj->gCE, gCB.
  * The field part uses the transposition of the App. B operators
- * (curl_E[C]^T = curl_B[C]) and recomputes E^{n+1} and B^{n+1/2} in the
- * grid's second field set.  The position wrap is a constant shift (derivative
+ * (curl_E[C]^T = curl_B[C]).  It needs E^{n+1} and B^{n+1/2}: with adj->En,
+ * adj->Bn given (the forward state at t^{n+1}, which must not alias lE, lB
+ * or the grid's fields) it rebuilds B^{n+1/2} = B^{n+1} + dt/2 curl_E E^{n+1}
+ * in the grid's second field set, else it first recomputes the forward sweep
+ * there.  The position wrap is a constant shift (derivative
  * the identity); at a cell face the shape function has a kink, and the
  * derivative taken is the one of the cell the particle is in.
  * PIC_EUNSUPPORTED for FP32-field grids and the analytic pusher; the

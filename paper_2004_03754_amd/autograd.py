@@ -4,9 +4,10 @@ library's forward step loop and its hand-written adjoint.
 Forward: ``nsteps`` steps of gather + Boris push + position update + fused
 field sweep (pic_step_n), keeping a checkpoint of the state (E, B, x, u)
 every ``K`` steps.  Backward: the segments are walked in reverse; each one is
-recomputed from its checkpoint one step at a time into a buffer of K states,
-then reversed step by step with pic_adjoint_step, which maps the cotangents
-of (E, B, x, u) from t^{n+1} to t^n and accumulates dL/dC^E and dL/dC^B.
+recomputed from its checkpoint one step at a time (pic_step_to, each state
+written into its own buffer of K + 1), then reversed step by step with
+pic_adjoint_step, which maps the cotangents of (E, B, x, u) from t^{n+1} to
+t^n, given both states, and accumulates dL/dC^E and dL/dC^B.
 The forward arithmetic is deterministic, so a recomputed state equals the
 stored forward state bit for bit.
 
@@ -78,37 +79,38 @@ class PICRun(torch.autograd.Function):
         gCE = torch.zeros(b.PIC_MAX_M, dtype=torch.float64, device=dev)
         gCB = torch.zeros(b.PIC_MAX_M, dtype=torch.float64, device=dev)
         K = min(cfg.K, cfg.nsteps)
-        slots = [_clone_state(E0, B0, x0, u0) for _ in range(K)]
+        # K + 1 state buffers: a segment's states t^{s0} .. t^{s0+n}
+        slots = [_clone_state(E0, B0, x0, u0) for _ in range(K + 1)]
         grid = b.Grid(slots[0][0], slots[0][1], cfg.dx, cfg.dt, ce, cb, ndim=cfg.ndim)
         lam = b.Particles(lx, lu, q=cfg.q, m=cfg.m, w=cfg.w)
         nseg = len(ctx.checkpoints)
         for seg in reversed(range(nseg)):
             s0 = seg * cfg.K
             n = min(cfg.K, cfg.nsteps - s0)
-            # recompute the segment's states t^{s0} .. t^{s0+n-1}
+            # recompute the segment's states, each step written into the next
+            # buffer (out of place: no field copies)
             cE, cB, cx, cu = ctx.checkpoints[seg]
             for a, c in zip(slots[0][0] + slots[0][1], cE + cB):
                 a.copy_(c)
             slots[0][2].copy_(cx)
             slots[0][3].copy_(cu)
-            for i in range(1, n):
+            for i in range(1, n + 1):
                 prev, cur = slots[i - 1], slots[i]
-                for a, c in zip(cur[0] + cur[1], prev[0] + prev[1]):
-                    a.copy_(c)
                 cur[2].copy_(prev[2])
                 cur[3].copy_(prev[3])
-                grid.set_fields(cur[0], cur[1])
+                grid.set_fields(prev[0], prev[1])
                 p = b.Particles(cur[2], cur[3], q=cfg.q, m=cfg.m, w=cfg.w)
-                grid.step_n([p] if p.np else [], 1, pusher="boris")
-            # reverse the segment
+                grid.step_to([p] if p.np else [], cur[0], cur[1], pusher="boris")
+            # reverse the segment (the particle adjoint needs x, u at t^n: the
+            # previous buffer's, since step_to advanced the copies)
             for i in reversed(range(n)):
-                st = slots[i]
+                st, nx = slots[i], slots[i + 1]
                 grid.set_fields(st[0], st[1])
                 p = b.Particles(st[2], st[3], q=cfg.q, m=cfg.m, w=cfg.w)
                 if p.np:
-                    grid.adjoint_step(lE, lB, gCE, gCB, [p], [lam])
+                    grid.adjoint_step(lE, lB, gCE, gCB, [p], [lam], next_E=nx[0], next_B=nx[1])
                 else:
-                    grid.adjoint_step(lE, lB, gCE, gCB)
+                    grid.adjoint_step(lE, lB, gCE, gCB, next_E=nx[0], next_B=nx[1])
         grid.sync()
         grid.close()
         dtype, device, M = ctx.coef_meta

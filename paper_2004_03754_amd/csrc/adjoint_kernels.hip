@@ -33,39 +33,48 @@ using namespace pdev;
 
 constexpr int kLags = PIC_MAX_M;  // every coefficient of the vector gets a gradient
 constexpr int kRow = 256;         // cells of x1 per block of the coefficient reduction
+constexpr int kRows = 16;         // x1 rows each block accumulates before reducing
 
-// Partial sums  acc_j = sum_i la_i D_j(fa)_i - lb_i D_j(fb)_i  over kRow cells
-// of one x1 row, for j = 1..kLags;  D_j f_i = f_{i+j} - f_{i-j+1} (FORM 0,
-// Faraday) or f_{i+j-1} - f_{i-j} (FORM 1, Ampere).  Block b covers row
-// b / nbx, cells [(b % nbx) kRow, +kRow).
+// Partial sums  acc_j = sum_i la_i D_j(fa)_i - lb_i D_j(fb)_i,  j = 1..kLags,
+// over kRow cells of each of kRows consecutive x1 rows;  D_j f_i = f_{i+j} -
+// f_{i-j+1} (FORM 0, Faraday) or f_{i+j-1} - f_{i-j} (FORM 1, Ampere).  Block
+// b covers rows (b / nbx) * kRows .. + kRows (clipped to nrows) and cells
+// [(b % nbx) kRow, + kRow) of each; every thread keeps its kLags sums in
+// registers over the rows, then the block reduces them once.
 template <int FORM>
 __global__ __launch_bounds__(kRow) void coef_partial_kernel(const double* __restrict__ la,
                                                             const double* __restrict__ fa,
                                                             const double* __restrict__ lb,
                                                             const double* __restrict__ fb, int n1, int nbx,
-                                                            double* __restrict__ partial) {
+                                                            int nrows, double* __restrict__ partial) {
   __shared__ double sa[kRow + 2 * kLags], sb[kRow + 2 * kLags];
   __shared__ double red[kRow / 64][kLags];
-  const int rowi = blockIdx.x / nbx;
+  const int r0 = (blockIdx.x / nbx) * kRows;
+  const int r1 = min(r0 + kRows, nrows);
   const int i0 = (blockIdx.x % nbx) * kRow;
-  const size_t row = (size_t)rowi * n1;
-  for (int t = threadIdx.x; t < kRow + 2 * kLags; t += kRow) {
-    int i = (i0 - kLags + t) % n1;
-    i += (i < 0) ? n1 : 0;
-    sa[t] = fa[row + i];
-    sb[t] = fb[row + i];
-  }
-  __syncthreads();
-  double acc[kLags];
   const int i = i0 + (int)threadIdx.x;
-  const double a = (i < n1) ? la[row + i] : 0.0;
-  const double b = (i < n1) ? lb[row + i] : 0.0;
   const int c = threadIdx.x + kLags;  // LDS slot of cell i
+  double acc[kLags];
 #pragma unroll
-  for (int j = 1; j <= kLags; ++j) {
-    const int hi = FORM == 0 ? c + j : c + j - 1;
-    const int lo = FORM == 0 ? c - j + 1 : c - j;
-    acc[j - 1] = a * (sa[hi] - sa[lo]) - b * (sb[hi] - sb[lo]);
+  for (int j = 0; j < kLags; ++j) acc[j] = 0.0;
+  for (int rr = r0; rr < r1; ++rr) {
+    const size_t row = (size_t)rr * n1;
+    __syncthreads();  // the previous row's reads are done
+    for (int t = threadIdx.x; t < kRow + 2 * kLags; t += kRow) {
+      int ii = (i0 - kLags + t) % n1;
+      ii += (ii < 0) ? n1 : 0;
+      sa[t] = fa[row + ii];
+      sb[t] = fb[row + ii];
+    }
+    __syncthreads();
+    const double a = (i < n1) ? la[row + i] : 0.0;
+    const double b = (i < n1) ? lb[row + i] : 0.0;
+#pragma unroll
+    for (int j = 1; j <= kLags; ++j) {
+      const int hi = FORM == 0 ? c + j : c + j - 1;
+      const int lo = FORM == 0 ? c - j + 1 : c - j;
+      acc[j - 1] += a * (sa[hi] - sa[lo]) - b * (sb[hi] - sb[lo]);
+    }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -260,7 +269,8 @@ __global__ __launch_bounds__(256) void adjoint_boris_kernel(AdjFields F, Mesh m,
 
 int coef_partial_blocks(const Mesh& m) {
   const int nbx = (m.n1 + kRow - 1) / kRow;
-  return nbx * m.n2 * m.n3;
+  const int nrows = m.n2 * m.n3;
+  return nbx * ((nrows + kRows - 1) / kRows);
 }
 
 int launch_coef_grad(const Mesh& m, int form, const double* la, const double* fa, const double* lb,
@@ -268,10 +278,13 @@ int launch_coef_grad(const Mesh& m, int form, const double* la, const double* fa
   hipStream_t s = (hipStream_t)stream;
   const int nbx = (m.n1 + kRow - 1) / kRow;
   const int nblocks = coef_partial_blocks(m);
+  const int nrows = m.n2 * m.n3;
   if (form == 0)
-    hipLaunchKernelGGL(coef_partial_kernel<0>, dim3(nblocks), dim3(kRow), 0, s, la, fa, lb, fb, m.n1, nbx, partial);
+    hipLaunchKernelGGL(coef_partial_kernel<0>, dim3(nblocks), dim3(kRow), 0, s, la, fa, lb, fb, m.n1, nbx, nrows,
+                       partial);
   else
-    hipLaunchKernelGGL(coef_partial_kernel<1>, dim3(nblocks), dim3(kRow), 0, s, la, fa, lb, fb, m.n1, nbx, partial);
+    hipLaunchKernelGGL(coef_partial_kernel<1>, dim3(nblocks), dim3(kRow), 0, s, la, fa, lb, fb, m.n1, nbx, nrows,
+                       partial);
   hipLaunchKernelGGL(coef_finalize_kernel, dim3(M), dim3(256), 0, s, (const double*)partial, nblocks, scale, g);
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "coefficient-gradient launch failed");
 }

@@ -254,7 +254,7 @@ int pic_grid_widths(const pic_grid* g, int* ME, int* MB) {
 
 int pic_advance_B_half(pic_grid* g) {
   if (!g) return set_error(PIC_EINVAL, "grid is NULL");
-  return launch_advance_b(g->prec, g->mesh, g->E, g->B, g->CE, g->ME, 0.5 * g->dt, g->stream);
+  return launch_advance_b(g->prec, g->mesh, g->E, g->B, g->B, g->CE, g->ME, 0.5 * g->dt, g->stream);
 }
 
 int pic_advance_E(pic_grid* g, int use_J) {
@@ -400,6 +400,30 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
   return rc;
 }
 
+int pic_step_to(pic_grid* g, pic_particles* const* species, int nspecies, int pusher, void* const Eout[3],
+                void* const Bout[3]) {
+  if (!g || !Eout || !Bout) return set_error(PIC_EINVAL, "pic_step_to: NULL argument");
+  if (nspecies < 0) return set_error(PIC_EINVAL, "negative count");
+  if (nspecies > 0 && !species) return set_error(PIC_EINVAL, "species is NULL");
+  if (pusher != PIC_PUSH_BORIS && pusher != PIC_PUSH_ANALYTIC) return set_error(PIC_EINVAL, "bad pusher");
+  for (int c = 0; c < 3; ++c) {
+    if (!Eout[c] || !Bout[c]) return set_error(PIC_EINVAL, "output field pointer is NULL");
+    if (((uintptr_t)Eout[c] | (uintptr_t)Bout[c]) & 15) return set_error(PIC_ESHAPE, "fields must be 16-byte aligned");
+    for (int q = 0; q < 3; ++q)
+      if (Eout[c] == g->E[q] || Eout[c] == g->B[q] || Bout[c] == g->E[q] || Bout[c] == g->B[q])
+        return set_error(PIC_EINVAL, "pic_step_to: output aliases the grid's fields");
+  }
+  for (int s = 0; s < nspecies; ++s) {
+    int rc = check_particles(g, species[s]);
+    if (rc) return rc;
+  }
+  for (int s = 0; s < nspecies; ++s) {
+    int rc = launch_gather_push(g->prec, g->mesh, g->E, g->B, *species[s], pusher, g->dt, nullptr, g->stream);
+    if (rc) return rc;
+  }
+  return sweep_once(g, g->E, g->B, Eout, Bout, 0);
+}
+
 int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* const* species,
                      pic_particles* const* lambda, int nspecies, int pusher) {
   if (!g || !adj) return set_error(PIC_EINVAL, "pic_adjoint_step: NULL argument");
@@ -436,15 +460,27 @@ int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* c
   }
   const double dt = g->dt;
   void* none[3] = {nullptr, nullptr, nullptr};
-  void* const* aE = g->alt;
-  void* const* aB = g->alt + 3;
-  auto d = [](void* p) { return (const double*)p; };
+  auto d = [](const void* p) { return (const double*)p; };
   void* const* lE = adj->lE;
   void* const* lB = adj->lB;
-  // forward intermediates: E' = E^{n+1} and B' = B^{n+1/2} (recomputed as
-  // B^{n+1} + dt/2 curl_E E^{n+1}) in the second field set
-  int rc = sweep_once(g, g->E, g->B, g->alt, g->alt + 3, 0);
-  if (!rc) rc = launch_advance_b(g->prec, m, aE, aB, g->CE, g->ME, -0.5 * dt, g->stream);
+  void* const* aB = g->alt + 3;
+  // forward intermediates: E' = E^{n+1}, and B' = B^{n+1/2} recomputed as
+  // B^{n+1} + dt/2 curl_E E^{n+1} into the second field set.  E^{n+1}, B^{n+1}
+  // come from the caller when given, else from a forward sweep.
+  const bool next = adj->En[0] && adj->En[1] && adj->En[2] && adj->Bn[0] && adj->Bn[1] && adj->Bn[2];
+  void* nE[3] = {g->alt[0], g->alt[1], g->alt[2]};
+  void* nB[3] = {g->alt[3], g->alt[4], g->alt[5]};
+  int rc = PIC_OK;
+  if (next) {
+    for (int c = 0; c < 3; ++c) {
+      nE[c] = const_cast<void*>(adj->En[c]);
+      nB[c] = const_cast<void*>(adj->Bn[c]);
+    }
+  } else {
+    rc = sweep_once(g, g->E, g->B, g->alt, g->alt + 3, 0);
+  }
+  void* const* aE = nE;
+  if (!rc) rc = launch_advance_b(g->prec, m, nE, nB, g->alt + 3, g->CE, g->ME, -0.5 * dt, g->stream);
   // third stage B'' = B' - dt/2 curl_E[C^E] E': dC^E from (lB, E')
   if (!rc) rc = launch_coef_grad(m, 0, d(lB[1]), d(aE[2]), d(lB[2]), d(aE[1]), 0.5 * dt / m.dx1, g->M, g->partial,
                                  adj->gCE, g->stream);
@@ -452,7 +488,7 @@ int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* c
   // second stage E' = E + dt curl_B[C^B] B': dC^B from (lE', B')
   if (!rc) rc = launch_coef_grad(m, 1, d(lE[2]), d(aB[1]), d(lE[1]), d(aB[2]), dt / m.dx1, g->M, g->partial,
                                  adj->gCB, g->stream);
-  if (!rc) rc = launch_advance_b(g->prec, m, lE, lB, g->CB, g->MB, -dt, g->stream);
+  if (!rc) rc = launch_advance_b(g->prec, m, lE, lB, lB, g->CB, g->MB, -dt, g->stream);
   // first stage B' = B - dt/2 curl_E[C^E] E: dC^E from (lB', E^n)
   if (!rc) rc = launch_coef_grad(m, 0, d(lB[1]), d(g->E[2]), d(lB[2]), d(g->E[1]), 0.5 * dt / m.dx1, g->M,
                                  g->partial, adj->gCE, g->stream);

@@ -27,14 +27,16 @@ __device__ __forceinline__ int wrap1(int i, int n) {
 
 // ---------------------------------------------------------------------------
 // Standalone steps: one thread per cell, neighbours read through the caches.
-// In place is safe: a B update reads only E and its own B, and vice versa.
+// In place is safe: a B update reads only E and its own B, and vice versa;
+// the B step may also write a different array than it reads.
 // ---------------------------------------------------------------------------
 
-// B <- B - h curl_E E.  ``ce`` holds h C^E_j/dx1; hy = h/dx2, hz = h/dx3.
+// Bout <- Bin - h curl_E E (Bout may be Bin).  ``ce`` holds h C^E_j/dx1;
+// hy = h/dx2, hz = h/dx3.
 template <typename T, int W>
 __global__ __launch_bounds__(256) void advance_b_kernel(const T* __restrict__ E1, const T* __restrict__ E2,
-                                                        const T* __restrict__ E3, T* __restrict__ B1,
-                                                        T* __restrict__ B2, T* __restrict__ B3, Mesh m,
+                                                        const T* __restrict__ E3, const T* Bi1, const T* Bi2,
+                                                        const T* Bi3, T* Bo1, T* Bo2, T* Bo3, Mesh m,
                                                         Taps<T, W> ce, T hy, T hz) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
@@ -55,9 +57,10 @@ __global__ __launch_bounds__(256) void advance_b_kernel(const T* __restrict__ E1
     d1E2 += ce.a[q - 1] * (E2[row + ip] - E2[row + im]);
   }
   const T e1 = E1[c], e2 = E2[c], e3 = E3[c];
-  B1[c] -= hy * (E3[rowjp + i] - e3) - hz * (E2[rowkp + i] - e2);
-  B2[c] -= hz * (E1[rowkp + i] - e1) - d1E3;
-  B3[c] -= d1E2 - hy * (E1[rowjp + i] - e1);
+  const T b1 = Bi1[c], b2 = Bi2[c], b3 = Bi3[c];
+  Bo1[c] = b1 - (hy * (E3[rowjp + i] - e3) - hz * (E2[rowkp + i] - e2));
+  Bo2[c] = b2 - (hz * (E1[rowkp + i] - e1) - d1E3);
+  Bo3[c] = b3 - (d1E2 - hy * (E1[rowjp + i] - e1));
 }
 
 // E <- E + dt (curl_B B - J).  ``cb`` holds dt C^B_j/dx1; ty = dt/dx2,
@@ -110,11 +113,12 @@ Taps<T, W> scaled_taps(const double* C, int M, double scale) {
 dim3 cell_grid(const Mesh& m, int bx) { return dim3((m.n1 + bx - 1) / bx, m.n2, m.n3); }
 
 template <typename T, int W>
-int run_advance_b(const Mesh& m, void* const E[3], void* const B[3], const double* CE, int ME, double h,
-                  hipStream_t s) {
+int run_advance_b(const Mesh& m, void* const E[3], void* const B[3], void* const Bo[3], const double* CE, int ME,
+                  double h, hipStream_t s) {
   const int bx = m.n1 >= 256 ? 256 : m.n1;
   hipLaunchKernelGGL((advance_b_kernel<T, W>), cell_grid(m, bx), dim3(bx), 0, s, (const T*)E[0], (const T*)E[1],
-                     (const T*)E[2], (T*)B[0], (T*)B[1], (T*)B[2], m, scaled_taps<T, W>(CE, ME, h / m.dx1),
+                     (const T*)E[2], (const T*)B[0], (const T*)B[1], (const T*)B[2], (T*)Bo[0], (T*)Bo[1],
+                     (T*)Bo[2], m, scaled_taps<T, W>(CE, ME, h / m.dx1),
                      (T)(h / m.dx2), (T)(m.ndim == 3 ? h / m.dx3 : 0.0));
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "advance_b launch failed");
 }
@@ -132,13 +136,14 @@ int run_advance_e(const Mesh& m, void* const E[3], void* const B[3], void* const
 }
 
 template <typename T>
-int dispatch_b(const Mesh& m, void* const E[3], void* const B[3], const double* CE, int ME, double h, hipStream_t s) {
+int dispatch_b(const Mesh& m, void* const E[3], void* const B[3], void* const Bo[3], const double* CE, int ME, double h,
+               hipStream_t s) {
   switch (round_width(ME)) {
-    case 1: return run_advance_b<T, 1>(m, E, B, CE, ME, h, s);
-    case 2: return run_advance_b<T, 2>(m, E, B, CE, ME, h, s);
-    case 4: return run_advance_b<T, 4>(m, E, B, CE, ME, h, s);
-    case 8: return run_advance_b<T, 8>(m, E, B, CE, ME, h, s);
-    default: return run_advance_b<T, 16>(m, E, B, CE, ME, h, s);
+    case 1: return run_advance_b<T, 1>(m, E, B, Bo, CE, ME, h, s);
+    case 2: return run_advance_b<T, 2>(m, E, B, Bo, CE, ME, h, s);
+    case 4: return run_advance_b<T, 4>(m, E, B, Bo, CE, ME, h, s);
+    case 8: return run_advance_b<T, 8>(m, E, B, Bo, CE, ME, h, s);
+    default: return run_advance_b<T, 16>(m, E, B, Bo, CE, ME, h, s);
   }
 }
 
@@ -676,10 +681,11 @@ int round_width(int m) {
   return kWidths[4];
 }
 
-int launch_advance_b(int prec, const Mesh& m, void* const E[3], void* const B[3], const double* CE, int ME,
-                     double h, void* stream) {
+int launch_advance_b(int prec, const Mesh& m, void* const E[3], void* const B[3], void* const Bout[3],
+                     const double* CE, int ME, double h, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  return prec == PIC_FP64 ? dispatch_b<double>(m, E, B, CE, ME, h, s) : dispatch_b<float>(m, E, B, CE, ME, h, s);
+  return prec == PIC_FP64 ? dispatch_b<double>(m, E, B, Bout, CE, ME, h, s)
+                          : dispatch_b<float>(m, E, B, Bout, CE, ME, h, s);
 }
 
 int launch_sweep(int prec, const Mesh& m, void* const Ein[3], void* const Bin[3], void* const J[3],

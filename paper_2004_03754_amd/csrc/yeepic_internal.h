@@ -32,7 +32,8 @@ struct FieldSet {
   T* B[3];
 };
 
-int launch_advance_b(int prec, const Mesh& m, void* const E[3], void* const B[3],
+// B step out of place: Bout = B - h curl_E E (Bout may be B).
+int launch_advance_b(int prec, const Mesh& m, void* const E[3], void* const B[3], void* const Bout[3],
                      const double* CE, int ME, double h, void* stream);
 int launch_advance_e(int prec, const Mesh& m, void* const E[3], void* const B[3],
                      void* const J[3], const double* CB, int MB, double dt, void* stream);

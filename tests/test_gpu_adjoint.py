@@ -180,6 +180,44 @@ def test_checkpoint_recompute_is_bit_exact(coeffs16):
         assert np.array_equal(a, c)
 
 
+def test_step_to_and_given_next_state(coeffs16):
+    """pic_step_to writes exactly what pic_step_n computes (bit for bit), and
+    an adjoint step given the t^{n+1} state equals one that recomputes it."""
+    CE, CB = coeffs16
+    n = (128, 8, 2)
+    E, B, x, u = _case(n, 51, 60, 2, u_th=0.5)
+    x[2] = np.repeat([0.5, 1.5], 30)
+    Ed, Bd = [dev(e) for e in E], [dev(v) for v in B]
+    grid = b.Grid(Ed, Bd, DX, wl.DT, CE, CB, ndim=2)
+    xa, ua = dev(x), dev(u)
+    Eo, Bo = [torch.empty_like(e) for e in Ed], [torch.empty_like(v) for v in Bd]
+    grid.step_to([b.Particles(xa, ua, q=QM, m=1.0)], Eo, Bo)
+    grid.sync()
+    assert all(np.array_equal(host(a), c) for a, c in zip(Ed + Bd, list(E) + list(B)))  # inputs untouched
+    Ec, Bc = [dev(e) for e in E], [dev(v) for v in B]
+    g2 = b.Grid(Ec, Bc, DX, wl.DT, CE, CB, ndim=2)
+    xb, ub = dev(x), dev(u)
+    g2.step_n([b.Particles(xb, ub, q=QM, m=1.0)], 1)
+    g2.sync()
+    for a, c in zip(Eo + Bo + [xa, ua], Ec + Bc + [xb, ub]):
+        assert torch.equal(a, c)
+    lE, lB, lx, lu = _cotangents(n, 60, 52)
+    outs = []
+    for nxt in (None, (Eo, Bo)):
+        grid.set_fields([dev(e) for e in E], [dev(v) for v in B])
+        lEd, lBd, lxd, lud = [dev(a) for a in lE], [dev(a) for a in lB], dev(lx), dev(lu)
+        gC = [torch.zeros(16, dtype=torch.float64, device="cuda:0") for _ in range(2)]
+        kw = {} if nxt is None else {"next_E": nxt[0], "next_B": nxt[1]}
+        grid.adjoint_step(lEd, lBd, gC[0], gC[1], [b.Particles(dev(x), dev(u), q=QM, m=1.0)],
+                          [b.Particles(lxd, lud, q=QM, m=1.0)], **kw)
+        grid.sync()
+        outs.append([host(a) for a in lEd + lBd + [lxd, lud] + gC])
+    for a, c in zip(*outs):
+        assert _rel(a, c) <= 1e-13
+    grid.close()
+    g2.close()
+
+
 def _run_autograd(CE, CB, E, B, x, u, cfg, w):
     from paper_2004_03754_amd import autograd as pa
     Ef, Bf, xf, uf = pa.run(CE, CB, E, B, x, u, cfg)
