@@ -26,37 +26,53 @@ __device__ __forceinline__ int wrap1(int i, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// Standalone steps: one thread per cell, neighbours read through the caches.
-// In place is safe: a B update reads only E and its own B, and vice versa;
-// the B step may also write a different array than it reads.
+// Standalone steps.  A block of kSB threads owns kSB consecutive x1 cells of
+// one (x2, x3) row; the two components under the wide x1 stencil are staged
+// in LDS once (row segment plus W cells each side, coalesced), everything
+// else is read directly.  In place is safe: a B update reads only E and its
+// own B, and vice versa; the B step may also write a different array.
 // ---------------------------------------------------------------------------
+constexpr int kSB = 256;
+
+template <typename T, int W>
+__device__ __forceinline__ void stage_row(const T* __restrict__ f, T* __restrict__ s, size_t row, int i0, int n1) {
+  for (int t = threadIdx.x; t < kSB + 2 * W; t += kSB) {
+    int i = (i0 - W + t) % n1;
+    i += (i < 0) ? n1 : 0;
+    s[t] = f[row + i];
+  }
+}
 
 // Bout <- Bin - h curl_E E (Bout may be Bin).  ``ce`` holds h C^E_j/dx1;
 // hy = h/dx2, hz = h/dx3.
 template <typename T, int W>
-__global__ __launch_bounds__(256) void advance_b_kernel(const T* __restrict__ E1, const T* __restrict__ E2,
+__global__ __launch_bounds__(kSB) void advance_b_kernel(const T* __restrict__ E1, const T* __restrict__ E2,
                                                         const T* __restrict__ E3, const T* Bi1, const T* Bi2,
                                                         const T* Bi3, T* Bo1, T* Bo2, T* Bo3, Mesh m,
                                                         Taps<T, W> ce, T hy, T hz) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ T s2[kSB + 2 * W], s3[kSB + 2 * W];
+  const int i0 = blockIdx.x * kSB;
+  const int i = i0 + (int)threadIdx.x;
   const int j = blockIdx.y;
   const int k = blockIdx.z;
+  const size_t row = ((size_t)k * m.n2 + j) * m.n1;
+  stage_row<T, W>(E2, s2, row, i0, m.n1);
+  stage_row<T, W>(E3, s3, row, i0, m.n1);
+  __syncthreads();
   if (i >= m.n1) return;
   const int jp = (j + 1 == m.n2) ? 0 : j + 1;
   const int kp = (k + 1 == m.n3) ? 0 : k + 1;
-  const size_t row = ((size_t)k * m.n2 + j) * m.n1;
   const size_t rowjp = ((size_t)k * m.n2 + jp) * m.n1;
   const size_t rowkp = ((size_t)kp * m.n2 + j) * m.n1;
   const size_t c = row + i;
+  const int t = threadIdx.x + W;  // LDS slot of cell i
   T d1E3 = 0, d1E2 = 0;
 #pragma unroll
   for (int q = 1; q <= W; ++q) {
-    const int ip = wrap1(i + q, m.n1);
-    const int im = wrap1(i - q + 1, m.n1);
-    d1E3 += ce.a[q - 1] * (E3[row + ip] - E3[row + im]);
-    d1E2 += ce.a[q - 1] * (E2[row + ip] - E2[row + im]);
+    d1E3 += ce.a[q - 1] * (s3[t + q] - s3[t - q + 1]);
+    d1E2 += ce.a[q - 1] * (s2[t + q] - s2[t - q + 1]);
   }
-  const T e1 = E1[c], e2 = E2[c], e3 = E3[c];
+  const T e1 = E1[c], e2 = s2[t], e3 = s3[t];
   const T b1 = Bi1[c], b2 = Bi2[c], b3 = Bi3[c];
   Bo1[c] = b1 - (hy * (E3[rowjp + i] - e3) - hz * (E2[rowkp + i] - e2));
   Bo2[c] = b2 - (hz * (E1[rowkp + i] - e1) - d1E3);
@@ -66,30 +82,34 @@ __global__ __launch_bounds__(256) void advance_b_kernel(const T* __restrict__ E1
 // E <- E + dt (curl_B B - J).  ``cb`` holds dt C^B_j/dx1; ty = dt/dx2,
 // tz = dt/dx3; J may be null.
 template <typename T, int W>
-__global__ __launch_bounds__(256) void advance_e_kernel(T* __restrict__ E1, T* __restrict__ E2, T* __restrict__ E3,
+__global__ __launch_bounds__(kSB) void advance_e_kernel(T* __restrict__ E1, T* __restrict__ E2, T* __restrict__ E3,
                                                         const T* __restrict__ B1, const T* __restrict__ B2,
                                                         const T* __restrict__ B3, const T* __restrict__ J1,
                                                         const T* __restrict__ J2, const T* __restrict__ J3,
                                                         Mesh m, Taps<T, W> cb, T ty, T tz, T dt) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ T s2[kSB + 2 * W], s3[kSB + 2 * W];
+  const int i0 = blockIdx.x * kSB;
+  const int i = i0 + (int)threadIdx.x;
   const int j = blockIdx.y;
   const int k = blockIdx.z;
+  const size_t row = ((size_t)k * m.n2 + j) * m.n1;
+  stage_row<T, W>(B2, s2, row, i0, m.n1);
+  stage_row<T, W>(B3, s3, row, i0, m.n1);
+  __syncthreads();
   if (i >= m.n1) return;
   const int jm = (j == 0) ? m.n2 - 1 : j - 1;
   const int km = (k == 0) ? m.n3 - 1 : k - 1;
-  const size_t row = ((size_t)k * m.n2 + j) * m.n1;
   const size_t rowjm = ((size_t)k * m.n2 + jm) * m.n1;
   const size_t rowkm = ((size_t)km * m.n2 + j) * m.n1;
   const size_t c = row + i;
+  const int t = threadIdx.x + W;
   T d1B3 = 0, d1B2 = 0;
 #pragma unroll
   for (int q = 1; q <= W; ++q) {
-    const int ip = wrap1(i + q - 1, m.n1);
-    const int im = wrap1(i - q, m.n1);
-    d1B3 += cb.a[q - 1] * (B3[row + ip] - B3[row + im]);
-    d1B2 += cb.a[q - 1] * (B2[row + ip] - B2[row + im]);
+    d1B3 += cb.a[q - 1] * (s3[t + q - 1] - s3[t - q]);
+    d1B2 += cb.a[q - 1] * (s2[t + q - 1] - s2[t - q]);
   }
-  const T b1 = B1[c], b2 = B2[c], b3 = B3[c];
+  const T b1 = B1[c], b2 = s2[t], b3 = s3[t];
   T c1 = ty * (b3 - B3[rowjm + i]) - tz * (b2 - B2[rowkm + i]);
   T c2 = tz * (b1 - B1[rowkm + i]) - d1B3;
   T c3 = d1B2 - ty * (b1 - B1[rowjm + i]);
@@ -115,7 +135,7 @@ dim3 cell_grid(const Mesh& m, int bx) { return dim3((m.n1 + bx - 1) / bx, m.n2, 
 template <typename T, int W>
 int run_advance_b(const Mesh& m, void* const E[3], void* const B[3], void* const Bo[3], const double* CE, int ME,
                   double h, hipStream_t s) {
-  const int bx = m.n1 >= 256 ? 256 : m.n1;
+  const int bx = kSB;
   hipLaunchKernelGGL((advance_b_kernel<T, W>), cell_grid(m, bx), dim3(bx), 0, s, (const T*)E[0], (const T*)E[1],
                      (const T*)E[2], (const T*)B[0], (const T*)B[1], (const T*)B[2], (T*)Bo[0], (T*)Bo[1],
                      (T*)Bo[2], m, scaled_taps<T, W>(CE, ME, h / m.dx1),
@@ -126,7 +146,7 @@ int run_advance_b(const Mesh& m, void* const E[3], void* const B[3], void* const
 template <typename T, int W>
 int run_advance_e(const Mesh& m, void* const E[3], void* const B[3], void* const J[3], const double* CB, int MB,
                   double dt, hipStream_t s) {
-  const int bx = m.n1 >= 256 ? 256 : m.n1;
+  const int bx = kSB;
   hipLaunchKernelGGL((advance_e_kernel<T, W>), cell_grid(m, bx), dim3(bx), 0, s, (T*)E[0], (T*)E[1], (T*)E[2],
                      (const T*)B[0], (const T*)B[1], (const T*)B[2], (const T*)(J ? J[0] : nullptr),
                      (const T*)(J ? J[1] : nullptr), (const T*)(J ? J[2] : nullptr), m,
