@@ -121,9 +121,13 @@ __global__ __launch_bounds__(256) void tile_scatter_kernel(const double* __restr
   if (id) sid[q] = id[p];
 }
 
-template <typename T>
-__device__ __forceinline__ void lds_add(T* p, double v) {
-  atomicAdd(p, (T)v);
+// The tile's current is accumulated in LDS as 64-bit fixed point: integer
+// LDS adds are an order of magnitude faster than float ones on this part,
+// and the sum is exact.  ``scale`` = 2^S maps the largest single contribution
+// |q w dx_d/dt| to 2^47, which leaves room for 2^15 such contributions per
+// node and rounds each one to 2^-47 of the largest.
+__device__ __forceinline__ void lds_add(unsigned long long* p, double v, double scale) {
+  atomicAdd(p, (unsigned long long)llrint(v * scale));
 }
 
 template <typename T, int PUSH>
@@ -132,9 +136,11 @@ __global__ __launch_bounds__(256) void tile_push_kernel(
     const T* __restrict__ B2, const T* __restrict__ B3, T* __restrict__ J1, T* __restrict__ J2, T* __restrict__ J3,
     Mesh m, TileGeom tg, const int* __restrict__ offsets, const double* sx1, const double* sx2, const double* sx3,
     const double* su1, const double* su2, const double* su3, const int64_t* sid, double* dx1, double* dx2,
-    double* dx3, double* du1, double* du2, double* du3, int64_t* did, double qm, double qw, double dt) {
+    double* dx3, double* du1, double* du2, double* du3, int64_t* did, double qm, double qw, double dt,
+    double scale, double unscale) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  T* jl = reinterpret_cast<T*>(lds_raw);  // current tile, 3 x r0 r1 r2
+  // current tile, 3 x r0 r1 r2, fixed point (see lds_add)
+  unsigned long long* jl = reinterpret_cast<unsigned long long*>(lds_raw);
   const int r0 = tg.r[0], r1 = tg.r[1], r2 = tg.r[2];
   const int R = r0 * r1 * r2;
   const int tile = blockIdx.x;
@@ -183,7 +189,7 @@ __global__ __launch_bounds__(256) void tile_push_kernel(
     if (inside) {
       const int o = (rel[2] * r1 + rel[1]) * r0 + rel[0];
       esirkepov3(sh[0], sh[1], sh[2], c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
-        lds_add(&jl[comp * R + o + (c * r1 + b) * r0 + a], v);
+        lds_add(&jl[comp * R + o + (c * r1 + b) * r0 + a], v, scale);
       });
     } else {
       esirkepov3(sh[0], sh[1], sh[2], c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
@@ -196,8 +202,9 @@ __global__ __launch_bounds__(256) void tile_push_kernel(
   __syncthreads();
   // flush: one global atomic per non-zero LDS node
   for (int i = threadIdx.x; i < 3 * R; i += blockDim.x) {
-    const T v = jl[i];
-    if (v == (T)0) continue;
+    const long long acc = (long long)jl[i];
+    if (acc == 0) continue;
+    const T v = (T)((double)acc * unscale);
     const int comp = i / R;
     const int q = i - comp * R;
     const int a = q % r0, b = (q / r0) % r1, c = q / (r0 * r1);
@@ -212,18 +219,22 @@ template <typename T>
 int run_tile_push(const Mesh& m, const TileGeom& tg, void* const E[3], void* const B[3], void* const J[3],
                   const int* offsets, const pic_particles& src, const pic_particles& dst, int pusher, double dt,
                   hipStream_t s) {
-  const size_t lds = sizeof(T) * 3 * (size_t)tg.r[0] * tg.r[1] * tg.r[2];
+  const size_t lds = sizeof(unsigned long long) * 3 * (size_t)tg.r[0] * tg.r[1] * tg.r[2];
   if (lds > 160 * 1024) return set_error(PIC_EUNSUPPORTED, "plasma tile needs %zu bytes of LDS", lds);
   auto k = pusher == PIC_PUSH_BORIS ? tile_push_kernel<T, PIC_PUSH_BORIS> : tile_push_kernel<T, PIC_PUSH_ANALYTIC>;
   if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return set_error(PIC_EHIP, "tile push: cannot reserve %zu bytes of LDS", lds);
   const double qm = src.q / src.m, qw = src.q * src.w;
+  // fixed-point scale of the LDS current (see lds_add)
+  const double cmax = std::fabs(qw) * std::fmax(m.dx1, std::fmax(m.dx2, m.dx3)) / dt;
+  const int S = cmax > 0 ? 47 - (int)std::ceil(std::log2(cmax)) : 0;
+  const double scale = std::ldexp(1.0, S), unscale = std::ldexp(1.0, -S);
 #define YP_TP(PUSH)                                                                                               \
   hipLaunchKernelGGL((tile_push_kernel<T, PUSH>), dim3(tg.ntiles), dim3(256), lds, s, (const T*)E[0],          \
                      (const T*)E[1], (const T*)E[2], (const T*)B[0], (const T*)B[1], (const T*)B[2], (T*)J[0],  \
                      (T*)J[1], (T*)J[2], m, tg, offsets, src.x[0], src.x[1], src.x[2], src.u[0], src.u[1],     \
                      src.u[2], src.id, dst.x[0], dst.x[1], dst.x[2], dst.u[0], dst.u[1], dst.u[2], dst.id, qm, qw, \
-                     dt)
+                     dt, scale, unscale)
   if (pusher == PIC_PUSH_BORIS) YP_TP(PIC_PUSH_BORIS); else YP_TP(PIC_PUSH_ANALYTIC);
 #undef YP_TP
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "tile push launch failed");
