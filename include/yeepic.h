@@ -181,7 +181,7 @@ int pic_step_n(pic_grid *g, pic_particles *const *species, int nspecies, int nst
  * adjoint checkpoints) without copying them. */
 int pic_step_to(pic_grid *g, pic_particles *const *species, int nspecies, int pusher,
                 void *const Eout[3], void *const Bout[3]);
-/* Steps between particle re-sorts in pic_step_n (1..64, default 4); the
+/* Steps between particle re-sorts in pic_step_n (1..64, default 3); the
  * on-chip current tile grows with the interval (|v| < c bounds the drift). */
 int pic_set_sort_interval(pic_grid *g, int steps);
 

@@ -42,7 +42,7 @@ struct pic_grid {
   int* d_flag = nullptr;
   double* xo[3] = {nullptr, nullptr, nullptr};  // x^n scratch of the unsorted deposit path (grow-only)
   int64_t xo_cap = 0;
-  int sort_every = 4;
+  int sort_every = 3;  // 3: the 64-bit tile current then fits three workgroups per CU
   std::vector<SortState> sorts;
   double* partial = nullptr;  // per-block partial sums of the coefficient gradients
   int64_t partial_cap = 0;

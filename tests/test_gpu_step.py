@@ -26,7 +26,7 @@ def _by_id(t, ids):
 def test_step_n_plasma(pusher, nsteps, prec, coeffs16):
     """Config-3 physics at a small size: laser + thermal plasma, push,
     Esirkepov deposit and fused sweep per step (Sec. 3.3 ordering).  The GPU
-    sorts the particles by tile (re-sorting every 4 steps, so 9 steps cross
+    sorts the particles by tile (re-sorting every 3 steps, so 9 steps cross
     two re-sorts); they are matched to the oracle's through their ids.  FP64
     to 1e-11; FP32 fields to 1e-5 (fields) with FP64 particles (momenta
     1e-6: FP32 field values differ from the oracle's FP64 ones)."""
