@@ -218,12 +218,20 @@ __device__ __forceinline__ void analytic(double u[3], const double E[3], const d
     if (fin && fabs(f) <= 1e-16 * fabs(dt)) break;
     // keep the root bracketed; a non-finite value lies beyond it, away from 0
     if (fin ? f > 0.0 : dt > 0.0) hi = tau; else lo = tau;
-    // Newton on log(t/dt): where t grows exponentially log t is close to
-    // linear, and for a particle accelerated from rest it is concave, so the
-    // steps do not overshoot (a plain Newton step on the steep, convex t does,
-    // far past the root); the bracket guards every other case
+    // Far from the root (t/dt outside (1/2, 2)) the step is Newton on
+    // log(t/dt): where t grows exponentially log t is close to linear, and for
+    // a particle accelerated from rest it is concave, so the step does not
+    // overshoot (a plain Newton step on the steep, convex t does, far past the
+    // root).  Near the root plain Newton is as fast and needs no logarithm:
+    // from t = dt/2 it reaches at most e/2 dt.  The bracket guards the rest.
     const double ratio = t / dt;
-    double nx = (fin && ratio > 0.0) ? tau - log(ratio) * (t / g) : 0.5 * (lo + hi);
+    double nx;
+    if (!fin || !(ratio > 0.0))
+      nx = 0.5 * (lo + hi);
+    else if (ratio > 0.5 && ratio < 2.0)
+      nx = tau - f / g;
+    else
+      nx = tau - log(ratio) * (t / g);
     if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
     const bool small = fabs(nx - tau) <= 1e-15 * fabs(tau);
     tau = nx;
