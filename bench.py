@@ -354,6 +354,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=2048,
                     help="steps of the differentiated 2D batch run (checkpoint every 64)")
     ap.add_argument("--adjoint-only", action="store_true", help="run only the adjoint workload")
+    ap.add_argument("--plasma-only", action="store_true", help="run only the plasma workload")
+    ap.add_argument("--plasma-steps", type=int, default=10, help="timed steps of the plasma workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args()
@@ -379,6 +381,9 @@ def main():
     CB = b.design_coeffs(16, r, "B")
     if args.adjoint_only:
         print(json.dumps({"adjoint_2d_2048x256_x16": run_adjoint(torch, b, wl, CE, CB, steps=args.adjoint_steps)}))
+        return
+    if args.plasma_only:
+        print(json.dumps({"plasma_512x256x256": run_plasma(torch, b, wl, CE, CB, steps=args.plasma_steps)}))
         return
     L = wl.LAMBDA0
     n = (1024, 256, 256)
@@ -429,7 +434,7 @@ def main():
             "speedup_vs_fp64_step": main_run["ms_step"] / fp32["ms_step"],
             "speedup_vs_fp64_sweep": main_run["ms_sweep"] / fp32["ms_sweep"]}
         res["plane_wave_2048x512x512"] = run_plane_wave(torch, b, wl, CE, CB, steps=20)
-        res["plasma_512x256x256"] = run_plasma(torch, b, wl, CE, CB, steps=10)
+        res["plasma_512x256x256"] = run_plasma(torch, b, wl, CE, CB, steps=args.plasma_steps)
         res["adjoint_2d_2048x256_x16"] = run_adjoint(torch, b, wl, CE, CB, steps=args.adjoint_steps)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline()
