@@ -5,8 +5,9 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The forward here restates, operation for operation, the NumPy oracle's field
 sweep (Eq. maxwell with the App. B operators), linear-shape gather (App. A),
-Boris push (Sec. 1) and leapfrog position update (Sec. 4.1); tests pin it to
-the NumPy oracle's values.  Its autograd gradient is then the plain
+Boris and exact pushes (Sec. 1) and leapfrog position update (Sec. 4.1);
+tests pin it to the NumPy oracle's values.  The exact push's root tau* of
+t(tau) = dt is differentiated implicitly (see ``analytic``).  Its autograd gradient is then the plain
 definition of the adjoint (the transposed Jacobian applied to a cotangent),
 against which the GPU's hand-written adjoint is compared.
 
@@ -121,6 +122,73 @@ def boris(u, Ep, Bp, qm, dt):
     return upl + eps * Ep
 
 
+def field_tensor(Ep, Bp):
+    """The 4x4 field matrix Lambda(E, B) acting on (gamma, u), per particle:
+    shape (np, 4, 4) (Sec. 1, the exact pusher's equation of motion)."""
+    E1, E2, E3 = Ep
+    B1, B2, B3 = Bp
+    z = torch.zeros_like(E1)
+    rows = [torch.stack([z, E1, E2, E3], -1), torch.stack([E1, z, B3, -B2], -1),
+            torch.stack([E2, -B3, z, B1], -1), torch.stack([E3, B2, -B1, z], -1)]
+    return torch.stack(rows, -2)
+
+
+def _exp_and_integral(F, tau):
+    """expm(F tau) and int_0^tau expm(F s) ds from the 8x8 block exponential."""
+    n = F.shape[0]
+    aug = torch.zeros((n, 8, 8), dtype=F.dtype)
+    aug[:, :4, :4] = F * tau[:, None, None]
+    aug[:, :4, 4:] = torch.eye(4, dtype=F.dtype)[None] * tau[:, None, None]
+    ex = torch.linalg.matrix_exp(aug)
+    return ex[:, :4, :4], ex[:, :4, 4:]
+
+
+def analytic(u, Ep, Bp, qm, dt, max_iter=20000):
+    """Exact push for fields constant over the step (Sec. 1, Sec. 4.1): the
+    proper-time exponential with t(tau*) = dt.  tau* is found without
+    gradients (bracketed Newton); the returned momentum uses
+    tau = tau* - (t(tau*) - dt)/gamma(tau*), whose value is tau* and whose
+    derivative is the implicit-function one, -(dt/dtheta)/gamma."""
+    F = qm * field_tensor(Ep, Bp)
+    g0 = torch.sqrt(1.0 + torch.sum(u * u, 0))
+    U0 = torch.cat([g0[None], u], 0).T  # (np, 4)
+    with torch.no_grad():
+        Fd, U0d = F.detach(), U0.detach()
+        n = U0d.shape[0]
+        lo = torch.full((n,), min(0.0, dt), dtype=u.dtype)
+        hi = torch.full((n,), max(0.0, dt), dtype=u.dtype)
+        tau = dt / U0d[:, 0]
+        done = torch.zeros(n, dtype=torch.bool)
+        for _ in range(max_iter):
+            ex, it = _exp_and_integral(Fd, tau)
+            tval = torch.einsum("pj,pj->p", it[:, 0, :], U0d)
+            gam = torch.einsum("pj,pj->p", ex[:, 0, :], U0d)
+            f = tval - dt
+            finite = torch.isfinite(f) & torch.isfinite(gam)
+            hit = finite & (torch.abs(f) <= 1e-16 * abs(dt))
+            over = torch.where(finite, f > 0, torch.full_like(finite, dt > 0))
+            hi = torch.where(over, tau, hi)
+            lo = torch.where(over, lo, tau)
+            newt = tau - f / gam
+            bad = ~finite | ~((newt > lo) & (newt < hi))
+            nxt = torch.where(bad, 0.5 * (lo + hi), newt)
+            small = torch.abs(nxt - tau) <= 1e-15 * torch.abs(tau)
+            tau = torch.where(done | hit, tau, nxt)
+            done |= hit | small
+            if bool(done.all()):
+                break
+        if not bool(done.all()):
+            raise RuntimeError("exact pusher: t(tau) = dt not solved")
+        ex, _ = _exp_and_integral(Fd, tau)
+        gam_star = torch.einsum("pj,pj->p", ex[:, 0, :], U0d)
+    _, it = _exp_and_integral(F, tau)
+    t_star = torch.einsum("pj,pj->p", it[:, 0, :], U0)
+    tau_g = tau - (t_star - dt) / gam_star
+    ex, _ = _exp_and_integral(F, tau_g)
+    U = torch.einsum("pij,pj->pi", ex, U0)
+    return U[:, 1:].T
+
+
 def advance_position(x, u, dt, L, ndim):
     """x + dt u/gamma, then the periodic wrap of the NumPy oracle (a
     piecewise-constant shift, so its derivative is the identity)."""
@@ -139,21 +207,21 @@ def advance_position(x, u, dt, L, ndim):
     return torch.stack(rows)
 
 
-def step(E, B, x, u, CE, CB, dx, dt, qm, L, ndim):
-    """One vacuum step with test particles: gather + Boris + position, sweep."""
+def step(E, B, x, u, CE, CB, dx, dt, qm, L, ndim, pusher="boris"):
+    """One vacuum step with test particles: gather + push + position, sweep."""
     Ep, Bp = gather(E, B, x, dx, ndim)
-    u = boris(u, Ep, Bp, qm, dt)
+    u = boris(u, Ep, Bp, qm, dt) if pusher == "boris" else analytic(u, Ep, Bp, qm, dt)
     x = advance_position(x, u, dt, L, ndim)
     E, B = sweep(E, B, CE, CB, dx, dt)
     return E, B, x, u
 
 
-def run(E, B, x, u, CE, CB, dx, dt, qm, nsteps, ndim):
+def run(E, B, x, u, CE, CB, dx, dt, qm, nsteps, ndim, pusher="boris"):
     """``nsteps`` calls of ``step`` on a periodic mesh."""
     n3, n2, n1 = E[0].shape
     L = [n1 * dx[0], n2 * dx[1], n3 * dx[2]]
     for _ in range(nsteps):
-        E, B, x, u = step(E, B, x, u, CE, CB, dx, dt, qm, L, ndim)
+        E, B, x, u = step(E, B, x, u, CE, CB, dx, dt, qm, L, ndim, pusher)
     return E, B, x, u
 
 

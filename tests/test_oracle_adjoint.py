@@ -72,6 +72,41 @@ def test_curl_transposition(ndim, n):
     assert abs(lhs) > 1e-3
 
 
+def test_torch_exact_pusher_matches_numpy_and_differences():
+    """The torch exact push equals the NumPy oracle's (weak to strong fields,
+    including near-null crossed fields of 1e4), and its implicit-function
+    gradient with respect to u, E and B matches central differences."""
+    from oracle import particles as pt
+    g = np.random.default_rng(11)
+    n = 12
+    E = g.standard_normal((3, n)) * np.repeat([0.3, 5.0, 50.0], 4)
+    B = g.standard_normal((3, n)) * np.repeat([0.3, 5.0, 50.0], 4)
+    E[:, -1] = [0, 1e4, 0]
+    B[:, -1] = [0, 0, 0.99e4]
+    u = g.standard_normal((3, n)) * 2
+    u[:, -1] = 0
+    ref = pt.analytic(u, E, B, -1.0, wl.DT)
+    got = ad.analytic(_t(u), _t(E), _t(B), -1.0, wl.DT).detach().numpy()
+    assert np.max(np.abs(got - ref) / np.maximum(1.0, np.abs(ref))) <= 1e-12
+    lam = _t(g.standard_normal((3, n)))
+    leaves = [_t(u).requires_grad_(), _t(E).requires_grad_(), _t(B).requires_grad_()]
+    L = torch.sum(ad.analytic(*leaves, -1.0, wl.DT) * lam)
+    grads = torch.autograd.grad(L, leaves)
+    h = 1e-6
+    for which in range(3):
+        for (d, p) in [(0, 0), (1, 5), (2, 9), (1, n - 1)]:
+            vals = []
+            for sgn in (1, -1):
+                args = [_t(u), _t(E), _t(B)]
+                step = h * max(1.0, abs(float(args[which][d, p])))
+                args[which][d, p] += sgn * step
+                with torch.no_grad():
+                    vals.append(float(torch.sum(ad.analytic(*args, -1.0, wl.DT) * lam)))
+            fd = (vals[0] - vals[1]) / (2 * step)
+            gr = float(grads[which][d, p])
+            assert abs(fd - gr) <= 1e-5 * max(1.0, abs(fd)), (which, d, p, fd, gr)
+
+
 def _loss(E, B, x, u, CE, CB, nsteps, ndim, w):
     Ef, Bf, xf, uf = ad.run(E, B, x, u, CE, CB, DX, wl.DT, -1.0, nsteps, ndim)
     # a mix of the two losses plus position and B terms so every cotangent is non-zero
