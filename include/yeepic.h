@@ -186,8 +186,8 @@ int pic_step_to(pic_grid *g, pic_particles *const *species, int nspecies, int pu
 int pic_set_sort_interval(pic_grid *g, int steps);
 
 /* ---- adjoint of one vacuum step ---------------------------------------------
- * Reverse mode of one step of pic_step_n without deposit and with the Boris
- * pusher: gather (App. A) + push (Sec. 1) + position update (Sec. 4.1) of
+ * Reverse mode of one step of pic_step_n without deposit, with the Boris or
+ * the exact pusher: gather (App. A) + push (Sec. 1) + position update (Sec. 4.1) of
  * each species, then the field sweep of Eq. maxwell with the App. B
  * operators.  The forward state at t^n is read, not modified: the grid's
  * fields E^n, B^n and species[s] (x^n, u^{n-1/2}).  lambda[s] has the same
@@ -203,8 +203,10 @@ int pic_set_sort_interval(pic_grid *g, int steps);
  * in the grid's second field set, else it first recomputes the forward sweep
  * there.  The position wrap is a constant shift (derivative
  * the identity); at a cell face the shape function has a kink, and the
- * derivative taken is the one of the cell the particle is in.
- * PIC_EUNSUPPORTED for FP32-field grids and the analytic pusher; the
+ * derivative taken is the one of the cell the particle is in.  The exact
+ * pusher's proper time tau* solves t(tau) = dt; its derivative is taken
+ * implicitly, d tau*/d theta = -(d t/d theta at fixed tau)/gamma(tau*).
+ * PIC_EUNSUPPORTED for FP32-field grids; PIC_EINVAL for another pusher; the
  * coefficient reduction allocates a scratch of 16 doubles per 256 cells of
  * x1 row at the first call (PIC_ENOMEM if that fails).  Scatter into lE, lB
  * uses atomics, so the field cotangents vary in the last bits between runs. */

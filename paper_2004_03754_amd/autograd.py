@@ -1,7 +1,7 @@
 """Differentiable vacuum PIC run: a torch.autograd.Function over the HIP
 library's forward step loop and its hand-written adjoint.
 
-Forward: ``nsteps`` steps of gather + Boris push + position update + fused
+Forward: ``nsteps`` steps of gather + push (Boris or exact) + position update + fused
 field sweep (pic_step_n), keeping a checkpoint of the state (E, B, x, u)
 every ``K`` steps.  Backward: the segments are walked in reverse; each one is
 recomputed from its checkpoint one step at a time (pic_step_to, each state
@@ -27,12 +27,13 @@ from . import binding as b
 class RunConfig:
     """Grid and run constants: cell sizes, time step, number of dimensions
     (2D grids may stack independent planes along n3), species constants,
-    step count and checkpoint interval."""
+    step count, checkpoint interval and pusher ("boris" or "analytic")."""
 
-    def __init__(self, dx, dt, nsteps, K=64, ndim=3, q=-1.0, m=1.0, w=1.0):
+    def __init__(self, dx, dt, nsteps, K=64, ndim=3, q=-1.0, m=1.0, w=1.0, pusher="boris"):
         self.dx, self.dt, self.nsteps, self.K = tuple(dx), float(dt), int(nsteps), int(K)
         self.ndim, self.q, self.m, self.w = int(ndim), float(q), float(m), float(w)
-        assert self.nsteps >= 0 and self.K >= 1
+        self.pusher = str(pusher)
+        assert self.nsteps >= 0 and self.K >= 1 and self.pusher in b.PUSHERS
 
 
 def _clone_state(E, B, x, u):
@@ -55,7 +56,7 @@ class PICRun(torch.autograd.Function):
         checkpoints = []
         for s in range(0, cfg.nsteps, cfg.K):
             checkpoints.append(_clone_state(E, B, x, u))
-            grid.step_n([p] if p.np else [], min(cfg.K, cfg.nsteps - s), pusher="boris")
+            grid.step_n([p] if p.np else [], min(cfg.K, cfg.nsteps - s), pusher=cfg.pusher)
         grid.close()
         ctx.cfg, ctx.ce, ctx.cb, ctx.checkpoints = cfg, ce, cb, checkpoints
         ctx.coef_meta = (CE.dtype, CE.device, CE.shape[0])
@@ -100,7 +101,7 @@ class PICRun(torch.autograd.Function):
                 cur[3].copy_(prev[3])
                 grid.set_fields(prev[0], prev[1])
                 p = b.Particles(cur[2], cur[3], q=cfg.q, m=cfg.m, w=cfg.w)
-                grid.step_to([p] if p.np else [], cur[0], cur[1], pusher="boris")
+                grid.step_to([p] if p.np else [], cur[0], cur[1], pusher=cfg.pusher)
             # reverse the segment (the particle adjoint needs x, u at t^n: the
             # previous buffer's, since step_to advanced the copies)
             for i in reversed(range(n)):
@@ -108,7 +109,7 @@ class PICRun(torch.autograd.Function):
                 grid.set_fields(st[0], st[1])
                 p = b.Particles(st[2], st[3], q=cfg.q, m=cfg.m, w=cfg.w)
                 if p.np:
-                    grid.adjoint_step(lE, lB, gCE, gCB, [p], [lam], next_E=nx[0], next_B=nx[1])
+                    grid.adjoint_step(lE, lB, gCE, gCB, [p], [lam], pusher=cfg.pusher, next_E=nx[0], next_B=nx[1])
                 else:
                     grid.adjoint_step(lE, lB, gCE, gCB, next_E=nx[0], next_B=nx[1])
         grid.sync()

@@ -17,8 +17,8 @@
 //   (difference of the stage input): coef_partial + coef_finalize, a
 //   deterministic two-pass reduction (per-block partial sums, then one block
 //   per coefficient).
-// * the particle adjoint: reverse of gather (App. A), Boris push (Sec. 1) and
-//   the position update (Sec. 4.1).  The gather's reverse scatters the
+// * the particle adjoint: reverse of gather (App. A), the Boris or exact push
+//   (Sec. 1) and the position update (Sec. 4.1).  The gather's reverse scatters the
 //   cotangent of each interpolated field value into the field cotangent with
 //   the same linear-shape weights, and adds the weights' x derivative to the
 //   position cotangent.
@@ -152,6 +152,167 @@ __device__ __forceinline__ void boris_vjp(const double u[3], const double E[3], 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Reverse of the exact push, by forward-mode differentiation one input
+// direction at a time (9 directions: u, E, B).  A dual number carries a value
+// and one directional derivative; the exponential's coefficients are
+// re-evaluated in dual arithmetic along the same branches as the forward.
+// The root tau* of t(tau) = dt depends on the inputs implicitly:
+// d tau*/d theta = -(d t/d theta at fixed tau)/gamma(tau*).
+// ---------------------------------------------------------------------------
+struct Dual {
+  double v, d;
+};
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a) { return {-a.v, -a.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Dual operator*(double a, Dual b) { return {a * b.v, a * b.d}; }
+__device__ __forceinline__ Dual operator+(Dual a, double b) { return {a.v + b, a.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, double b) { return {a.v * b, a.d * b}; }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+  const double q = a.v / b.v;
+  return {q, (a.d - q * b.d) / b.v};
+}
+__device__ __forceinline__ Dual dsqrt(Dual a) {
+  const double r = sqrt(a.v);
+  return {r, r > 0 ? a.d / (2 * r) : 0.0};
+}
+__device__ __forceinline__ Dual dsinh(Dual a) { return {sinh(a.v), cosh(a.v) * a.d}; }
+__device__ __forceinline__ Dual dsin(Dual a) { return {sin(a.v), cos(a.v) * a.d}; }
+
+struct ExpCoefD {
+  Dual a0, a1, a2, a3, A1, A3;
+};
+
+// exp_coef in dual arithmetic (same branches, chosen by the values)
+__device__ __forceinline__ ExpCoefD exp_coef_dual(Dual k2, Dual w2, Dual tau) {
+  const Dual t2 = tau * tau;
+  const Dual X = k2 * t2, Y = w2 * t2;
+  ExpCoefD e;
+  if (X.v <= 1.0 && Y.v <= 1.0) {
+    const Dual Z = -Y;
+    Dual h = {1.0, 0.0}, zk = {1.0, 0.0};
+    Dual G[7];
+    for (int m = 0; m < 7; ++m) G[m] = {0.0, 0.0};
+    double f2 = 1.0 / 2, f3 = 1.0 / 6, f4 = 1.0 / 24, f5 = 1.0 / 120, f6 = 1.0 / 720;
+    for (int k = 0; k < 14; ++k) {
+      G[2] = G[2] + f2 * h;
+      G[3] = G[3] + f3 * h;
+      G[4] = G[4] + f4 * h;
+      G[5] = G[5] + f5 * h;
+      G[6] = G[6] + f6 * h;
+      zk = zk * Z;
+      h = X * h + zk;
+      const double n2 = 2.0 * k + 2;
+      f2 /= (n2 + 1) * (n2 + 2);
+      f3 /= (n2 + 2) * (n2 + 3);
+      f4 /= (n2 + 3) * (n2 + 4);
+      f5 /= (n2 + 4) * (n2 + 5);
+      f6 /= (n2 + 5) * (n2 + 6);
+    }
+    const Dual XY = X * Y;
+    e.a0 = XY * G[4] + 1.0;
+    e.a1 = tau * (XY * G[5] + 1.0);
+    e.a2 = t2 * G[2];
+    e.a3 = t2 * tau * G[3];
+    e.A1 = t2 * (XY * G[6] + 0.5);
+    e.A3 = t2 * t2 * G[4];
+    return e;
+  }
+  Dual sh, ch1, sn, cs1;
+  if (sqrt(k2.v) * fabs(tau.v) < 1e-4) {
+    sh = tau * (X * (1.0 / 6.0) * (X * (1.0 / 20.0) + 1.0) + 1.0);
+    ch1 = 0.5 * t2 * (X * (1.0 / 12.0) * (X * (1.0 / 30.0) + 1.0) + 1.0);
+  } else {
+    const Dual kap = dsqrt(k2);
+    sh = dsinh(kap * tau) / kap;
+    const Dual s = dsinh(0.5 * (kap * tau)) / kap;
+    ch1 = 2.0 * (s * s);
+  }
+  if (sqrt(w2.v) * fabs(tau.v) < 1e-4) {
+    sn = tau * (-(Y * (1.0 / 6.0) * (-(Y * (1.0 / 20.0)) + 1.0)) + 1.0);
+    cs1 = 0.5 * t2 * (-(Y * (1.0 / 12.0) * (-(Y * (1.0 / 30.0)) + 1.0)) + 1.0);
+  } else {
+    const Dual om = dsqrt(w2);
+    sn = dsin(om * tau) / om;
+    const Dual s = dsin(0.5 * (om * tau)) / om;
+    cs1 = 2.0 * (s * s);
+  }
+  const Dual inv = Dual{1.0, 0.0} / (k2 + w2);
+  const Dual chx = k2 * ch1 + 1.0, cy = -(w2 * cs1) + 1.0;
+  e.a0 = (w2 * chx + k2 * cy) * inv;
+  e.a1 = (w2 * sh + k2 * sn) * inv;
+  e.a2 = (k2 * ch1 + w2 * cs1) * inv;
+  e.a3 = (sh - sn) * inv;
+  e.A1 = (w2 * ch1 + k2 * cs1) * inv;
+  e.A3 = (ch1 - cs1) * inv;
+  return e;
+}
+
+__device__ __forceinline__ void apply_F_dual(const Dual E[3], const Dual B[3], double qm, const Dual v[4], Dual o[4]) {
+  o[0] = qm * (E[0] * v[1] + E[1] * v[2] + E[2] * v[3]);
+  o[1] = qm * (E[0] * v[0] + B[2] * v[2] - B[1] * v[3]);
+  o[2] = qm * (E[1] * v[0] - B[2] * v[1] + B[0] * v[3]);
+  o[3] = qm * (E[2] * v[0] + B[1] * v[1] - B[0] * v[2]);
+}
+
+// Reverse of analytic(): u is the input momentum, lun the cotangent of the
+// output momentum; returns the cotangents of u, E and B.
+__device__ void analytic_vjp(const double u[3], const double E[3], const double B[3], double qm, double dt,
+                             const double lun[3], double lu[3], double lE[3], double lB[3]) {
+  ExactState st;
+  const double tau_s = analytic_solve(u, E, B, qm, dt, st);
+  for (int dir = 0; dir < 9; ++dir) {
+    Dual ud[3], Ed[3], Bd[3];
+    for (int c = 0; c < 3; ++c) {
+      ud[c] = {u[c], dir == c ? 1.0 : 0.0};
+      Ed[c] = {E[c], dir == 3 + c ? 1.0 : 0.0};
+      Bd[c] = {B[c], dir == 6 + c ? 1.0 : 0.0};
+    }
+    const Dual E2 = Ed[0] * Ed[0] + Ed[1] * Ed[1] + Ed[2] * Ed[2];
+    const Dual B2 = Bd[0] * Bd[0] + Bd[1] * Bd[1] + Bd[2] * Bd[2];
+    const Dual EB = Ed[0] * Bd[0] + Ed[1] * Bd[1] + Ed[2] * Bd[2];
+    const double q2 = qm * qm;
+    const Dual P = 0.5 * (E2 - B2);
+    // Q = sqrt(P^2 + EB^2) is homogeneous of degree 2 in the fields: its
+    // derivative vanishes where it does
+    const Dual Q = dsqrt(P * P + EB * EB);
+    Dual k2, w2;
+    if (P.v >= 0) {
+      k2 = q2 * (P + Q);
+      w2 = (P + Q).v > 0 ? q2 * ((EB * EB) / (P + Q)) : Dual{0.0, 0.0};
+    } else {
+      w2 = q2 * (Q - P);
+      k2 = q2 * ((EB * EB) / (Q - P));
+    }
+    Dual U0[4], V1[4], V2[4], V3[4];
+    U0[0] = dsqrt(ud[0] * ud[0] + ud[1] * ud[1] + ud[2] * ud[2] + 1.0);
+    for (int c = 0; c < 3; ++c) U0[c + 1] = ud[c];
+    apply_F_dual(Ed, Bd, qm, U0, V1);
+    apply_F_dual(Ed, Bd, qm, V1, V2);
+    apply_F_dual(Ed, Bd, qm, V2, V3);
+    // lab time and gamma at the root with tau held fixed, then the root's
+    // implicit derivative
+    const ExpCoefD e0 = exp_coef_dual(k2, w2, Dual{tau_s, 0.0});
+    const Dual t = e0.a1 * U0[0] + e0.A1 * V1[0] + e0.a3 * V2[0] + e0.A3 * V3[0];
+    const Dual g = e0.a0 * U0[0] + e0.a1 * V1[0] + e0.a2 * V2[0] + e0.a3 * V3[0];
+    const Dual tau = {tau_s, -t.d / g.v};
+    const ExpCoefD e = exp_coef_dual(k2, w2, tau);
+    double acc = 0;
+    for (int c = 0; c < 3; ++c) {
+      const Dual o = e.a0 * U0[c + 1] + e.a1 * V1[c + 1] + e.a2 * V2[c + 1] + e.a3 * V3[c + 1];
+      acc += o.d * lun[c];
+    }
+    if (dir < 3)
+      lu[dir] = acc;
+    else if (dir < 6)
+      lE[dir - 3] = acc;
+    else
+      lB[dir - 6] = acc;
+  }
+}
+
 // Reverse of one 3D linear-shape interpolation: scatter lv W into lf at the
 // eight nodes and add lv dv/dx to lx.
 __device__ __forceinline__ void interp3_vjp(const double* __restrict__ f, double* lf, const Axis& a,
@@ -206,8 +367,8 @@ struct AdjFields {
 // One thread per particle: reverse of gather + Boris + position update.
 // In: x^n, u^{n-1/2}, lx = dL/dx^{n+1}, lu = dL/du^{n+1/2}.
 // Out: lx = dL/dx^n, lu = dL/du^{n-1/2}; field cotangents accumulated.
-template <int NDIM>
-__global__ __launch_bounds__(256) void adjoint_boris_kernel(AdjFields F, Mesh m, const double* __restrict__ x1,
+template <int NDIM, int PUSH>
+__global__ __launch_bounds__(256) void adjoint_push_kernel(AdjFields F, Mesh m, const double* __restrict__ x1,
                                                             const double* __restrict__ x2,
                                                             const double* __restrict__ x3,
                                                             const double* __restrict__ u1,
@@ -226,7 +387,10 @@ __global__ __launch_bounds__(256) void adjoint_boris_kernel(AdjFields F, Mesh m,
   gather6<double, NDIM>(F.f[0], F.f[1], F.f[2], F.f[3], F.f[4], F.f[5], m, x, E, B);
   // forward push (recomputed) for the position update's Jacobian
   double un[3] = {u[0], u[1], u[2]};
-  boris(un, E, B, qm, dt);
+  if (PUSH == PIC_PUSH_BORIS)
+    boris(un, E, B, qm, dt);
+  else
+    analytic(un, E, B, qm, dt);
   const double gn = sqrt(1.0 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
   double lx[3] = {lx1[p], lx2[p], NDIM == 3 ? lx3[p] : 0.0};
   // x_d' = x_d + dt u'_d/gamma' for d < NDIM (the wrap is a constant shift)
@@ -236,7 +400,10 @@ __global__ __launch_bounds__(256) void adjoint_boris_kernel(AdjFields F, Mesh m,
   double lun[3] = {lu1[p], lu2[p], lu3[p]};
   for (int d = 0; d < 3; ++d) lun[d] += (d < NDIM ? ig * lx[d] : 0.0) - ig3 * un[d] * ux;
   double lu[3], lE[3], lB[3];
-  boris_vjp(u, E, B, qm, dt, lun, lu, lE, lB);
+  if (PUSH == PIC_PUSH_BORIS)
+    boris_vjp(u, E, B, qm, dt, lun, lu, lE, lB);
+  else
+    analytic_vjp(u, E, B, qm, dt, lun, lu, lE, lB);
   // reverse of the gather
   const Axis a0 = axis(x[0], m.idx1, 0.0, m.n1), ah = axis(x[0], m.idx1, 0.5, m.n1);
   const Axis b0 = axis(x[1], m.idx2, 0.0, m.n2), bh = axis(x[1], m.idx2, 0.5, m.n2);
@@ -290,7 +457,7 @@ int launch_coef_grad(const Mesh& m, int form, const double* la, const double* fa
 }
 
 int launch_adjoint_push(const Mesh& m, void* const E[3], void* const B[3], void* const lE[3], void* const lB[3],
-                        const pic_particles& p, const pic_particles& lam, double dt, void* stream) {
+                        const pic_particles& p, const pic_particles& lam, int pusher, double dt, void* stream) {
   if (p.np == 0) return PIC_OK;
   hipStream_t s = (hipStream_t)stream;
   AdjFields F;
@@ -302,12 +469,15 @@ int launch_adjoint_push(const Mesh& m, void* const E[3], void* const B[3], void*
   }
   const dim3 grid((unsigned)((p.np + 255) / 256)), block(256);
   const double qm = p.q / p.m;
-  if (m.ndim == 3)
-    hipLaunchKernelGGL(adjoint_boris_kernel<3>, grid, block, 0, s, F, m, p.x[0], p.x[1], p.x[2], p.u[0], p.u[1],
-                       p.u[2], lam.x[0], lam.x[1], lam.x[2], lam.u[0], lam.u[1], lam.u[2], p.np, qm, dt);
-  else
-    hipLaunchKernelGGL(adjoint_boris_kernel<2>, grid, block, 0, s, F, m, p.x[0], p.x[1], p.x[2], p.u[0], p.u[1],
-                       p.u[2], lam.x[0], lam.x[1], lam.x[2], lam.u[0], lam.u[1], lam.u[2], p.np, qm, dt);
+#define YP_ADJ(ND, PU)                                                                                        \
+  hipLaunchKernelGGL((adjoint_push_kernel<ND, PU>), grid, block, 0, s, F, m, p.x[0], p.x[1], p.x[2], p.u[0], p.u[1], \
+                     p.u[2], lam.x[0], lam.x[1], lam.x[2], lam.u[0], lam.u[1], lam.u[2], p.np, qm, dt)
+  if (m.ndim == 3) {
+    if (pusher == PIC_PUSH_BORIS) YP_ADJ(3, PIC_PUSH_BORIS); else YP_ADJ(3, PIC_PUSH_ANALYTIC);
+  } else {
+    if (pusher == PIC_PUSH_BORIS) YP_ADJ(2, PIC_PUSH_BORIS); else YP_ADJ(2, PIC_PUSH_ANALYTIC);
+  }
+#undef YP_ADJ
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "adjoint push launch failed");
 }
 

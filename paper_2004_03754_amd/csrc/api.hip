@@ -428,7 +428,7 @@ int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* c
                      pic_particles* const* lambda, int nspecies, int pusher) {
   if (!g || !adj) return set_error(PIC_EINVAL, "pic_adjoint_step: NULL argument");
   if (g->prec != PIC_FP64) return set_error(PIC_EUNSUPPORTED, "the adjoint is built for FP64 grids only");
-  if (pusher != PIC_PUSH_BORIS) return set_error(PIC_EUNSUPPORTED, "the adjoint is built for the Boris pusher only");
+  if (pusher != PIC_PUSH_BORIS && pusher != PIC_PUSH_ANALYTIC) return set_error(PIC_EINVAL, "bad pusher");
   if (nspecies < 0) return set_error(PIC_EINVAL, "negative count");
   if (nspecies > 0 && (!species || !lambda)) return set_error(PIC_EINVAL, "species or lambda is NULL");
   for (int c = 0; c < 3; ++c) {
@@ -495,7 +495,7 @@ int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* c
   if (!rc) rc = launch_advance_e(g->prec, m, lE, lB, none, g->CE, g->ME, -0.5 * dt, g->stream);
   // particles: reverse of position update, push and gather at t^n
   for (int s = 0; s < nspecies && !rc; ++s)
-    rc = launch_adjoint_push(m, g->E, g->B, lE, lB, *species[s], *lambda[s], dt, g->stream);
+    rc = launch_adjoint_push(m, g->E, g->B, lE, lB, *species[s], *lambda[s], pusher, dt, g->stream);
   return rc;
 }
 

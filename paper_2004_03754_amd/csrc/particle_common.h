@@ -183,8 +183,17 @@ __device__ __forceinline__ void apply_F(const double E[3], const double B[3], do
   o[3] = qm * (E[2] * v[0] + B[1] * v[1] - B[0] * v[2]);
 }
 
-__device__ __forceinline__ void analytic(double u[3], const double E[3], const double B[3], double qm,
-                                         double dt) {
+// The exact push's state before the exponential: invariants kappa^2,
+// omega^2, U0 = (gamma, u) and F U0, F^2 U0, F^3 U0.
+struct ExactState {
+  double k2, w2;
+  double U0[4], V1[4], V2[4], V3[4];
+};
+
+// Solves t(tau) = dt for the exact push of u in (E, B); returns tau and the
+// state the exponential is applied to.
+__device__ __forceinline__ double analytic_solve(const double u[3], const double E[3], const double B[3], double qm,
+                                                 double dt, ExactState& st) {
   const double E2 = E[0] * E[0] + E[1] * E[1] + E[2] * E[2];
   const double B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
   const double EB = E[0] * B[0] + E[1] * B[1] + E[2] * B[2];
@@ -199,8 +208,16 @@ __device__ __forceinline__ void analytic(double u[3], const double E[3], const d
     w2 = q2 * (Q - P);
     k2 = q2 * (EB * EB) / (Q - P);
   }
-  double U0[4] = {sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]), u[0], u[1], u[2]};
-  double V1[4], V2[4], V3[4];
+  st.k2 = k2;
+  st.w2 = w2;
+  double* U0 = st.U0;
+  double* V1 = st.V1;
+  double* V2 = st.V2;
+  double* V3 = st.V3;
+  U0[0] = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  U0[1] = u[0];
+  U0[2] = u[1];
+  U0[3] = u[2];
   apply_F(E, B, qm, U0, V1);
   apply_F(E, B, qm, V1, V2);
   apply_F(E, B, qm, V2, V3);
@@ -237,8 +254,16 @@ __device__ __forceinline__ void analytic(double u[3], const double E[3], const d
     tau = nx;
     if (small) break;
   }
-  const ExpCoef e = exp_coef(k2, w2, tau);
-  for (int d = 0; d < 3; ++d) u[d] = e.a0 * U0[d + 1] + e.a1 * V1[d + 1] + e.a2 * V2[d + 1] + e.a3 * V3[d + 1];
+  return tau;
+}
+
+__device__ __forceinline__ void analytic(double u[3], const double E[3], const double B[3], double qm,
+                                         double dt) {
+  ExactState st;
+  const double tau = analytic_solve(u, E, B, qm, dt, st);
+  const ExpCoef e = exp_coef(st.k2, st.w2, tau);
+  for (int d = 0; d < 3; ++d)
+    u[d] = e.a0 * st.U0[d + 1] + e.a1 * st.V1[d + 1] + e.a2 * st.V2[d + 1] + e.a3 * st.V3[d + 1];
 }
 
 // periodic wrap of an advanced position (the oracle's rule)

@@ -72,7 +72,7 @@ int coef_partial_blocks(const Mesh& m);
 int launch_coef_grad(const Mesh& m, int form, const double* la, const double* fa, const double* lb,
                      const double* fb, double scale, int M, double* partial, double* g, void* stream);
 int launch_adjoint_push(const Mesh& m, void* const E[3], void* const B[3], void* const lE[3], void* const lB[3],
-                        const pic_particles& p, const pic_particles& lam, double dt, void* stream);
+                        const pic_particles& p, const pic_particles& lam, int pusher, double dt, void* stream);
 
 int launch_check(int prec, const Mesh& m, void* const E[3], void* const B[3],
                  const pic_particles* p, int* d_flag, void* stream);
