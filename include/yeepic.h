@@ -204,8 +204,8 @@ int pic_set_sort_interval(pic_grid *g, int steps);
  * there.  The position wrap is a constant shift (derivative
  * the identity); at a cell face the shape function has a kink, and the
  * derivative taken is the one of the cell the particle is in.  The exact
- * pusher's proper time tau* solves t(tau) = dt; its derivative is taken
- * implicitly, d tau*/d theta = -(d t/d theta at fixed tau)/gamma(tau*).
+ * pusher's proper time tau_r solves t(tau) = dt; its derivative is taken
+ * implicitly: d tau_r / d theta = -(d t / d theta at fixed tau) / gamma(tau_r).
  * PIC_EUNSUPPORTED for FP32-field grids; PIC_EINVAL for another pusher; the
  * coefficient reduction allocates a scratch of 16 doubles per 256 cells of
  * x1 row at the first call (PIC_ENOMEM if that fails).  Scatter into lE, lB

@@ -640,6 +640,388 @@ __global__ __launch_bounds__(NT) void sweep_kernel(const T* __restrict__ iE1, co
 #undef YP_STORE_PLANE
 }
 
+// ---------------------------------------------------------------------------
+// Fused sweep for the Yee Ampere operator (C^B = e1, which the App. B design
+// gives at dt = dx1/2): the same three stages as sweep_kernel, in a layout
+// that holds TY = 8 rows of cells per tile.
+//
+// Only one plane of each stage's input is kept in LDS.  What a stage needs
+// from a neighbouring x3 plane it needs at its own positions, and the thread
+// that owns those positions holds it in registers:
+//   * stage 1 at plane ka needs E1, E2 of plane ka+1: loaded from memory one
+//     plane ahead by the same thread;
+//   * stage 2 at ka needs B^{n+1/2}(ka-1), and stage 3 at ka-1 needs it as
+//     well: the thread re-reads its own B^{n+1/2} from LDS after each plane;
+//   * stage 3 at ka-1 reads E^{n+1}(ka-1) across the tile and E^{n+1}(ka) at
+//     its own positions: E^{n+1} is double-buffered.
+// A task is RW = 4 consecutive x1 outputs of one row, so the 2ME-tap
+// Faraday windows are read once per four outputs.  The same thread owns the
+// same task in every stage.  FP64 tasks are laid out 8 groups x 2 rows per 16
+// lanes, with row pitches of 2 mod 4 elements: the 16-byte LDS reads of 16
+// lanes then fall on 16 distinct bank quads.
+// Per plane ka (stage 3 on plane ka-1):
+//   E(ka+1) -> registers | stage 1: B^{n+1/2}(ka) -> LDS | B^n(ka+1), E1/E2(ka+2)
+//   own -> registers | barrier | stage 2: E^{n+1}(ka) -> LDS, memory | stage 3:
+//   B^{n+1}(ka-1) -> memory | barrier | E(ka+1) -> LDS | barrier.
+// Extents (columns from the tile's first column, rows from its first row):
+//   B^{n+1/2}: columns [-HB, TX+HB), rows -1..TY
+//   E^{n+1}:   columns [-HB, TX+HB), rows  0..TY
+//   E1:        columns [-HB, TX+HB), rows -1..TY+1
+//   E2:        columns [-2HB, TX+2HB), rows -1..TY
+//   E3:        columns [-2HB, TX+2HB), rows -1..TY+1
+// ---------------------------------------------------------------------------
+template <typename T, int ME, int TX, int TY>
+struct YeeGeom {
+  static constexpr int R = 16 / (int)sizeof(T);  // elements per 16-byte vector
+  static constexpr int RW = 4;                    // outputs per task
+  static constexpr int VW = RW / R;               // vectors per task row segment
+  static constexpr int HB = ME <= 4 ? 4 : ME;     // B and E^{n+1} halo (>= ME, multiple of 4)
+  static constexpr int WB = TX + 2 * HB, WE = TX + 4 * HB;
+  static constexpr int NWIN = (RW + HB + ME + R - 1) / R * R;  // Faraday window elements
+  static constexpr int NWV = NWIN / R;
+  static constexpr int NGX = WB / RW;  // task groups per row
+  static constexpr int GT0 = HB / RW, NGT = TX / RW;
+  static constexpr int PYE = TY + 3, PYB = TY + 2, PYF = TY + 1;
+  static constexpr int PAD = sizeof(T) == 8 ? 2 : 0;
+  static constexpr int PE = WE + PAD, PB = WB + PAD;
+  static constexpr int SE3 = PYE * PE, SE1 = PYE * PB, SE2 = (PYE - 1) * PE;
+  static constexpr int SB = PYB * PB, SF = PYF * PB;
+  static constexpr int O_E1 = SE3, O_E2 = O_E1 + SE1, O_B = O_E2 + SE2, O_F = O_B + 3 * SB;
+  static constexpr int NLDS = O_F + 6 * SF;
+  static constexpr size_t lds_bytes = sizeof(T) * (size_t)NLDS;
+  static constexpr int CG = sizeof(T) == 8 ? 8 : 16, CR = 16 / CG;  // task groups x rows per 16 lanes
+  static constexpr int NCX = (NGX + CG - 1) / CG;
+  static constexpr int NTASK = (PYB + CR - 1) / CR * NCX * 16;
+  // E plane loader: 16-byte vectors of E3 (PYE x WE), E1 (PYE x WB), E2 ((PYE-1) x WE)
+  static constexpr int L3 = PYE * (WE / R), L1 = PYE * (WB / R), L2 = (PYE - 1) * (WE / R);
+  static constexpr int NLV = L3 + L1 + L2;
+};
+
+// RW aligned consecutive elements as 16-byte vectors (LDS or global memory)
+template <typename T, int RW>
+__device__ __forceinline__ void ld_run(const T* __restrict__ p, T (&o)[RW]) {
+  using V = typename Vec16<T>::type;
+  constexpr int R = 16 / (int)sizeof(T);
+#pragma unroll
+  for (int v = 0; v < RW / R; ++v) {
+    const V a = *reinterpret_cast<const V*>(p + v * R);
+#pragma unroll
+    for (int e = 0; e < R; ++e) o[v * R + e] = a[e];
+  }
+}
+template <typename T, int RW>
+__device__ __forceinline__ void st_run(T* __restrict__ p, const T (&o)[RW]) {
+  using V = typename Vec16<T>::type;
+  constexpr int R = 16 / (int)sizeof(T);
+#pragma unroll
+  for (int v = 0; v < RW / R; ++v) {
+    V a;
+#pragma unroll
+    for (int e = 0; e < R; ++e) a[e] = o[v * R + e];
+    *reinterpret_cast<V*>(p + v * R) = a;
+  }
+}
+
+// Faraday taps of output u for a window whose index 0 is HB columns left of
+// the task's first output: sum_q a_q (w[u+HB+q] - w[u+HB-q+1])
+template <typename T, int ME, int HB, int NW>
+__device__ __forceinline__ T faraday_w(const T (&w)[NW], const T (&a)[ME], int u) {
+  T acc = 0;
+#pragma unroll
+  for (int q = 1; q <= ME; ++q) acc += a[q - 1] * (w[u + HB + q] - w[u + HB - q + 1]);
+  return acc;
+}
+
+template <typename T, int ME, int TX, int TY, int NT, bool HAS_J>
+__global__ __launch_bounds__(NT) void sweep_yee_kernel(const T* __restrict__ iE1, const T* __restrict__ iE2,
+                                                       const T* __restrict__ iE3, const T* __restrict__ iB1,
+                                                       const T* __restrict__ iB2, const T* __restrict__ iB3,
+                                                       const T* __restrict__ J1, const T* __restrict__ J2,
+                                                       const T* __restrict__ J3, T* __restrict__ oE1,
+                                                       T* __restrict__ oE2, T* __restrict__ oE3,
+                                                       T* __restrict__ oB1, T* __restrict__ oB2,
+                                                       T* __restrict__ oB3, Mesh m, int tiles_x, int tiles,
+                                                       SweepCoef<T, ME, 1> c) {
+  using G = YeeGeom<T, ME, TX, TY>;
+  using V = typename Vec16<T>::type;
+  constexpr int R = G::R, RW = G::RW, HB = G::HB;
+  // loader slots per component (each slot loads one component)
+  constexpr int N3S = (G::L3 + NT - 1) / NT, N1S = (G::L1 + NT - 1) / NT, N2S = (G::L2 + NT - 1) / NT;
+  static_assert(G::NTASK <= NT, "tasks exceed the workgroup");
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* const lds = reinterpret_cast<T*>(lds_raw);
+  T* const sE3 = lds;
+  T* const sE1 = lds + G::O_E1;
+  T* const sE2 = lds + G::O_E2;
+  T* const sB = lds + G::O_B;  // [component][PYB][PB]
+  T* const sF = lds + G::O_F;  // [plane parity][component][PYF][PB]
+
+  const int tid = threadIdx.x;
+  // XCD-aware tile order (consecutive workgroups go round-robin to the 8 XCDs)
+  int tile = blockIdx.x;
+  if (tiles % 8 == 0) tile = (tile % 8) * (tiles / 8) + tile / 8;
+  const int i0 = (tile % tiles_x) * TX, j0 = (tile / tiles_x) * TY;
+  const size_t plane_sz = (size_t)m.n1 * m.n2;
+  auto gi = [&](int rel) {
+    int i = (i0 + rel) % m.n1;
+    return i < 0 ? i + m.n1 : i;
+  };
+  auto gj = [&](int rel) {
+    int j = (j0 + rel) % m.n2;
+    return j < 0 ? j + m.n2 : j;
+  };
+  auto poff = [&](int k) {
+    k %= m.n3;
+    return (size_t)(k < 0 ? k + m.n3 : k) * plane_sz;
+  };
+
+  // this thread's task: group tg (columns x .. x+RW-1), row tr
+  const int chunk = tid >> 4, l16 = tid & 15;
+  const int rp = chunk / G::NCX, cx = chunk - rp * G::NCX;
+  const int tg = cx * G::CG + l16 % G::CG;
+  const int tr = rp * G::CR + l16 / G::CG;
+  const int x = -HB + RW * tg;
+  const bool t1 = chunk < G::NTASK / 16 && tg < G::NGX && tr < G::PYB;  // B^{n+1/2} row tr-1
+  const bool t2 = t1 && tr < G::PYF;                                      // E^{n+1} row tr
+  const bool t3 = t2 && tr < TY && tg >= G::GT0 && tg < G::GT0 + G::NGT;   // tile output
+  // in-plane offsets of the task's first element (a plane holds < 2^31 cells)
+  const int g1 = t1 ? gj(tr - 1) * m.n1 + gi(x) : 0;
+  const int g2 = t2 ? gj(tr) * m.n1 + gi(x) : 0;
+  const bool out = t3 && j0 + tr < m.n2 && i0 + x < m.n1;
+  const int wcol = RW * tg;  // LDS column of the task's window / B-extent position
+
+  // E plane loader: slot s of component q covers vector tid + s NT of that
+  // component's region; only the wrapped global offset is kept
+  int ga3[N3S], ga1[N1S], ga2[N2S];
+  auto slot_g = [&](int v, int wv, int halo) {
+    const int row = v / wv, col = (v - row * wv) * R;
+    return gj(row - 1) * m.n1 + gi(col - halo);
+  };
+#pragma unroll
+  for (int s = 0; s < N3S; ++s) ga3[s] = tid + s * NT < G::L3 ? slot_g(tid + s * NT, G::WE / R, 2 * HB) : 0;
+#pragma unroll
+  for (int s = 0; s < N1S; ++s) ga1[s] = tid + s * NT < G::L1 ? slot_g(tid + s * NT, G::WB / R, HB) : 0;
+#pragma unroll
+  for (int s = 0; s < N2S; ++s) ga2[s] = tid + s * NT < G::L2 ? slot_g(tid + s * NT, G::WE / R, 2 * HB) : 0;
+  V pe3[N3S], pe1[N1S], pe2[N2S];
+  auto load_E = [&](int k) {
+    const size_t o = poff(k);
+#pragma unroll
+    for (int s = 0; s < N3S; ++s)
+      if (tid + s * NT < G::L3) pe3[s] = *reinterpret_cast<const V*>(iE3 + o + ga3[s]);
+#pragma unroll
+    for (int s = 0; s < N1S; ++s)
+      if (tid + s * NT < G::L1) pe1[s] = *reinterpret_cast<const V*>(iE1 + o + ga1[s]);
+#pragma unroll
+    for (int s = 0; s < N2S; ++s)
+      if (tid + s * NT < G::L2) pe2[s] = *reinterpret_cast<const V*>(iE2 + o + ga2[s]);
+  };
+  auto lds_at = [&](int v, int wv, int pitch) {
+    const int row = v / wv;
+    return row * pitch + (v - row * wv) * R;
+  };
+  auto store_E = [&]() {
+#pragma unroll
+    for (int s = 0; s < N3S; ++s) {
+      const int v = tid + s * NT;
+      if (v < G::L3) *reinterpret_cast<V*>(sE3 + lds_at(v, G::WE / R, G::PE)) = pe3[s];
+    }
+#pragma unroll
+    for (int s = 0; s < N1S; ++s) {
+      const int v = tid + s * NT;
+      if (v < G::L1) *reinterpret_cast<V*>(sE1 + lds_at(v, G::WB / R, G::PB)) = pe1[s];
+    }
+#pragma unroll
+    for (int s = 0; s < N2S; ++s) {
+      const int v = tid + s * NT;
+      if (v < G::L2) *reinterpret_cast<V*>(sE2 + lds_at(v, G::WE / R, G::PE)) = pe2[s];
+    }
+  };
+
+  T bn[3][RW], nn[2][RW], cb[3][RW], jv[HAS_J ? 3 : 1][RW];
+  auto load_own = [&](int k) {  // B^n(k), E1/E2(k+1) at the stage-1 positions
+    const size_t o = poff(k) + g1, on = poff(k + 1) + g1;
+    ld_run<T, RW>(iB1 + o, bn[0]);
+    ld_run<T, RW>(iB2 + o, bn[1]);
+    ld_run<T, RW>(iB3 + o, bn[2]);
+    ld_run<T, RW>(iE1 + on, nn[0]);
+    ld_run<T, RW>(iE2 + on, nn[1]);
+  };
+  auto load_J = [&](int k) {
+    if constexpr (HAS_J) {
+      const size_t o = poff(k) + g2;
+      ld_run<T, RW>(J1 + o, jv[0]);
+      ld_run<T, RW>(J2 + o, jv[1]);
+      ld_run<T, RW>(J3 + o, jv[2]);
+    }
+  };
+
+  // ---- prologue: E(k0-1) in LDS; B^n(k0-1), E1/E2(k0) own, J(k0-1) ----
+  const int k0 = 0, kend = m.n3;
+  load_E(k0 - 1);
+  store_E();
+  if (t1) load_own(k0 - 1);
+  if (t2) load_J(k0 - 1);
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int u = 0; u < RW; ++u) cb[q][u] = 0;
+  __syncthreads();
+
+  for (int ka = k0 - 1; ka <= kend; ++ka) {
+    const bool more = ka < kend;
+    if (more) load_E(ka + 1);
+    // ---- stage 1: B^{n+1/2}(ka) on the B extent ----
+    if (t1) {
+      T* bo = sB + tr * G::PB + wcol;
+      T e1c[RW], e2w[RW];
+      ld_run<T, RW>(sE1 + tr * G::PB + wcol, e1c);
+      {  // B3 from the x1 derivative of E2 and the x2 difference of E1
+        T w[G::NWIN], e1n[RW], o3[RW];
+        load_window<T, G::NWV, R>(sE2 + tr * G::PE + wcol, w);
+        ld_run<T, RW>(sE1 + (tr + 1) * G::PB + wcol, e1n);
+#pragma unroll
+        for (int u = 0; u < RW; ++u) {
+          e2w[u] = w[u + HB];
+          o3[u] = bn[2][u] - (faraday_w<T, ME, HB>(w, c.ae, u) - c.hy * (e1n[u] - e1c[u]));
+        }
+        st_run<T, RW>(bo + 2 * G::SB, o3);
+      }
+      {  // B2 and B1
+        T w[G::NWIN], e3n[RW], o1[RW], o2[RW];
+        load_window<T, G::NWV, R>(sE3 + tr * G::PE + wcol, w);
+        ld_run<T, RW>(sE3 + (tr + 1) * G::PE + wcol + HB, e3n);
+#pragma unroll
+        for (int u = 0; u < RW; ++u) {
+          o2[u] = bn[1][u] - (c.hz * (nn[0][u] - e1c[u]) - faraday_w<T, ME, HB>(w, c.ae, u));
+          o1[u] = bn[0][u] - (c.hy * (e3n[u] - w[u + HB]) - c.hz * (nn[1][u] - e2w[u]));
+        }
+        st_run<T, RW>(bo, o1);
+        st_run<T, RW>(bo + G::SB, o2);
+      }
+      if (more) load_own(ka + 1);
+    }
+    __syncthreads();
+    // ---- stage 2: E^{n+1}(ka) on the E^{n+1} extent ----
+    T g1c[RW], g2c[RW];
+    if (t2) {
+      const T* b = sB + (tr + 1) * G::PB + wcol;
+      T b1c[RW], b2c[RW], b3c[RW], b1s[RW], b3s[RW];
+      ld_run<T, RW>(b, b1c);
+      ld_run<T, RW>(b + G::SB, b2c);
+      ld_run<T, RW>(b + 2 * G::SB, b3c);
+      ld_run<T, RW>(b - G::PB, b1s);
+      ld_run<T, RW>(b + 2 * G::SB - G::PB, b3s);
+      // x1 neighbour of the first output (the extent's first column, whose
+      // E^{n+1} is never read, takes its own value)
+      const int lm = wcol > 0 ? -1 : 0;
+      const T b2l = b[G::SB + lm], b3l = b[2 * G::SB + lm];
+      T e1o[RW], e2o[RW], e3o[RW];
+      ld_run<T, RW>(sE1 + (tr + 1) * G::PB + wcol, e1o);
+      ld_run<T, RW>(sE2 + (tr + 1) * G::PE + wcol + HB, e2o);
+      ld_run<T, RW>(sE3 + (tr + 1) * G::PE + wcol + HB, e3o);
+      T f3[RW];
+#pragma unroll
+      for (int u = 0; u < RW; ++u) {
+        const T b3p = u == 0 ? b3l : b3c[u - 1];
+        const T b2p = u == 0 ? b2l : b2c[u - 1];
+        T c1 = c.ty * (b3c[u] - b3s[u]) - c.tz * (b2c[u] - cb[1][u]);
+        T c2 = c.tz * (b1c[u] - cb[0][u]) - c.ab[0] * (b3c[u] - b3p);
+        T c3 = c.ab[0] * (b2c[u] - b2p) - c.ty * (b1c[u] - b1s[u]);
+        if constexpr (HAS_J) {
+          c1 -= c.dt * jv[0][u];
+          c2 -= c.dt * jv[1][u];
+          c3 -= c.dt * jv[2][u];
+        }
+        g1c[u] = e1o[u] + c1;
+        g2c[u] = e2o[u] + c2;
+        f3[u] = e3o[u] + c3;
+      }
+      T* f = sF + (ka & 1) * 3 * G::SF + tr * G::PB + wcol;
+      st_run<T, RW>(f, g1c);
+      st_run<T, RW>(f + G::SF, g2c);
+      st_run<T, RW>(f + 2 * G::SF, f3);
+      if (out && ka >= k0 && ka < kend) {
+        const size_t o = poff(ka) + g2;
+        st_run<T, RW>(oE1 + o, g1c);
+        st_run<T, RW>(oE2 + o, g2c);
+        st_run<T, RW>(oE3 + o, f3);
+      }
+      if (more) load_J(ka + 1);
+    }
+    // ---- stage 3: B^{n+1}(ka-1) on the tile ----
+    if (t3 && ka - 1 >= k0) {
+      const T* f = sF + ((ka - 1) & 1) * 3 * G::SF + tr * G::PB;
+      const size_t o = poff(ka - 1) + g2;
+      T f1c[RW], f2w[RW];
+      ld_run<T, RW>(f + wcol, f1c);
+      {  // B3 from the x1 derivative of E2 and the x2 difference of E1
+        T w[G::NWIN], f1n[RW], o3[RW];
+        load_window<T, G::NWV, R>(f + G::SF + wcol - HB, w);
+        ld_run<T, RW>(f + G::PB + wcol, f1n);
+#pragma unroll
+        for (int u = 0; u < RW; ++u) {
+          f2w[u] = w[u + HB];
+          o3[u] = cb[2][u] - (faraday_w<T, ME, HB>(w, c.ae, u) - c.hy * (f1n[u] - f1c[u]));
+        }
+        if (out) st_run<T, RW>(oB3 + o, o3);
+      }
+      {  // B2 and B1
+        T w[G::NWIN], f3n[RW], o1[RW], o2[RW];
+        load_window<T, G::NWV, R>(f + 2 * G::SF + wcol - HB, w);
+        ld_run<T, RW>(f + 2 * G::SF + G::PB + wcol, f3n);
+#pragma unroll
+        for (int u = 0; u < RW; ++u) {
+          o2[u] = cb[1][u] - (c.hz * (g1c[u] - f1c[u]) - faraday_w<T, ME, HB>(w, c.ae, u));
+          o1[u] = cb[0][u] - (c.hy * (f3n[u] - w[u + HB]) - c.hz * (g2c[u] - f2w[u]));
+        }
+        if (out) {
+          st_run<T, RW>(oB1 + o, o1);
+          st_run<T, RW>(oB2 + o, o2);
+        }
+      }
+    }
+    // B^{n+1/2}(ka) at this task's positions, for stage 2 at ka+1 and stage 3 at ka
+    if (t2) {
+      const T* b = sB + (tr + 1) * G::PB + wcol;
+      ld_run<T, RW>(b, cb[0]);
+      ld_run<T, RW>(b + G::SB, cb[1]);
+      ld_run<T, RW>(b + 2 * G::SB, cb[2]);
+    }
+    __syncthreads();
+    if (more) store_E();
+    __syncthreads();
+  }
+}
+
+template <typename T, int ME, int TX, int TY, int NT>
+int run_sweep_yee(const Mesh& m, void* const Ein[3], void* const Bin[3], void* const J[3], void* const Eout[3],
+                  void* const Bout[3], const double* CE, int MEr, const double* CB, double dt, hipStream_t s) {
+  using G = YeeGeom<T, ME, TX, TY>;
+  SweepCoef<T, ME, 1> c;
+  for (int q = 0; q < ME; ++q) c.ae[q] = (T)(q < MEr ? CE[q] * (dt / 2) / m.dx1 : 0.0);
+  c.ab[0] = (T)(CB[0] * dt / m.dx1);
+  c.hy = (T)((dt / 2) / m.dx2);
+  c.hz = (T)(m.ndim == 3 ? (dt / 2) / m.dx3 : 0.0);
+  c.ty = (T)(dt / m.dx2);
+  c.tz = (T)(m.ndim == 3 ? dt / m.dx3 : 0.0);
+  c.dt = (T)dt;
+  const int tiles_x = (m.n1 + TX - 1) / TX;
+  const int tiles_y = (m.n2 + TY - 1) / TY;
+  const bool hasJ = J && J[0];
+  auto kern = hasJ ? sweep_yee_kernel<T, ME, TX, TY, NT, true> : sweep_yee_kernel<T, ME, TX, TY, NT, false>;
+  static_assert(G::lds_bytes <= 160 * 1024, "sweep tile exceeds LDS");
+  if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G::lds_bytes) !=
+      hipSuccess)
+    return set_error(PIC_EHIP, "sweep: cannot reserve %zu bytes of LDS", G::lds_bytes);
+  hipLaunchKernelGGL(kern, dim3(tiles_x * tiles_y), dim3(NT), G::lds_bytes, s, (const T*)Ein[0], (const T*)Ein[1],
+                     (const T*)Ein[2], (const T*)Bin[0], (const T*)Bin[1], (const T*)Bin[2],
+                     (const T*)(hasJ ? J[0] : nullptr), (const T*)(hasJ ? J[1] : nullptr),
+                     (const T*)(hasJ ? J[2] : nullptr), (T*)Eout[0], (T*)Eout[1], (T*)Eout[2], (T*)Bout[0],
+                     (T*)Bout[1], (T*)Bout[2], m, tiles_x, tiles_x * tiles_y, c);
+  return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "sweep launch failed");
+}
+
 template <typename T, int ME, int MB, int TX, int TY, int NT>
 int run_sweep(const Mesh& m, void* const Ein[3], void* const Bin[3], void* const J[3], void* const Eout[3],
               void* const Bout[3], const double* CE, int MEr, const double* CB, int MBr, double dt, hipStream_t s) {
@@ -669,7 +1051,7 @@ int run_sweep(const Mesh& m, void* const Ein[3], void* const Bin[3], void* const
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "sweep launch failed");
 }
 
-template <typename T, int TXw, int TXn, int TY, int NT>
+template <typename T, int TXn, int TY, int NT>
 int dispatch_sweep(const Mesh& m, void* const Ein[3], void* const Bin[3], void* const J[3], void* const Eout[3],
                    void* const Bout[3], const double* CE, int ME, const double* CB, int MB, double dt,
                    hipStream_t s) {
@@ -677,12 +1059,13 @@ int dispatch_sweep(const Mesh& m, void* const Ein[3], void* const Bin[3], void* 
   const int w = we > wb ? we : wb;
   // Ampere stencil either Yee (width 1) or padded to the Faraday width
   if (wb == 1) {
+    constexpr int YT = 8;  // rows per tile of the Yee-Ampere sweep
     switch (we) {
-      case 1: return run_sweep<T, 1, 1, TXw, TY, NT>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, MB, dt, s);
-      case 2: return run_sweep<T, 2, 1, TXw, TY, NT>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, MB, dt, s);
-      case 4: return run_sweep<T, 4, 1, TXw, TY, NT>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, MB, dt, s);
-      case 8: return run_sweep<T, 8, 1, TXw, TY, NT>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, MB, dt, s);
-      default: return run_sweep<T, 16, 1, TXw, TY, NT>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, MB, dt, s);
+      case 1: return run_sweep_yee<T, 1, 128, YT, NT>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, dt, s);
+      case 2: return run_sweep_yee<T, 2, 128, YT, NT>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, dt, s);
+      case 4: return run_sweep_yee<T, 4, 128, YT, NT>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, dt, s);
+      case 8: return run_sweep_yee<T, 8, 128, YT, NT>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, dt, s);
+      default: return run_sweep_yee<T, 16, 128, YT, NT>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, dt, s);
     }
   }
   switch (w) {
@@ -712,8 +1095,8 @@ int launch_sweep(int prec, const Mesh& m, void* const Ein[3], void* const Bin[3]
                  void* const Eout[3], void* const Bout[3], const double* CE, int ME, const double* CB, int MB,
                  double dt, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  if (prec == PIC_FP64) return dispatch_sweep<double, 128, 64, 4, 512>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, MB, dt, s);
-  return dispatch_sweep<float, 128, 128, 8, 512>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, MB, dt, s);
+  if (prec == PIC_FP64) return dispatch_sweep<double, 64, 4, 512>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, MB, dt, s);
+  return dispatch_sweep<float, 128, 8, 512>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, MB, dt, s);
 }
 
 int launch_advance_e(int prec, const Mesh& m, void* const E[3], void* const B[3], void* const J[3],
