@@ -169,7 +169,12 @@ int pic_deposit_J(pic_grid *g, const pic_particles *p, double *const x_old[3], i
  * spatial tile (8^3 cells) at the first step and then every
  * pic_set_sort_interval steps, and the current of each tile is accumulated in
  * on-chip memory: such calls REORDER the particles (x, u and id together).
- * Vacuum calls and 2D grids keep the order. */
+ * Vacuum calls and 2D grids keep the order.  A vacuum call on a 3D grid with
+ * nsteps >= 2 pushes each species of at least 32768 particles as a copy in
+ * library scratch sorted by the same tiles (two copies of 56 bytes per
+ * particle plus 4-byte keys, grow-only, PIC_ENOMEM if they cannot be
+ * allocated), re-sorted every 16 steps and scattered back to the caller's
+ * order at the end: the results equal those of pushing in place, bit for bit. */
 int pic_step_n(pic_grid *g, pic_particles *const *species, int nspecies, int nsteps,
                int pusher, int deposit);
 /* One vacuum step (no deposit) out of place: gather + push + position update

@@ -44,6 +44,8 @@ struct pic_grid {
   int64_t xo_cap = 0;
   int sort_every = 3;  // 3: the 64-bit tile current then fits three workgroups per CU
   std::vector<SortState> sorts;
+  // vacuum step loop: two tile-ordered copies per species (re-sort ping-pong)
+  std::vector<SortState> vsort_a, vsort_b;
   double* partial = nullptr;  // per-block partial sums of the coefficient gradients
   int64_t partial_cap = 0;
   yeepic::Mesh mesh = {};
@@ -52,6 +54,12 @@ struct pic_grid {
 namespace yeepic {
 
 static thread_local char g_err[512] = "no error";
+
+// vacuum step loop: species of at least kVacSortMin particles are pushed as a
+// tile-ordered copy, re-sorted every kVacSortEvery steps (|v| < c moves a
+// particle at most kVacSortEvery dt / dx1 = 8 cells at dt = dx1/2, one tile)
+constexpr int64_t kVacSortMin = 1 << 15;
+constexpr int kVacSortEvery = 16;
 
 int set_error(int code, const char* fmt, ...) {
   va_list ap;
@@ -357,6 +365,48 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
       rc = ensure_sort(g, g->sorts[s], species[s]->np, tg.ntiles, species[s]->id != nullptr);
     if (rc) return rc;
   }
+  // 3D vacuum: each large species is pushed as a tile-ordered copy, so that
+  // the eight-node gathers of a wave share cache lines; the copy is re-sorted
+  // every kVacSortEvery steps and scattered back to the caller's order at the
+  // end.  Every particle's arithmetic is the same as in place.
+  const bool vac = !deposit && g->ndim == 3 && nsteps >= 2;
+  std::vector<pic_particles> vcur, valt;
+  std::vector<char> vuse;
+  if (vac) {
+    tg = make_tile_geom(g->mesh, g->dt, 1);
+    if ((int)g->vsort_a.size() < nspecies) {
+      g->vsort_a.resize(nspecies);
+      g->vsort_b.resize(nspecies);
+    }
+    vcur.resize(nspecies);
+    valt.resize(nspecies);
+    vuse.assign(nspecies, 0);
+    for (int s = 0; s < nspecies && rc == PIC_OK; ++s) {
+      if (species[s]->np < kVacSortMin) continue;
+      SortState& A = g->vsort_a[s];
+      SortState& B = g->vsort_b[s];
+      rc = ensure_sort(g, A, species[s]->np, tg.ntiles, true);
+      if (rc == PIC_OK) rc = ensure_sort(g, B, species[s]->np, tg.ntiles, true);
+      if (rc) break;
+      vuse[s] = 1;
+      vcur[s] = valt[s] = *species[s];
+      for (int d = 0; d < 3; ++d) {
+        vcur[s].x[d] = A.xs[d];
+        vcur[s].u[d] = A.us[d];
+        valt[s].x[d] = B.xs[d];
+        valt[s].u[d] = B.us[d];
+      }
+      vcur[s].id = A.ids;
+      valt[s].id = B.ids;
+      // original indices (in B's id array) travel with the first sort into A
+      pic_particles src = *species[s];
+      src.id = B.ids;
+      rc = launch_iota(B.ids, species[s]->np, g->stream);
+      if (rc == PIC_OK)
+        rc = launch_tile_sort(g->mesh, tg, src, vcur[s], A.keys, A.counts, A.offsets, A.cursors, g->stream);
+    }
+    if (rc) return rc;
+  }
   for (int step = 0; step < nsteps && rc == PIC_OK; ++step) {
     if (deposit)
       for (int c = 0; c < 3 && rc == PIC_OK; ++c)
@@ -381,6 +431,16 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
                                 g->dt, g->stream);
         continue;
       }
+      if (vac && vuse[s]) {
+        if (step > 0 && step % kVacSortEvery == 0) {
+          SortState& D = (vcur[s].x[0] == g->vsort_a[s].xs[0]) ? g->vsort_b[s] : g->vsort_a[s];
+          rc = launch_tile_sort(g->mesh, tg, vcur[s], valt[s], D.keys, D.counts, D.offsets, D.cursors, g->stream);
+          std::swap(vcur[s], valt[s]);
+        }
+        if (rc == PIC_OK) rc = launch_gather_push(g->prec, g->mesh, cur, cur + 3, vcur[s], pusher, g->dt, nullptr,
+                                                  g->stream);
+        continue;
+      }
       rc = launch_gather_push(g->prec, g->mesh, cur, cur + 3, *species[s], pusher, g->dt, deposit ? xo : nullptr,
                               g->stream);
       if (rc == PIC_OK && deposit) rc = launch_deposit(g->prec, g->mesh, g->J, *species[s], xo, g->dt, g->stream);
@@ -388,6 +448,9 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
     if (rc == PIC_OK) rc = sweep_once(g, cur, cur + 3, nxt, nxt + 3, deposit);
     for (int c = 0; c < 6; ++c) std::swap(cur[c], nxt[c]);
   }
+  if (vac)
+    for (int s = 0; s < nspecies && rc == PIC_OK; ++s)
+      if (vuse[s]) rc = launch_unsort(vcur[s], vcur[s].id, *species[s], g->stream);
   if (rc == PIC_OK && cur[0] != g->E[0]) {
     // odd number of steps: the state is in the alt set
     const size_t bytes = jbytes;
@@ -543,6 +606,8 @@ void pic_destroy(pic_grid* g) {
   for (int d = 0; d < 3; ++d)
     if (g->xo[d]) (void)hipFree(g->xo[d]);
   for (SortState& st : g->sorts) free_sort(st);
+  for (SortState& st : g->vsort_a) free_sort(st);
+  for (SortState& st : g->vsort_b) free_sort(st);
   if (g->d_flag) (void)hipFree(g->d_flag);
   if (g->partial) (void)hipFree(g->partial);
   delete g;

@@ -274,6 +274,47 @@ int launch_tile_sort(const Mesh& m, const TileGeom& tg, const pic_particles& p, 
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "tile sort launch failed");
 }
 
+// ---------------------------------------------------------------------------
+// Tile-ordered copies of a species for the vacuum step loop: the copy carries
+// each particle's original index, through which it is scattered back.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void iota_kernel(int64_t* __restrict__ ids, int64_t np) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < np) ids[p] = p;
+}
+
+__global__ __launch_bounds__(256) void unsort_kernel(const double* __restrict__ x1, const double* __restrict__ x2,
+                                                     const double* __restrict__ x3, const double* __restrict__ u1,
+                                                     const double* __restrict__ u2, const double* __restrict__ u3,
+                                                     const int64_t* __restrict__ ids, int64_t np,
+                                                     double* __restrict__ dx1, double* __restrict__ dx2,
+                                                     double* __restrict__ dx3, double* __restrict__ du1,
+                                                     double* __restrict__ du2, double* __restrict__ du3) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int64_t q = ids[p];
+  dx1[q] = x1[p];
+  dx2[q] = x2[p];
+  dx3[q] = x3[p];
+  du1[q] = u1[p];
+  du2[q] = u2[p];
+  du3[q] = u3[p];
+}
+
+int launch_iota(int64_t* ids, int64_t np, void* stream) {
+  if (np == 0) return PIC_OK;
+  hipLaunchKernelGGL(iota_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, (hipStream_t)stream, ids, np);
+  return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "iota launch failed");
+}
+
+int launch_unsort(const pic_particles& sorted, const int64_t* ids, const pic_particles& dst, void* stream) {
+  if (sorted.np == 0) return PIC_OK;
+  hipLaunchKernelGGL(unsort_kernel, dim3((unsigned)((sorted.np + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     sorted.x[0], sorted.x[1], sorted.x[2], sorted.u[0], sorted.u[1], sorted.u[2], ids, sorted.np,
+                     dst.x[0], dst.x[1], dst.x[2], dst.u[0], dst.u[1], dst.u[2]);
+  return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "unsort launch failed");
+}
+
 int launch_tile_push(int prec, const Mesh& m, const TileGeom& tg, void* const E[3], void* const B[3],
                      void* const J[3], const int* offsets, const pic_particles& src, const pic_particles& dst,
                      int pusher, double dt, void* stream) {

@@ -60,6 +60,9 @@ struct TileGeom {
 TileGeom make_tile_geom(const Mesh& m, double dt, int sort_every);
 int launch_tile_sort(const Mesh& m, const TileGeom& tg, const pic_particles& p, const pic_particles& scratch,
                      int* keys, int* counts, int* offsets, int* cursors, void* stream);
+// ids[i] = i; dst[ids[i]] = sorted[i] for x and u (3D)
+int launch_iota(int64_t* ids, int64_t np, void* stream);
+int launch_unsort(const pic_particles& sorted, const int64_t* ids, const pic_particles& dst, void* stream);
 int launch_tile_push(int prec, const Mesh& m, const TileGeom& tg, void* const E[3], void* const B[3],
                      void* const J[3], const int* offsets, const pic_particles& src, const pic_particles& dst,
                      int pusher, double dt, void* stream);
