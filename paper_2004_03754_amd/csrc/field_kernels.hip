@@ -732,8 +732,8 @@ __device__ __forceinline__ T faraday_w(const T (&w)[NW], const T (&a)[ME], int u
   return acc;
 }
 
-template <typename T, int ME, int TX, int TY, int NT, bool HAS_J>
-__global__ __launch_bounds__(NT) void sweep_yee_kernel(const T* __restrict__ iE1, const T* __restrict__ iE2,
+template <typename T, int ME, int TX, int TY, int NT, int WPE, bool HAS_J>
+__global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict__ iE1, const T* __restrict__ iE2,
                                                        const T* __restrict__ iE3, const T* __restrict__ iB1,
                                                        const T* __restrict__ iB2, const T* __restrict__ iB3,
                                                        const T* __restrict__ J1, const T* __restrict__ J2,
@@ -994,10 +994,39 @@ __global__ __launch_bounds__(NT) void sweep_yee_kernel(const T* __restrict__ iE1
   }
 }
 
+// compute units of the current device (queried once per device)
+int device_cus() {
+  static int cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int n = 0;
+    cached[dev] = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0 ? n : 256;
+  }
+  return cached[dev];
+}
+
+template <typename T, int ME, int TX, int TY, int NT, int WPE>
+int launch_sweep_yee(const Mesh& m, void* const Ein[3], void* const Bin[3], void* const J[3], void* const Eout[3],
+                     void* const Bout[3], const SweepCoef<T, ME, 1>& c, int tiles_x, int tiles, hipStream_t s) {
+  using G = YeeGeom<T, ME, TX, TY>;
+  const bool hasJ = J && J[0];
+  auto kern = hasJ ? sweep_yee_kernel<T, ME, TX, TY, NT, WPE, true> : sweep_yee_kernel<T, ME, TX, TY, NT, WPE, false>;
+  static_assert(G::lds_bytes <= 160 * 1024, "sweep tile exceeds LDS");
+  if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G::lds_bytes) !=
+      hipSuccess)
+    return set_error(PIC_EHIP, "sweep: cannot reserve %zu bytes of LDS", G::lds_bytes);
+  hipLaunchKernelGGL(kern, dim3(tiles), dim3(NT), G::lds_bytes, s, (const T*)Ein[0], (const T*)Ein[1],
+                     (const T*)Ein[2], (const T*)Bin[0], (const T*)Bin[1], (const T*)Bin[2],
+                     (const T*)(hasJ ? J[0] : nullptr), (const T*)(hasJ ? J[1] : nullptr),
+                     (const T*)(hasJ ? J[2] : nullptr), (T*)Eout[0], (T*)Eout[1], (T*)Eout[2], (T*)Bout[0],
+                     (T*)Bout[1], (T*)Bout[2], m, tiles_x, tiles, c);
+  return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "sweep launch failed");
+}
+
 template <typename T, int ME, int TX, int TY, int NT>
 int run_sweep_yee(const Mesh& m, void* const Ein[3], void* const Bin[3], void* const J[3], void* const Eout[3],
                   void* const Bout[3], const double* CE, int MEr, const double* CB, double dt, hipStream_t s) {
-  using G = YeeGeom<T, ME, TX, TY>;
   SweepCoef<T, ME, 1> c;
   for (int q = 0; q < ME; ++q) c.ae[q] = (T)(q < MEr ? CE[q] * (dt / 2) / m.dx1 : 0.0);
   c.ab[0] = (T)(CB[0] * dt / m.dx1);
@@ -1007,19 +1036,13 @@ int run_sweep_yee(const Mesh& m, void* const Ein[3], void* const Bin[3], void* c
   c.tz = (T)(m.ndim == 3 ? dt / m.dx3 : 0.0);
   c.dt = (T)dt;
   const int tiles_x = (m.n1 + TX - 1) / TX;
-  const int tiles_y = (m.n2 + TY - 1) / TY;
-  const bool hasJ = J && J[0];
-  auto kern = hasJ ? sweep_yee_kernel<T, ME, TX, TY, NT, true> : sweep_yee_kernel<T, ME, TX, TY, NT, false>;
-  static_assert(G::lds_bytes <= 160 * 1024, "sweep tile exceeds LDS");
-  if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G::lds_bytes) !=
-      hipSuccess)
-    return set_error(PIC_EHIP, "sweep: cannot reserve %zu bytes of LDS", G::lds_bytes);
-  hipLaunchKernelGGL(kern, dim3(tiles_x * tiles_y), dim3(NT), G::lds_bytes, s, (const T*)Ein[0], (const T*)Ein[1],
-                     (const T*)Ein[2], (const T*)Bin[0], (const T*)Bin[1], (const T*)Bin[2],
-                     (const T*)(hasJ ? J[0] : nullptr), (const T*)(hasJ ? J[1] : nullptr),
-                     (const T*)(hasJ ? J[2] : nullptr), (T*)Eout[0], (T*)Eout[1], (T*)Eout[2], (T*)Bout[0],
-                     (T*)Bout[1], (T*)Bout[2], m, tiles_x, tiles_x * tiles_y, c);
-  return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "sweep launch failed");
+  const int tiles = tiles_x * ((m.n2 + TY - 1) / TY);
+  // FP32 tiles fit two workgroups per CU (LDS and 128 VGPRs); that pays once
+  // there are at least two tiles per CU.  FP64 takes one workgroup per CU.
+  if constexpr (sizeof(T) == 4)
+    if (tiles >= 2 * device_cus())
+      return launch_sweep_yee<T, ME, TX, TY, NT, 4>(m, Ein, Bin, J, Eout, Bout, c, tiles_x, tiles, s);
+  return launch_sweep_yee<T, ME, TX, TY, NT, 2>(m, Ein, Bin, J, Eout, Bout, c, tiles_x, tiles, s);
 }
 
 template <typename T, int ME, int MB, int TX, int TY, int NT>

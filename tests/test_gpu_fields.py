@@ -120,6 +120,27 @@ def test_fused_sweep_small_and_ragged_meshes(n, coeffs16):
     grid.close()
 
 
+@pytest.mark.parametrize("kind", ["custom", "m8"])
+def test_fp32_sweep_two_workgroups_per_cu(kind, coeffs16):
+    """FP32 meshes with at least two 128 x 8 tiles per compute unit run the
+    sweep at two workgroups per CU: 1024 x 512 x 2 cells (512 tiles), with a
+    current, against the oracle."""
+    CE, CB = _coeffs(kind, coeffs16)
+    n = (1024, 512, 2)
+    E, B = wl.random_fields(n, seed=41)
+    J, _ = wl.random_fields(n, seed=42, scale=0.3)
+    E, B, J = ([a.astype(np.float32).astype(np.float64) for a in f] for f in (E, B, J))
+    grid = b.Grid([dev(e, torch.float32) for e in E], [dev(x, torch.float32) for x in B], DX, wl.DT, CE, CB,
+                  J=[dev(j, torch.float32) for j in J], prec="fp32")
+    for _ in range(2):
+        grid.sweep(use_J=True)
+        E, B = fdtd.sweep(E, B, J, CE, CB, DX, wl.DT)
+    grid.sync()
+    assert_fields_close(grid.E, E, 4 * TOL["fp32"], "sweep E")
+    assert_fields_close(grid.B, B, 4 * TOL["fp32"], "sweep B")
+    grid.close()
+
+
 def test_sweep_preserves_divergence_on_gpu(coeffs16):
     """Faraday's divergence of B and the vacuum Gauss divergence of E stay at
     their initial values over 50 GPU sweeps (invariant check at a size the
