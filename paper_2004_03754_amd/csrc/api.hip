@@ -18,6 +18,7 @@ struct SortState {
   int* counts = nullptr;
   int* offsets = nullptr;
   int* cursors = nullptr;
+  int* segsum = nullptr;  // per-segment sums of the tile-count scan
   double* xs[3] = {nullptr, nullptr, nullptr};
   double* us[3] = {nullptr, nullptr, nullptr};
   int64_t* ids = nullptr;
@@ -119,7 +120,7 @@ static int check_particles(const pic_grid* g, const pic_particles* p) {
 }
 
 static void free_sort(SortState& st) {
-  void* ptrs[] = {st.keys, st.counts, st.offsets, st.cursors, st.xs[0], st.xs[1], st.xs[2],
+  void* ptrs[] = {st.keys, st.counts, st.offsets, st.cursors, st.segsum, st.xs[0], st.xs[1], st.xs[2],
                   st.us[0], st.us[1], st.us[2], st.ids};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -134,7 +135,8 @@ static int ensure_sort(pic_grid* g, SortState& st, int64_t np, int ntiles, bool 
   bool ok = hipMalloc((void**)&st.keys, n * sizeof(int)) == hipSuccess &&
             hipMalloc((void**)&st.counts, (size_t)ntiles * sizeof(int)) == hipSuccess &&
             hipMalloc((void**)&st.offsets, ((size_t)ntiles + 1) * sizeof(int)) == hipSuccess &&
-            hipMalloc((void**)&st.cursors, (size_t)ntiles * sizeof(int)) == hipSuccess;
+            hipMalloc((void**)&st.cursors, (size_t)ntiles * sizeof(int)) == hipSuccess &&
+            hipMalloc((void**)&st.segsum, (size_t)scan_segments(ntiles) * sizeof(int)) == hipSuccess;
   for (int d = 0; d < 3 && ok; ++d)
     ok = hipMalloc((void**)&st.xs[d], n * sizeof(double)) == hipSuccess &&
          hipMalloc((void**)&st.us[d], n * sizeof(double)) == hipSuccess;
@@ -403,7 +405,8 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
       src.id = B.ids;
       rc = launch_iota(B.ids, species[s]->np, g->stream);
       if (rc == PIC_OK)
-        rc = launch_tile_sort(g->mesh, tg, src, vcur[s], A.keys, A.counts, A.offsets, A.cursors, g->stream);
+        rc = launch_tile_sort(g->mesh, tg, src, vcur[s], A.keys, A.counts, A.offsets, A.cursors, A.segsum,
+                                  g->stream);
     }
     if (rc) return rc;
   }
@@ -423,7 +426,7 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
           }
           scr.id = species[s]->id ? st.ids : nullptr;
           rc = launch_tile_sort(g->mesh, tg, *species[s], scr, st.keys, st.counts, st.offsets, st.cursors,
-                                g->stream);
+                                st.segsum, g->stream);
           src = scr;
         }
         if (rc == PIC_OK)
@@ -434,7 +437,8 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
       if (vac && vuse[s]) {
         if (step > 0 && step % kVacSortEvery == 0) {
           SortState& D = (vcur[s].x[0] == g->vsort_a[s].xs[0]) ? g->vsort_b[s] : g->vsort_a[s];
-          rc = launch_tile_sort(g->mesh, tg, vcur[s], valt[s], D.keys, D.counts, D.offsets, D.cursors, g->stream);
+          rc = launch_tile_sort(g->mesh, tg, vcur[s], valt[s], D.keys, D.counts, D.offsets, D.cursors, D.segsum,
+                                g->stream);
           std::swap(vcur[s], valt[s]);
         }
         if (rc == PIC_OK) rc = launch_gather_push(g->prec, g->mesh, cur, cur + 3, vcur[s], pusher, g->dt, nullptr,

@@ -101,9 +101,11 @@ __device__ __forceinline__ void boris(double u[3], const double E[3], const doub
 //   G_m = sum_k h_k(X, -Y)/(2k+m)!,  h_k = complete homogeneous polynomial.
 // For max(X, Y) <= 1 the series is summed; otherwise the hyperbolic /
 // trigonometric closed forms are used, written without cancellation where a
-// cancellation-free form exists.  t(tau) = dt is solved by safeguarded Newton
-// (t increases with dt/dtau = gamma >= 1, root between 0 and dt) applied to
-// log(t/dt).
+// cancellation-free form exists.  t(tau) = dt is solved by bracketed Newton
+// (t increases with dt/dtau = gamma >= 1, root between 0 and dt) from a
+// first guess on the Taylor polynomial of t: plain Newton near the root, on
+// log(t/dt) far from it, stopping when the correction is below the rounding
+// of tau.
 // ---------------------------------------------------------------------------
 struct ExpCoef {
   double a0, a1, a2, a3, A1, A3;  // A0 = a1, A2 = a3
@@ -222,9 +224,23 @@ __device__ __forceinline__ double analytic_solve(const double u[3], const double
   apply_F(E, B, qm, V1, V2);
   apply_F(E, B, qm, V2, V3);
   double lo = fmin(0.0, dt), hi = fmax(0.0, dt);
-  // first guess dt/gamma, pulled in so that exp(sqrt(k2 + w2) tau) stays finite
+  // First guess: from dt/gamma, two Newton steps on the Taylor polynomial
+  // t(tau) ~ gamma tau + (F U)^0 tau^2/2 + (F^2 U)^0 tau^3/6 + (F^3 U)^0 tau^4/24
+  // (exact where F^4 U = 0, e.g. a null field), kept only while it rises and
+  // stays in the bracket; then pulled in so that exp(sqrt(k2 + w2) tau)
+  // stays finite.
   const double kw = sqrt(k2 + w2);
   double tau = dt / U0[0];
+  {
+    const double c1 = 0.5 * V1[0], c2 = V2[0] / 6.0, c3 = V3[0] / 24.0;
+    for (int s = 0; s < 2; ++s) {
+      const double p = (((c3 * tau + c2) * tau + c1) * tau + U0[0]) * tau - dt;
+      const double dp = ((4.0 * c3 * tau + 3.0 * c2) * tau + 2.0 * c1) * tau + U0[0];
+      const double nt = tau - p / dp;
+      if (!(dp > 0.0) || !(nt > lo && nt < hi)) break;
+      tau = nt;
+    }
+  }
   if (kw * fabs(tau) > 50.0) tau = copysign(50.0 / kw, dt);
   for (int it = 0; it < 100; ++it) {
     const ExpCoef e = exp_coef(k2, w2, tau);
@@ -243,12 +259,17 @@ __device__ __forceinline__ double analytic_solve(const double u[3], const double
     // from t = dt/2 it reaches at most e/2 dt.  The bracket guards the rest.
     const double ratio = t / dt;
     double nx;
-    if (!fin || !(ratio > 0.0))
+    if (!fin || !(ratio > 0.0)) {
       nx = 0.5 * (lo + hi);
-    else if (ratio > 0.5 && ratio < 2.0)
-      nx = tau - f / g;
-    else
+    } else if (ratio > 0.5 && ratio < 2.0) {
+      // a Newton correction below the rounding of tau ends the solve: t is
+      // then at its rounding floor, which can stay above 1e-16 dt
+      const double step = f / g;
+      if (fabs(step) <= 1e-15 * fabs(tau)) break;
+      nx = tau - step;
+    } else {
       nx = tau - log(ratio) * (t / g);
+    }
     if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
     const bool small = fabs(nx - tau) <= 1e-15 * fabs(tau);
     tau = nx;

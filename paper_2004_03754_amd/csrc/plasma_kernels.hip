@@ -66,31 +66,69 @@ __global__ __launch_bounds__(256) void tile_count_kernel(const double* __restric
   if (leader_lane == (int)(threadIdx.x & 63) && key >= 0) atomicAdd(&counts[key], runlen);
 }
 
-// exclusive scan of n counts by one workgroup of 1024 threads; also clears
-// the scatter cursors and writes offsets[n] = total
-__global__ __launch_bounds__(1024) void tile_scan_kernel(const int* __restrict__ counts, int* __restrict__ offsets,
-                                                         int* __restrict__ cursors, int n) {
-  __shared__ int part[1024];
-  const int t = threadIdx.x;
-  const int chunk = (n + 1023) / 1024;
-  const int lo = t * chunk, hi = min(n, lo + chunk);
-  int sum = 0;
-  for (int i = lo; i < hi; ++i) sum += counts[i];
-  part[t] = sum;
+// Exclusive scan of n tile counts in two passes over segments of kScanSeg
+// counts (one workgroup of 1024 threads, four consecutive counts per thread):
+// the segment sums, then each segment's scan plus the sum of the segments
+// before it.  The second pass also clears the scatter cursors and writes
+// offsets[n] = total.
+constexpr int kScanSeg = 4096;
+
+__device__ __forceinline__ int load_count(const int* __restrict__ c, int i, int n) { return i < n ? c[i] : 0; }
+
+__global__ __launch_bounds__(1024) void tile_segsum_kernel(const int* __restrict__ counts, int n,
+                                                           int* __restrict__ segsum) {
+  __shared__ int wsum[16];
+  const int t = threadIdx.x, base = blockIdx.x * kScanSeg + 4 * t;
+  int v = load_count(counts, base, n) + load_count(counts, base + 1, n) + load_count(counts, base + 2, n) +
+          load_count(counts, base + 3, n);
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_down(v, d);
+  if ((t & 63) == 0) wsum[t >> 6] = v;
   __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
-    const int v = t >= d ? part[t - d] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  if (t == 0) {
+    int s = 0;
+    for (int w = 0; w < 16; ++w) s += wsum[w];
+    segsum[blockIdx.x] = s;
   }
-  int run = part[t] - sum;
-  for (int i = lo; i < hi; ++i) {
-    offsets[i] = run;
-    run += counts[i];
-    cursors[i] = 0;
+}
+
+__global__ __launch_bounds__(1024) void tile_segscan_kernel(const int* __restrict__ counts, int n,
+                                                            const int* __restrict__ segsum, int nseg,
+                                                            int* __restrict__ offsets, int* __restrict__ cursors) {
+  __shared__ int wpre[16];
+  __shared__ int segbase;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (w == 0) {  // sum of the preceding segments
+    int s = 0;
+    for (int i = lane; i < (int)blockIdx.x; i += 64) s += segsum[i];
+    for (int d = 32; d > 0; d >>= 1) s += __shfl_down(s, d);
+    if (lane == 0) segbase = s;
   }
-  if (t == 1023) offsets[n] = part[1023];
+  const int base = blockIdx.x * kScanSeg + 4 * t;
+  const int c0 = load_count(counts, base, n), c1 = load_count(counts, base + 1, n),
+            c2 = load_count(counts, base + 2, n), c3 = load_count(counts, base + 3, n);
+  const int mine = c0 + c1 + c2 + c3;
+  int inc = mine;  // inclusive scan across the wave
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(inc, d);
+    if (lane >= d) inc += y;
+  }
+  if (lane == 63) wpre[w] = inc;
+  __syncthreads();
+  int before = segbase;
+  for (int v = 0; v < w; ++v) before += wpre[v];
+  int run = before + inc - mine;
+  const int cs[4] = {c0, c1, c2, c3};
+  for (int e = 0; e < 4; ++e)
+    if (base + e < n) {
+      offsets[base + e] = run;
+      cursors[base + e] = 0;
+      run += cs[e];
+    }
+  if (blockIdx.x == nseg - 1 && t == 1023) {
+    int total = segbase;
+    for (int v = 0; v < 16; ++v) total += wpre[v];
+    offsets[n] = total;
+  }
 }
 
 __global__ __launch_bounds__(256) void tile_scatter_kernel(const double* __restrict__ x1, const double* __restrict__ x2,
@@ -259,15 +297,20 @@ TileGeom make_tile_geom(const Mesh& m, double dt, int sort_every) {
   return tg;
 }
 
+int scan_segments(int ntiles) { return (ntiles + kScanSeg - 1) / kScanSeg; }
+
 int launch_tile_sort(const Mesh& m, const TileGeom& tg, const pic_particles& p, const pic_particles& scratch,
-                     int* keys, int* counts, int* offsets, int* cursors, void* stream) {
+                     int* keys, int* counts, int* offsets, int* cursors, int* segsum, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   if (p.np == 0) return PIC_OK;
   if (hipMemsetAsync(counts, 0, sizeof(int) * tg.ntiles, s) != hipSuccess)
     return set_error(PIC_EHIP, "tile sort: clear counts");
   const dim3 grid((unsigned)((p.np + 255) / 256));
   hipLaunchKernelGGL(tile_count_kernel, grid, dim3(256), 0, s, p.x[0], p.x[1], p.x[2], p.np, m, tg, keys, counts);
-  hipLaunchKernelGGL(tile_scan_kernel, dim3(1), dim3(1024), 0, s, counts, offsets, cursors, tg.ntiles);
+  const int nseg = (tg.ntiles + kScanSeg - 1) / kScanSeg;
+  hipLaunchKernelGGL(tile_segsum_kernel, dim3(nseg), dim3(1024), 0, s, counts, tg.ntiles, segsum);
+  hipLaunchKernelGGL(tile_segscan_kernel, dim3(nseg), dim3(1024), 0, s, counts, tg.ntiles, segsum, nseg, offsets,
+                     cursors);
   hipLaunchKernelGGL(tile_scatter_kernel, grid, dim3(256), 0, s, p.x[0], p.x[1], p.x[2], p.u[0], p.u[1], p.u[2],
                      p.id, keys, offsets, cursors, p.np, scratch.x[0], scratch.x[1], scratch.x[2], scratch.u[0],
                      scratch.u[1], scratch.u[2], scratch.id);

@@ -58,8 +58,10 @@ struct TileGeom {
   int ntiles;
 };
 TileGeom make_tile_geom(const Mesh& m, double dt, int sort_every);
+// counting sort of p by tile into scratch; segsum holds scan_segments(ntiles) ints
+int scan_segments(int ntiles);
 int launch_tile_sort(const Mesh& m, const TileGeom& tg, const pic_particles& p, const pic_particles& scratch,
-                     int* keys, int* counts, int* offsets, int* cursors, void* stream);
+                     int* keys, int* counts, int* offsets, int* cursors, int* segsum, void* stream);
 // ids[i] = i; dst[ids[i]] = sorted[i] for x and u (3D)
 int launch_iota(int64_t* ids, int64_t np, void* stream);
 int launch_unsort(const pic_particles& sorted, const int64_t* ids, const pic_particles& dst, void* stream);
