@@ -229,10 +229,14 @@ __global__ __launch_bounds__(256) void tile_push_kernel(
       esirkepov3(sh[0], sh[1], sh[2], c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
         lds_add(&jl[comp * R + o + (c * r1 + b) * r0 + a], v, scale);
       });
-    } else {
+    } else {  // outside the on-chip tile (rare): global atomics, stencil nodes wrapped once
+      int gw[3][3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gw[d][k] = wrapn(sh[d].base + k, n[d]);
       esirkepov3(sh[0], sh[1], sh[2], c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
-        const size_t gidx = (size_t)wrapn(sh[2].base + c, m.n3) * pl + (size_t)wrapn(sh[1].base + b, m.n2) * m.n1 +
-                            wrapn(sh[0].base + a, m.n1);
+        const size_t gidx = (size_t)gw[2][c] * pl + (size_t)gw[1][b] * m.n1 + gw[0][a];
         atomic_add(&Jg[comp][gidx], v);
       });
     }
