@@ -741,7 +741,7 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
                                                        T* __restrict__ oE2, T* __restrict__ oE3,
                                                        T* __restrict__ oB1, T* __restrict__ oB2,
                                                        T* __restrict__ oB3, Mesh m, int tiles_x, int tiles,
-                                                       SweepCoef<T, ME, 1> c) {
+                                                       int KZ, SweepCoef<T, ME, 1> c) {
   using G = YeeGeom<T, ME, TX, TY>;
   using V = typename Vec16<T>::type;
   constexpr int R = G::R, RW = G::RW, HB = G::HB;
@@ -857,7 +857,8 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
   };
 
   // ---- prologue: E(k0-1) in LDS; B^n(k0-1), E1/E2(k0) own, J(k0-1) ----
-  const int k0 = 0, kend = m.n3;
+  // (the march covers planes k0 .. kend-1: one x3 chunk of KZ planes)
+  const int k0 = blockIdx.y * KZ, kend = min(m.n3, k0 + KZ);
   load_E(k0 - 1);
   store_E();
   if (t1) load_own(k0 - 1);
@@ -1008,7 +1009,8 @@ int device_cus() {
 
 template <typename T, int ME, int TX, int TY, int NT, int WPE>
 int launch_sweep_yee(const Mesh& m, void* const Ein[3], void* const Bin[3], void* const J[3], void* const Eout[3],
-                     void* const Bout[3], const SweepCoef<T, ME, 1>& c, int tiles_x, int tiles, hipStream_t s) {
+                     void* const Bout[3], const SweepCoef<T, ME, 1>& c, int tiles_x, int tiles, int wgs_per_cu,
+                     hipStream_t s) {
   using G = YeeGeom<T, ME, TX, TY>;
   const bool hasJ = J && J[0];
   auto kern = hasJ ? sweep_yee_kernel<T, ME, TX, TY, NT, WPE, true> : sweep_yee_kernel<T, ME, TX, TY, NT, WPE, false>;
@@ -1016,11 +1018,18 @@ int launch_sweep_yee(const Mesh& m, void* const Ein[3], void* const Bin[3], void
   if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G::lds_bytes) !=
       hipSuccess)
     return set_error(PIC_EHIP, "sweep: cannot reserve %zu bytes of LDS", G::lds_bytes);
-  hipLaunchKernelGGL(kern, dim3(tiles), dim3(NT), G::lds_bytes, s, (const T*)Ein[0], (const T*)Ein[1],
+  // too few tiles to fill the chip: split the x3 march into chunks (each one
+  // re-reads the two planes before it)
+  int nz = 1;
+  const int want = wgs_per_cu * device_cus();
+  if (tiles < want) nz = min(m.n3, (want + tiles - 1) / tiles);
+  const int KZ = (m.n3 + nz - 1) / nz;
+  nz = (m.n3 + KZ - 1) / KZ;
+  hipLaunchKernelGGL(kern, dim3(tiles, nz), dim3(NT), G::lds_bytes, s, (const T*)Ein[0], (const T*)Ein[1],
                      (const T*)Ein[2], (const T*)Bin[0], (const T*)Bin[1], (const T*)Bin[2],
                      (const T*)(hasJ ? J[0] : nullptr), (const T*)(hasJ ? J[1] : nullptr),
                      (const T*)(hasJ ? J[2] : nullptr), (T*)Eout[0], (T*)Eout[1], (T*)Eout[2], (T*)Bout[0],
-                     (T*)Bout[1], (T*)Bout[2], m, tiles_x, tiles, c);
+                     (T*)Bout[1], (T*)Bout[2], m, tiles_x, tiles, KZ, c);
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "sweep launch failed");
 }
 
@@ -1041,8 +1050,8 @@ int run_sweep_yee(const Mesh& m, void* const Ein[3], void* const Bin[3], void* c
   // there are at least two tiles per CU.  FP64 takes one workgroup per CU.
   if constexpr (sizeof(T) == 4)
     if (tiles >= 2 * device_cus())
-      return launch_sweep_yee<T, ME, TX, TY, NT, 4>(m, Ein, Bin, J, Eout, Bout, c, tiles_x, tiles, s);
-  return launch_sweep_yee<T, ME, TX, TY, NT, 2>(m, Ein, Bin, J, Eout, Bout, c, tiles_x, tiles, s);
+      return launch_sweep_yee<T, ME, TX, TY, NT, 4>(m, Ein, Bin, J, Eout, Bout, c, tiles_x, tiles, 2, s);
+  return launch_sweep_yee<T, ME, TX, TY, NT, 2>(m, Ein, Bin, J, Eout, Bout, c, tiles_x, tiles, 1, s);
 }
 
 template <typename T, int ME, int MB, int TX, int TY, int NT>
