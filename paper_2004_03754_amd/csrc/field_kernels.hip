@@ -19,12 +19,6 @@ struct Taps {
   T a[W];
 };
 
-__device__ __forceinline__ int wrap1(int i, int n) {
-  i += (i < 0) ? n : 0;
-  i -= (i >= n) ? n : 0;
-  return i;
-}
-
 // ---------------------------------------------------------------------------
 // Standalone steps.  A block of kSB threads owns kSB consecutive x1 cells of
 // one (x2, x3) row; the two components under the wide x1 stencil are staged
@@ -1046,11 +1040,11 @@ int run_sweep_yee(const Mesh& m, void* const Ein[3], void* const Bin[3], void* c
   c.dt = (T)dt;
   const int tiles_x = (m.n1 + TX - 1) / TX;
   const int tiles = tiles_x * ((m.n2 + TY - 1) / TY);
-  // FP32 tiles fit two workgroups per CU (LDS and 128 VGPRs); that pays once
-  // there are at least two tiles per CU.  FP64 takes one workgroup per CU.
+  // FP32 tiles fit two workgroups per CU (LDS and 128 VGPRs), with the x3
+  // march split when the mesh has fewer than two tiles per CU.  FP64 takes
+  // one workgroup per CU.
   if constexpr (sizeof(T) == 4)
-    if (tiles >= 2 * device_cus())
-      return launch_sweep_yee<T, ME, TX, TY, NT, 4>(m, Ein, Bin, J, Eout, Bout, c, tiles_x, tiles, 2, s);
+    return launch_sweep_yee<T, ME, TX, TY, NT, 4>(m, Ein, Bin, J, Eout, Bout, c, tiles_x, tiles, 2, s);
   return launch_sweep_yee<T, ME, TX, TY, NT, 2>(m, Ein, Bin, J, Eout, Bout, c, tiles_x, tiles, 1, s);
 }
 
