@@ -32,51 +32,79 @@ namespace {
 using namespace pdev;
 
 constexpr int kLags = PIC_MAX_M;  // every coefficient of the vector gets a gradient
-constexpr int kRow = 256;         // cells of x1 per block of the coefficient reduction
-constexpr int kRows = 16;         // x1 rows each block accumulates before reducing
+constexpr int kCT = 256;           // threads of a coefficient-reduction block
+constexpr int kCRW = 4;            // consecutive x1 cells per thread
+constexpr int kRow = kCT * kCRW;   // cells of x1 per block
+constexpr int kRows = 8;           // x1 rows each block accumulates before reducing
 
 // Partial sums  acc_j = sum_i la_i D_j(fa)_i - lb_i D_j(fb)_i,  j = 1..kLags,
 // over kRow cells of each of kRows consecutive x1 rows;  D_j f_i = f_{i+j} -
 // f_{i-j+1} (FORM 0, Faraday) or f_{i+j-1} - f_{i-j} (FORM 1, Ampere).  Block
 // b covers rows (b / nbx) * kRows .. + kRows (clipped to nrows) and cells
-// [(b % nbx) kRow, + kRow) of each; every thread keeps its kLags sums in
-// registers over the rows, then the block reduces them once.
+// [(b % nbx) kRow, + kRow) of each.  Each row segment of fa and fb is staged
+// in LDS; a thread reads the 2 kLags + kCRW values around its kCRW cells once
+// per array (16-byte reads), keeps its kLags sums in registers over the rows,
+// and the block reduces them once.
 template <int FORM>
-__global__ __launch_bounds__(kRow) void coef_partial_kernel(const double* __restrict__ la,
-                                                            const double* __restrict__ fa,
-                                                            const double* __restrict__ lb,
-                                                            const double* __restrict__ fb, int n1, int nbx,
-                                                            int nrows, double* __restrict__ partial) {
-  __shared__ double sa[kRow + 2 * kLags], sb[kRow + 2 * kLags];
-  __shared__ double red[kRow / 64][kLags];
+__global__ __launch_bounds__(kCT) void coef_partial_kernel(const double* __restrict__ la,
+                                                           const double* __restrict__ fa,
+                                                           const double* __restrict__ lb,
+                                                           const double* __restrict__ fb, int n1, int nbx,
+                                                           int nrows, double* __restrict__ partial) {
+  constexpr int NW = kCRW + 2 * kLags;  // window of one thread (index k: cell ib - kLags + k)
+  __shared__ __align__(16) double sa[kRow + 2 * kLags];
+  __shared__ __align__(16) double sb[kRow + 2 * kLags];
+  __shared__ double red[kCT / 64][kLags];
   const int r0 = (blockIdx.x / nbx) * kRows;
   const int r1 = min(r0 + kRows, nrows);
   const int i0 = (blockIdx.x % nbx) * kRow;
-  const int i = i0 + (int)threadIdx.x;
-  const int c = threadIdx.x + kLags;  // LDS slot of cell i
+  const int t = threadIdx.x;
+  const int ib = i0 + kCRW * t;  // first cell of this thread
   double acc[kLags];
 #pragma unroll
   for (int j = 0; j < kLags; ++j) acc[j] = 0.0;
   for (int rr = r0; rr < r1; ++rr) {
     const size_t row = (size_t)rr * n1;
     __syncthreads();  // the previous row's reads are done
-    for (int t = threadIdx.x; t < kRow + 2 * kLags; t += kRow) {
-      int ii = (i0 - kLags + t) % n1;
+    for (int q = t; q < kRow + 2 * kLags; q += kCT) {
+      int ii = (i0 - kLags + q) % n1;
       ii += (ii < 0) ? n1 : 0;
-      sa[t] = fa[row + ii];
-      sb[t] = fb[row + ii];
+      sa[q] = fa[row + ii];
+      sb[q] = fb[row + ii];
     }
     __syncthreads();
-    const double a = (i < n1) ? la[row + i] : 0.0;
-    const double b = (i < n1) ? lb[row + i] : 0.0;
+    double a[kCRW], b[kCRW];
 #pragma unroll
-    for (int j = 1; j <= kLags; ++j) {
-      const int hi = FORM == 0 ? c + j : c + j - 1;
-      const int lo = FORM == 0 ? c - j + 1 : c - j;
-      acc[j - 1] += a * (sa[hi] - sa[lo]) - b * (sb[hi] - sb[lo]);
+    for (int u = 0; u < kCRW; ++u) {
+      a[u] = (ib + u < n1) ? la[row + ib + u] : 0.0;
+      b[u] = (ib + u < n1) ? lb[row + ib + u] : 0.0;
+    }
+#pragma unroll
+    for (int arr = 0; arr < 2; ++arr) {
+      double w[NW];
+      {
+        typedef double v2 __attribute__((ext_vector_type(2)));
+        const v2* src = reinterpret_cast<const v2*>((arr == 0 ? sa : sb) + kCRW * t);
+#pragma unroll
+        for (int k = 0; k < NW / 2; ++k) {
+          const v2 v = src[k];
+          w[2 * k] = v[0];
+          w[2 * k + 1] = v[1];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kCRW; ++u) {
+        const double x = arr == 0 ? a[u] : -b[u];
+#pragma unroll
+        for (int j = 1; j <= kLags; ++j) {
+          const int hi = FORM == 0 ? kLags + u + j : kLags + u + j - 1;
+          const int lo = FORM == 0 ? kLags + u - j + 1 : kLags + u - j;
+          acc[j - 1] += x * (w[hi] - w[lo]);
+        }
+      }
     }
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = t & 63, wave = t >> 6;
 #pragma unroll
   for (int j = 0; j < kLags; ++j) {
     double v = acc[j];
@@ -85,11 +113,11 @@ __global__ __launch_bounds__(kRow) void coef_partial_kernel(const double* __rest
     if (lane == 0) red[wave][j] = v;
   }
   __syncthreads();
-  if (threadIdx.x < kLags) {
+  if (t < kLags) {
     double s = 0;
 #pragma unroll
-    for (int w = 0; w < kRow / 64; ++w) s += red[w][threadIdx.x];
-    partial[(size_t)blockIdx.x * kLags + threadIdx.x] = s;
+    for (int w = 0; w < kCT / 64; ++w) s += red[w][t];
+    partial[(size_t)blockIdx.x * kLags + t] = s;
   }
 }
 
@@ -447,10 +475,10 @@ int launch_coef_grad(const Mesh& m, int form, const double* la, const double* fa
   const int nblocks = coef_partial_blocks(m);
   const int nrows = m.n2 * m.n3;
   if (form == 0)
-    hipLaunchKernelGGL(coef_partial_kernel<0>, dim3(nblocks), dim3(kRow), 0, s, la, fa, lb, fb, m.n1, nbx, nrows,
+    hipLaunchKernelGGL(coef_partial_kernel<0>, dim3(nblocks), dim3(kCT), 0, s, la, fa, lb, fb, m.n1, nbx, nrows,
                        partial);
   else
-    hipLaunchKernelGGL(coef_partial_kernel<1>, dim3(nblocks), dim3(kRow), 0, s, la, fa, lb, fb, m.n1, nbx, nrows,
+    hipLaunchKernelGGL(coef_partial_kernel<1>, dim3(nblocks), dim3(kCT), 0, s, la, fa, lb, fb, m.n1, nbx, nrows,
                        partial);
   hipLaunchKernelGGL(coef_finalize_kernel, dim3(M), dim3(256), 0, s, (const double*)partial, nblocks, scale, g);
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "coefficient-gradient launch failed");
