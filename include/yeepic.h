@@ -95,6 +95,8 @@ typedef struct pic_adjoint {
   double *gCB;         /* device, PIC_MAX_M doubles: dL/dC^B_j, accumulated (+=) for j < M */
   const void *En[3];   /* optional (all six or none): the forward state at t^{n+1}, E ... */
   const void *Bn[3];   /* ... and B, read only; when given the step recomputes no sweep */
+  const void *Bh[3];   /* optional (with En, Bn; all three or none): B^{n+1/2} of the step,
+                          read only; when given the step rebuilds nothing */
 } pic_adjoint;
 
 /* ---- coefficient design (host only; App. B) ------------------------------
@@ -181,11 +183,13 @@ int pic_step_n(pic_grid *g, pic_particles *const *species, int nspecies, int nst
  * of each species at the grid's fields (particles advanced in place), then
  * the fused sweep (Eq. maxwell, App. B operators) from the grid's fields
  * into Eout, Bout (device, same shape and precision, 16-byte aligned, not
- * the grid's own arrays: PIC_EINVAL).  The grid's fields are not modified.
- * For callers that keep a sequence of states (e.g. recomputation between
- * adjoint checkpoints) without copying them. */
+ * the grid's own arrays: PIC_EINVAL).  If Bhalf is not NULL, its three
+ * arrays (same rules) also receive the half-step field B^{n+1/2} =
+ * B^n - dt/2 curl_E E^n.  The grid's fields are not modified.  For callers
+ * that keep a sequence of states (e.g. recomputation between adjoint
+ * checkpoints) without copying them. */
 int pic_step_to(pic_grid *g, pic_particles *const *species, int nspecies, int pusher,
-                void *const Eout[3], void *const Bout[3]);
+                void *const Eout[3], void *const Bout[3], void *const Bhalf[3]);
 /* Steps between particle re-sorts in pic_step_n (1..64, default 3); the
  * on-chip current tile grows with the interval (|v| < c bounds the drift). */
 int pic_set_sort_interval(pic_grid *g, int steps);
@@ -204,16 +208,17 @@ int pic_set_sort_interval(pic_grid *g, int steps);
  * The field part uses the transposition of the App. B operators
  * (curl_E[C]^T = curl_B[C]).  It needs E^{n+1} and B^{n+1/2}: with adj->En,
  * adj->Bn given (the forward state at t^{n+1}, which must not alias lE, lB
- * or the grid's fields) it rebuilds B^{n+1/2} = B^{n+1} + dt/2 curl_E E^{n+1}
- * in the grid's second field set, else it first recomputes the forward sweep
- * there.  The position wrap is a constant shift (derivative
+ * or the grid's fields) it uses adj->Bh as B^{n+1/2} if given (as written
+ * by pic_step_to), else rebuilds B^{n+1/2} = B^{n+1} + dt/2 curl_E E^{n+1}
+ * in the grid's second field set; without En, Bn it first recomputes the
+ * forward sweep there.  The position wrap is a constant shift (derivative
  * the identity); at a cell face the shape function has a kink, and the
  * derivative taken is the one of the cell the particle is in.  The exact
  * pusher's proper time tau_r solves t(tau) = dt; its derivative is taken
  * implicitly: d tau_r / d theta = -(d t / d theta at fixed tau) / gamma(tau_r).
  * PIC_EUNSUPPORTED for FP32-field grids; PIC_EINVAL for another pusher; the
- * coefficient reduction allocates a scratch of 16 doubles per 256 cells of
- * x1 row at the first call (PIC_ENOMEM if that fails).  Scatter into lE, lB
+ * coefficient reduction allocates a scratch of 16 doubles per 1024 cells of
+ * 8 x1 rows at the first call (PIC_ENOMEM if that fails).  Scatter into lE, lB
  * uses atomics, so the field cotangents vary in the last bits between runs. */
 int pic_adjoint_step(pic_grid *g, const pic_adjoint *adj, const pic_particles *const *species,
                      pic_particles *const *lambda, int nspecies, int pusher);

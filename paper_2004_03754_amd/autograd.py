@@ -5,9 +5,10 @@ Forward: ``nsteps`` steps of gather + push (Boris or exact) + position update + 
 field sweep (pic_step_n), keeping a checkpoint of the state (E, B, x, u)
 every ``K`` steps.  Backward: the segments are walked in reverse; each one is
 recomputed from its checkpoint one step at a time (pic_step_to, each state
-written into its own buffer of K + 1), then reversed step by step with
-pic_adjoint_step, which maps the cotangents of (E, B, x, u) from t^{n+1} to
-t^n, given both states, and accumulates dL/dC^E and dL/dC^B.
+written into its own buffer of K + 1, and each step's half-step field B^{n+1/2}
+into one of K more), then reversed step by step with pic_adjoint_step, which
+maps the cotangents of (E, B, x, u) from t^{n+1} to t^n, given both states and
+B^{n+1/2}, and accumulates dL/dC^E and dL/dC^B.
 The forward arithmetic is deterministic, so a recomputed state equals the
 stored forward state bit for bit.
 
@@ -82,6 +83,7 @@ class PICRun(torch.autograd.Function):
         K = min(cfg.K, cfg.nsteps)
         # K + 1 state buffers: a segment's states t^{s0} .. t^{s0+n}
         slots = [_clone_state(E0, B0, x0, u0) for _ in range(K + 1)]
+        halves = [[torch.empty_like(v) for v in B0] for _ in range(K)]  # B^{n+1/2} of each step
         grid = b.Grid(slots[0][0], slots[0][1], cfg.dx, cfg.dt, ce, cb, ndim=cfg.ndim)
         lam = b.Particles(lx, lu, q=cfg.q, m=cfg.m, w=cfg.w)
         nseg = len(ctx.checkpoints)
@@ -101,7 +103,7 @@ class PICRun(torch.autograd.Function):
                 cur[3].copy_(prev[3])
                 grid.set_fields(prev[0], prev[1])
                 p = b.Particles(cur[2], cur[3], q=cfg.q, m=cfg.m, w=cfg.w)
-                grid.step_to([p] if p.np else [], cur[0], cur[1], pusher=cfg.pusher)
+                grid.step_to([p] if p.np else [], cur[0], cur[1], pusher=cfg.pusher, B_half=halves[i - 1])
             # reverse the segment (the particle adjoint needs x, u at t^n: the
             # previous buffer's, since step_to advanced the copies)
             for i in reversed(range(n)):
@@ -109,9 +111,10 @@ class PICRun(torch.autograd.Function):
                 grid.set_fields(st[0], st[1])
                 p = b.Particles(st[2], st[3], q=cfg.q, m=cfg.m, w=cfg.w)
                 if p.np:
-                    grid.adjoint_step(lE, lB, gCE, gCB, [p], [lam], pusher=cfg.pusher, next_E=nx[0], next_B=nx[1])
+                    grid.adjoint_step(lE, lB, gCE, gCB, [p], [lam], pusher=cfg.pusher, next_E=nx[0], next_B=nx[1],
+                                      half_B=halves[i])
                 else:
-                    grid.adjoint_step(lE, lB, gCE, gCB, next_E=nx[0], next_B=nx[1])
+                    grid.adjoint_step(lE, lB, gCE, gCB, next_E=nx[0], next_B=nx[1], half_B=halves[i])
         grid.sync()
         grid.close()
         dtype, device, M = ctx.coef_meta

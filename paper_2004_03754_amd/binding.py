@@ -46,7 +46,8 @@ class _Particles(ctypes.Structure):
 
 class _Adjoint(ctypes.Structure):
     _fields_ = [("lE", ctypes.c_void_p * 3), ("lB", ctypes.c_void_p * 3), ("gCE", ctypes.c_void_p),
-                ("gCB", ctypes.c_void_p), ("En", ctypes.c_void_p * 3), ("Bn", ctypes.c_void_p * 3)]
+                ("gCB", ctypes.c_void_p), ("En", ctypes.c_void_p * 3), ("Bn", ctypes.c_void_p * 3),
+                ("Bh", ctypes.c_void_p * 3)]
 
 
 EXPORTS = ["pic_design_coeffs", "pic_init_grid", "pic_set_fields", "pic_advance_B_half", "pic_advance_E",
@@ -75,7 +76,7 @@ def lib():
         L.pic_set_sort_interval.argtypes = [vp, i]
         PP = ctypes.POINTER(ctypes.POINTER(_Particles))
         L.pic_adjoint_step.argtypes = [vp, ctypes.POINTER(_Adjoint), PP, PP, i, i]
-        L.pic_step_to.argtypes = [vp, PP, i, i, ctypes.c_void_p * 3, ctypes.c_void_p * 3]
+        L.pic_step_to.argtypes = [vp, PP, i, i, ctypes.c_void_p * 3, ctypes.c_void_p * 3, ctypes.c_void_p]
         L.pic_sync.argtypes = [vp]
         L.pic_check.argtypes = [vp, ctypes.POINTER(_Particles)]
         L.pic_grid_widths.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i)]
@@ -184,16 +185,18 @@ class Grid:
         self.E, self.B, self.J = list(E), list(B), (list(J) if J is not None else None)
         _check(lib().pic_set_fields(self._h, _ptr3(E), _ptr3(B), _ptr3(J)))
 
-    def adjoint_step(self, lE, lB, gCE, gCB, species=(), lambdas=(), pusher="boris", next_E=None, next_B=None):
+    def adjoint_step(self, lE, lB, gCE, gCB, species=(), lambdas=(), pusher="boris", next_E=None, next_B=None,
+                     half_B=None):
         """Reverse of one vacuum step from the grid's current state (see
         pic_adjoint_step): lE, lB (FP64, field layout) and the particle
         cotangents in ``lambdas`` are mapped from t^{n+1} to t^n in place;
         gCE, gCB (16 doubles on the device) are accumulated.  next_E, next_B:
-        the forward state at t^{n+1}, if the caller has it."""
+        the forward state at t^{n+1}, if the caller has it; half_B (with
+        them): the step's B^{n+1/2}, as step_to writes it."""
         adj = _Adjoint()
         adj.lE, adj.lB = _ptr3(lE), _ptr3(lB)
         adj.gCE, adj.gCB = gCE.data_ptr(), gCB.data_ptr()
-        adj.En, adj.Bn = _ptr3(next_E), _ptr3(next_B)
+        adj.En, adj.Bn, adj.Bh = _ptr3(next_E), _ptr3(next_B), _ptr3(half_B)
         ns = len(species)
         assert len(lambdas) == ns
         a = (ctypes.POINTER(_Particles) * max(1, ns))()
@@ -242,13 +245,16 @@ class Grid:
             arr[s] = ctypes.pointer(p._s)
         _check(lib().pic_step_n(self._h, arr, len(species), int(nsteps), PUSHERS[pusher], int(deposit)))
 
-    def step_to(self, species, E_out, B_out, pusher="boris"):
+    def step_to(self, species, E_out, B_out, pusher="boris", B_half=None):
         """One vacuum step from the grid's fields into E_out, B_out (see
-        pic_step_to); particles advance in place."""
+        pic_step_to); particles advance in place.  B_half (optional, three
+        arrays like B_out) receives the step's B^{n+1/2}."""
         arr = (ctypes.POINTER(_Particles) * max(1, len(species)))()
         for s_, p in enumerate(species):
             arr[s_] = ctypes.pointer(p._s)
-        _check(lib().pic_step_to(self._h, arr, len(species), PUSHERS[pusher], _ptr3(E_out), _ptr3(B_out)))
+        half = _ptr3(B_half) if B_half is not None else None
+        _check(lib().pic_step_to(self._h, arr, len(species), PUSHERS[pusher], _ptr3(E_out), _ptr3(B_out),
+                                 ctypes.cast(half, ctypes.c_void_p) if half is not None else None))
 
     def set_sort_interval(self, steps):
         _check(lib().pic_set_sort_interval(self._h, int(steps)))

@@ -275,10 +275,10 @@ int pic_advance_E(pic_grid* g, int use_J) {
 }
 
 static int sweep_once(pic_grid* g, void* const inE[3], void* const inB[3], void* const outE[3],
-                      void* const outB[3], int use_J) {
+                      void* const outB[3], int use_J, void* const half[3] = nullptr) {
   void* none[3] = {nullptr, nullptr, nullptr};
-  return launch_sweep(g->prec, g->mesh, inE, inB, use_J ? g->J : none, outE, outB, g->CE, g->ME, g->CB, g->MB,
-                      g->dt, g->stream);
+  return launch_sweep(g->prec, g->mesh, inE, inB, use_J ? g->J : none, outE, outB, half, g->CE, g->ME, g->CB,
+                      g->MB, g->dt, g->stream);
 }
 
 int pic_field_sweep(pic_grid* g, int use_J) {
@@ -468,7 +468,7 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
 }
 
 int pic_step_to(pic_grid* g, pic_particles* const* species, int nspecies, int pusher, void* const Eout[3],
-                void* const Bout[3]) {
+                void* const Bout[3], void* const Bhalf[3]) {
   if (!g || !Eout || !Bout) return set_error(PIC_EINVAL, "pic_step_to: NULL argument");
   if (nspecies < 0) return set_error(PIC_EINVAL, "negative count");
   if (nspecies > 0 && !species) return set_error(PIC_EINVAL, "species is NULL");
@@ -480,6 +480,14 @@ int pic_step_to(pic_grid* g, pic_particles* const* species, int nspecies, int pu
       if (Eout[c] == g->E[q] || Eout[c] == g->B[q] || Bout[c] == g->E[q] || Bout[c] == g->B[q])
         return set_error(PIC_EINVAL, "pic_step_to: output aliases the grid's fields");
   }
+  if (Bhalf)
+    for (int c = 0; c < 3; ++c) {
+      if (!Bhalf[c]) return set_error(PIC_EINVAL, "half-step field pointer is NULL");
+      if ((uintptr_t)Bhalf[c] & 15) return set_error(PIC_ESHAPE, "fields must be 16-byte aligned");
+      for (int q = 0; q < 3; ++q)
+        if (Bhalf[c] == g->E[q] || Bhalf[c] == g->B[q] || Bhalf[c] == Eout[q] || Bhalf[c] == Bout[q])
+          return set_error(PIC_EINVAL, "pic_step_to: half-step output aliases another field");
+    }
   for (int s = 0; s < nspecies; ++s) {
     int rc = check_particles(g, species[s]);
     if (rc) return rc;
@@ -488,7 +496,7 @@ int pic_step_to(pic_grid* g, pic_particles* const* species, int nspecies, int pu
     int rc = launch_gather_push(g->prec, g->mesh, g->E, g->B, *species[s], pusher, g->dt, nullptr, g->stream);
     if (rc) return rc;
   }
-  return sweep_once(g, g->E, g->B, Eout, Bout, 0);
+  return sweep_once(g, g->E, g->B, Eout, Bout, 0, Bhalf);
 }
 
 int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* const* species,
@@ -530,11 +538,22 @@ int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* c
   auto d = [](const void* p) { return (const double*)p; };
   void* const* lE = adj->lE;
   void* const* lB = adj->lB;
-  void* const* aB = g->alt + 3;
-  // forward intermediates: E' = E^{n+1}, and B' = B^{n+1/2} recomputed as
-  // B^{n+1} + dt/2 curl_E E^{n+1} into the second field set.  E^{n+1}, B^{n+1}
-  // come from the caller when given, else from a forward sweep.
+  // forward intermediates: E' = E^{n+1}, and B' = B^{n+1/2}, given by the
+  // caller or recomputed as B^{n+1} + dt/2 curl_E E^{n+1} into the second
+  // field set.  E^{n+1}, B^{n+1} come from the caller when given, else from a
+  // forward sweep.
   const bool next = adj->En[0] && adj->En[1] && adj->En[2] && adj->Bn[0] && adj->Bn[1] && adj->Bn[2];
+  const bool half = next && adj->Bh[0] && adj->Bh[1] && adj->Bh[2];
+  void* hB[3] = {g->alt[3], g->alt[4], g->alt[5]};
+  if (half)
+    for (int c = 0; c < 3; ++c) {
+      if ((uintptr_t)adj->Bh[c] & 15) return set_error(PIC_ESHAPE, "adjoint fields must be 16-byte aligned");
+      for (int q = 0; q < 3; ++q)
+        if (adj->Bh[c] == lE[q] || adj->Bh[c] == lB[q])
+          return set_error(PIC_EINVAL, "the half-step field aliases a cotangent");
+      hB[c] = const_cast<void*>(adj->Bh[c]);
+    }
+  void* const* aB = hB;
   void* nE[3] = {g->alt[0], g->alt[1], g->alt[2]};
   void* nB[3] = {g->alt[3], g->alt[4], g->alt[5]};
   int rc = PIC_OK;
@@ -547,7 +566,7 @@ int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* c
     rc = sweep_once(g, g->E, g->B, g->alt, g->alt + 3, 0);
   }
   void* const* aE = nE;
-  if (!rc) rc = launch_advance_b(g->prec, m, nE, nB, g->alt + 3, g->CE, g->ME, -0.5 * dt, g->stream);
+  if (!rc && !half) rc = launch_advance_b(g->prec, m, nE, nB, g->alt + 3, g->CE, g->ME, -0.5 * dt, g->stream);
   // third stage B'' = B' - dt/2 curl_E[C^E] E': dC^E from (lB, E')
   if (!rc) rc = launch_coef_grad(m, 0, d(lB[1]), d(aE[2]), d(lB[2]), d(aE[1]), 0.5 * dt / m.dx1, g->M, g->partial,
                                  adj->gCE, g->stream);

@@ -734,8 +734,9 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
                                                        const T* __restrict__ J3, T* __restrict__ oE1,
                                                        T* __restrict__ oE2, T* __restrict__ oE3,
                                                        T* __restrict__ oB1, T* __restrict__ oB2,
-                                                       T* __restrict__ oB3, Mesh m, int tiles_x, int tiles,
-                                                       int KZ, SweepCoef<T, ME, 1> c) {
+                                                       T* __restrict__ oB3, T* __restrict__ oH1,
+                                                       T* __restrict__ oH2, T* __restrict__ oH3, Mesh m,
+                                                       int tiles_x, int tiles, int KZ, SweepCoef<T, ME, 1> c) {
   using G = YeeGeom<T, ME, TX, TY>;
   using V = typename Vec16<T>::type;
   constexpr int R = G::R, RW = G::RW, HB = G::HB;
@@ -782,6 +783,9 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
   const int g1 = t1 ? gj(tr - 1) * m.n1 + gi(x) : 0;
   const int g2 = t2 ? gj(tr) * m.n1 + gi(x) : 0;
   const bool out = t3 && j0 + tr < m.n2 && i0 + x < m.n1;
+  // stage-1 tasks on the tile also write B^{n+1/2} (when oH1 is given)
+  const bool out_h = oH1 && t1 && tr >= 1 && tr <= TY && tg >= G::GT0 && tg < G::GT0 + G::NGT &&
+                     j0 + tr - 1 < m.n2 && i0 + x < m.n1;
   const int wcol = RW * tg;  // LDS column of the task's window / B-extent position
 
   // E plane loader: slot s of component q covers vector tid + s NT of that
@@ -881,6 +885,7 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
           o3[u] = bn[2][u] - (faraday_w<T, ME, HB>(w, c.ae, u) - c.hy * (e1n[u] - e1c[u]));
         }
         st_run<T, RW>(bo + 2 * G::SB, o3);
+        if (out_h && ka >= k0 && ka < kend) st_run<T, RW>(oH3 + poff(ka) + g1, o3);
       }
       {  // B2 and B1
         T w[G::NWIN], e3n[RW], o1[RW], o2[RW];
@@ -893,6 +898,11 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
         }
         st_run<T, RW>(bo, o1);
         st_run<T, RW>(bo + G::SB, o2);
+        if (out_h && ka >= k0 && ka < kend) {
+          const size_t o = poff(ka) + g1;
+          st_run<T, RW>(oH1 + o, o1);
+          st_run<T, RW>(oH2 + o, o2);
+        }
       }
       if (more) load_own(ka + 1);
     }
@@ -1003,8 +1013,8 @@ int device_cus() {
 
 template <typename T, int ME, int TX, int TY, int NT, int WPE>
 int launch_sweep_yee(const Mesh& m, void* const Ein[3], void* const Bin[3], void* const J[3], void* const Eout[3],
-                     void* const Bout[3], const SweepCoef<T, ME, 1>& c, int tiles_x, int tiles, int wgs_per_cu,
-                     hipStream_t s) {
+                     void* const Bout[3], void* const Bh[3], const SweepCoef<T, ME, 1>& c, int tiles_x, int tiles,
+                     int wgs_per_cu, hipStream_t s) {
   using G = YeeGeom<T, ME, TX, TY>;
   const bool hasJ = J && J[0];
   auto kern = hasJ ? sweep_yee_kernel<T, ME, TX, TY, NT, WPE, true> : sweep_yee_kernel<T, ME, TX, TY, NT, WPE, false>;
@@ -1023,13 +1033,15 @@ int launch_sweep_yee(const Mesh& m, void* const Ein[3], void* const Bin[3], void
                      (const T*)Ein[2], (const T*)Bin[0], (const T*)Bin[1], (const T*)Bin[2],
                      (const T*)(hasJ ? J[0] : nullptr), (const T*)(hasJ ? J[1] : nullptr),
                      (const T*)(hasJ ? J[2] : nullptr), (T*)Eout[0], (T*)Eout[1], (T*)Eout[2], (T*)Bout[0],
-                     (T*)Bout[1], (T*)Bout[2], m, tiles_x, tiles, KZ, c);
+                     (T*)Bout[1], (T*)Bout[2], (T*)(Bh ? Bh[0] : nullptr), (T*)(Bh ? Bh[1] : nullptr),
+                     (T*)(Bh ? Bh[2] : nullptr), m, tiles_x, tiles, KZ, c);
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "sweep launch failed");
 }
 
 template <typename T, int ME, int TX, int TY, int NT>
 int run_sweep_yee(const Mesh& m, void* const Ein[3], void* const Bin[3], void* const J[3], void* const Eout[3],
-                  void* const Bout[3], const double* CE, int MEr, const double* CB, double dt, hipStream_t s) {
+                  void* const Bout[3], void* const Bh[3], const double* CE, int MEr, const double* CB, double dt,
+                  hipStream_t s) {
   SweepCoef<T, ME, 1> c;
   for (int q = 0; q < ME; ++q) c.ae[q] = (T)(q < MEr ? CE[q] * (dt / 2) / m.dx1 : 0.0);
   c.ab[0] = (T)(CB[0] * dt / m.dx1);
@@ -1044,8 +1056,8 @@ int run_sweep_yee(const Mesh& m, void* const Ein[3], void* const Bin[3], void* c
   // march split when the mesh has fewer than two tiles per CU.  FP64 takes
   // one workgroup per CU.
   if constexpr (sizeof(T) == 4)
-    return launch_sweep_yee<T, ME, TX, TY, NT, 4>(m, Ein, Bin, J, Eout, Bout, c, tiles_x, tiles, 2, s);
-  return launch_sweep_yee<T, ME, TX, TY, NT, 2>(m, Ein, Bin, J, Eout, Bout, c, tiles_x, tiles, 1, s);
+    return launch_sweep_yee<T, ME, TX, TY, NT, 4>(m, Ein, Bin, J, Eout, Bout, Bh, c, tiles_x, tiles, 2, s);
+  return launch_sweep_yee<T, ME, TX, TY, NT, 2>(m, Ein, Bin, J, Eout, Bout, Bh, c, tiles_x, tiles, 1, s);
 }
 
 template <typename T, int ME, int MB, int TX, int TY, int NT>
@@ -1079,20 +1091,25 @@ int run_sweep(const Mesh& m, void* const Ein[3], void* const Bin[3], void* const
 
 template <typename T, int TXn, int TY, int NT>
 int dispatch_sweep(const Mesh& m, void* const Ein[3], void* const Bin[3], void* const J[3], void* const Eout[3],
-                   void* const Bout[3], const double* CE, int ME, const double* CB, int MB, double dt,
-                   hipStream_t s) {
+                   void* const Bout[3], void* const Bh[3], const double* CE, int ME, const double* CB, int MB,
+                   double dt, hipStream_t s) {
   const int we = round_width(ME), wb = round_width(MB);
   const int w = we > wb ? we : wb;
   // Ampere stencil either Yee (width 1) or padded to the Faraday width
   if (wb == 1) {
     constexpr int YT = 8;  // rows per tile of the Yee-Ampere sweep
     switch (we) {
-      case 1: return run_sweep_yee<T, 1, 128, YT, NT>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, dt, s);
-      case 2: return run_sweep_yee<T, 2, 128, YT, NT>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, dt, s);
-      case 4: return run_sweep_yee<T, 4, 128, YT, NT>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, dt, s);
-      case 8: return run_sweep_yee<T, 8, 128, YT, NT>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, dt, s);
-      default: return run_sweep_yee<T, 16, 128, YT, NT>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, dt, s);
+      case 1: return run_sweep_yee<T, 1, 128, YT, NT>(m, Ein, Bin, J, Eout, Bout, Bh, CE, ME, CB, dt, s);
+      case 2: return run_sweep_yee<T, 2, 128, YT, NT>(m, Ein, Bin, J, Eout, Bout, Bh, CE, ME, CB, dt, s);
+      case 4: return run_sweep_yee<T, 4, 128, YT, NT>(m, Ein, Bin, J, Eout, Bout, Bh, CE, ME, CB, dt, s);
+      case 8: return run_sweep_yee<T, 8, 128, YT, NT>(m, Ein, Bin, J, Eout, Bout, Bh, CE, ME, CB, dt, s);
+      default: return run_sweep_yee<T, 16, 128, YT, NT>(m, Ein, Bin, J, Eout, Bout, Bh, CE, ME, CB, dt, s);
     }
+  }
+  // general Ampere stencil: B^{n+1/2} (when asked for) from its own half step
+  if (Bh && Bh[0]) {
+    const int rc = dispatch_b<T>(m, Ein, Bin, Bh, CE, ME, dt / 2, s);
+    if (rc) return rc;
   }
   switch (w) {
     case 2: return run_sweep<T, 2, 2, TXn, TY, NT>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, MB, dt, s);
@@ -1118,11 +1135,12 @@ int launch_advance_b(int prec, const Mesh& m, void* const E[3], void* const B[3]
 }
 
 int launch_sweep(int prec, const Mesh& m, void* const Ein[3], void* const Bin[3], void* const J[3],
-                 void* const Eout[3], void* const Bout[3], const double* CE, int ME, const double* CB, int MB,
-                 double dt, void* stream) {
+                 void* const Eout[3], void* const Bout[3], void* const Bh[3], const double* CE, int ME,
+                 const double* CB, int MB, double dt, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  if (prec == PIC_FP64) return dispatch_sweep<double, 64, 4, 512>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, MB, dt, s);
-  return dispatch_sweep<float, 128, 8, 512>(m, Ein, Bin, J, Eout, Bout, CE, ME, CB, MB, dt, s);
+  if (prec == PIC_FP64)
+    return dispatch_sweep<double, 64, 4, 512>(m, Ein, Bin, J, Eout, Bout, Bh, CE, ME, CB, MB, dt, s);
+  return dispatch_sweep<float, 128, 8, 512>(m, Ein, Bin, J, Eout, Bout, Bh, CE, ME, CB, MB, dt, s);
 }
 
 int launch_advance_e(int prec, const Mesh& m, void* const E[3], void* const B[3], void* const J[3],

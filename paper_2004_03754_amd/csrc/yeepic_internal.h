@@ -38,9 +38,10 @@ int launch_advance_b(int prec, const Mesh& m, void* const E[3], void* const B[3]
 int launch_advance_e(int prec, const Mesh& m, void* const E[3], void* const B[3],
                      void* const J[3], const double* CB, int MB, double dt, void* stream);
 // Fused B-half / E / B-half sweep from (Ein, Bin) to (Eout, Bout); J may be
-// all-null.  In and out must not alias.
+// all-null; Bh, if not NULL, also receives B^{n+1/2}.  In and out must not
+// alias.
 int launch_sweep(int prec, const Mesh& m, void* const Ein[3], void* const Bin[3],
-                 void* const J[3], void* const Eout[3], void* const Bout[3],
+                 void* const J[3], void* const Eout[3], void* const Bout[3], void* const Bh[3],
                  const double* CE, int ME, const double* CB, int MB, double dt, void* stream);
 
 // Particle kernels (particle_kernels.hip).

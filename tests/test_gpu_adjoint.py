@@ -229,6 +229,46 @@ def test_step_to_and_given_next_state(coeffs16):
     g2.close()
 
 
+@pytest.mark.parametrize("ampere", ["yee", "wide"])
+def test_step_to_half_field_output(ampere, coeffs16):
+    """pic_step_to's optional B^{n+1/2} equals the separate Faraday half step
+    (pic_advance_B_half) from the same E^n, B^n; an adjoint step handed it
+    equals one that rebuilds it.  "yee": the width-1 Ampere stencil (fused
+    Yee sweep writes it from its first stage); "wide": a width-3 Ampere
+    stencil (the general sweep, B^{n+1/2} from its own half step)."""
+    CE, CB = coeffs16
+    if ampere == "wide":
+        CB = np.zeros(16)
+        CB[:3] = [1.2, -0.1, 0.02]
+    n = (256, 12, 3)
+    E, B, x, u = _case(n, 61, 80, 3, u_th=0.5)
+    grid = b.Grid([dev(e) for e in E], [dev(v) for v in B], DX, wl.DT, CE, CB)
+    Eo, Bo = [torch.empty_like(grid.E[0]) for _ in range(3)], [torch.empty_like(grid.B[0]) for _ in range(3)]
+    Bh = [torch.full_like(grid.B[0], np.nan) for _ in range(3)]
+    print(f"step_to B_half: {ampere} Ampere stencil, {n}", flush=True)
+    grid.step_to([b.Particles(dev(x), dev(u), q=QM, m=1.0)], Eo, Bo, B_half=Bh)
+    grid.sync()
+    ref = b.Grid([dev(e) for e in E], [dev(v) for v in B], DX, wl.DT, CE, CB)
+    ref.advance_B_half()
+    ref.sync()
+    for a, c in zip(Bh, ref.B):
+        assert _rel(host(a), host(c)) <= 1e-14
+    lE, lB, lx, lu = _cotangents(n, 80, 62)
+    outs = []
+    for half in (None, Bh):
+        grid.set_fields([dev(e) for e in E], [dev(v) for v in B])
+        lEd, lBd, lxd, lud = [dev(a) for a in lE], [dev(a) for a in lB], dev(lx), dev(lu)
+        gC = [torch.zeros(16, dtype=torch.float64, device="cuda:0") for _ in range(2)]
+        grid.adjoint_step(lEd, lBd, gC[0], gC[1], [b.Particles(dev(x), dev(u), q=QM, m=1.0)],
+                          [b.Particles(lxd, lud, q=QM, m=1.0)], next_E=Eo, next_B=Bo, half_B=half)
+        grid.sync()
+        outs.append([host(a) for a in lEd + lBd + [lxd, lud] + gC])
+    for a, c in zip(*outs):
+        assert _rel(a, c) <= 1e-13
+    grid.close()
+    ref.close()
+
+
 def _run_autograd(CE, CB, E, B, x, u, cfg, w):
     from paper_2004_03754_amd import autograd as pa
     Ef, Bf, xf, uf = pa.run(CE, CB, E, B, x, u, cfg)
