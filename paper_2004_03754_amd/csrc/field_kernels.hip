@@ -801,18 +801,21 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
   for (int s = 0; s < N1S; ++s) ga1[s] = tid + s * NT < G::L1 ? slot_g(tid + s * NT, G::WB / R, HB) : 0;
 #pragma unroll
   for (int s = 0; s < N2S; ++s) ga2[s] = tid + s * NT < G::L2 ? slot_g(tid + s * NT, G::WE / R, 2 * HB) : 0;
+  // Every thread issues every global load of the march, whether or not it
+  // uses the value (idle slots and tasks read the plane's first vector), and
+  // past the last plane as well.  The compiler's wait counts take the fewest
+  // memory operations any path issues after a load; with no load under a
+  // branch, stage 1 waits only for the loads of the plane before, not for the
+  // E-plane prefetch issued at the top of the iteration.
   V pe3[N3S], pe1[N1S], pe2[N2S];
   auto load_E = [&](int k) {
     const size_t o = poff(k);
 #pragma unroll
-    for (int s = 0; s < N3S; ++s)
-      if (tid + s * NT < G::L3) pe3[s] = *reinterpret_cast<const V*>(iE3 + o + ga3[s]);
+    for (int s = 0; s < N3S; ++s) pe3[s] = *reinterpret_cast<const V*>(iE3 + o + ga3[s]);
 #pragma unroll
-    for (int s = 0; s < N1S; ++s)
-      if (tid + s * NT < G::L1) pe1[s] = *reinterpret_cast<const V*>(iE1 + o + ga1[s]);
+    for (int s = 0; s < N1S; ++s) pe1[s] = *reinterpret_cast<const V*>(iE1 + o + ga1[s]);
 #pragma unroll
-    for (int s = 0; s < N2S; ++s)
-      if (tid + s * NT < G::L2) pe2[s] = *reinterpret_cast<const V*>(iE2 + o + ga2[s]);
+    for (int s = 0; s < N2S; ++s) pe2[s] = *reinterpret_cast<const V*>(iE2 + o + ga2[s]);
   };
   auto lds_at = [&](int v, int wv, int pitch) {
     const int row = v / wv;
@@ -859,8 +862,8 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
   const int k0 = blockIdx.y * KZ, kend = min(m.n3, k0 + KZ);
   load_E(k0 - 1);
   store_E();
-  if (t1) load_own(k0 - 1);
-  if (t2) load_J(k0 - 1);
+  load_own(k0 - 1);
+  load_J(k0 - 1);
 #pragma unroll
   for (int q = 0; q < 3; ++q)
 #pragma unroll
@@ -869,7 +872,7 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
 
   for (int ka = k0 - 1; ka <= kend; ++ka) {
     const bool more = ka < kend;
-    if (more) load_E(ka + 1);
+    load_E(ka + 1);
     // ---- stage 1: B^{n+1/2}(ka) on the B extent ----
     if (t1) {
       T* bo = sB + tr * G::PB + wcol;
@@ -904,8 +907,8 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
           st_run<T, RW>(oH2 + o, o2);
         }
       }
-      if (more) load_own(ka + 1);
     }
+    load_own(ka + 1);
     __syncthreads();
     // ---- stage 2: E^{n+1}(ka) on the E^{n+1} extent ----
     T g1c[RW], g2c[RW];
@@ -952,8 +955,8 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
         st_run<T, RW>(oE2 + o, g2c);
         st_run<T, RW>(oE3 + o, f3);
       }
-      if (more) load_J(ka + 1);
     }
+    load_J(ka + 1);
     // ---- stage 3: B^{n+1}(ka-1) on the tile ----
     if (t3 && ka - 1 >= k0) {
       const T* f = sF + ((ka - 1) & 1) * 3 * G::SF + tr * G::PB;
