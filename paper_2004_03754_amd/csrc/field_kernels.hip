@@ -664,10 +664,11 @@ __global__ __launch_bounds__(NT) void sweep_kernel(const T* __restrict__ iE1, co
 //   E2:        columns [-2HB, TX+2HB), rows -1..TY
 //   E3:        columns [-2HB, TX+2HB), rows -1..TY+1
 // ---------------------------------------------------------------------------
-template <typename T, int ME, int TX, int TY>
+template <typename T, int ME, int TX, int TY_>
 struct YeeGeom {
   static constexpr int R = 16 / (int)sizeof(T);  // elements per 16-byte vector
   static constexpr int RW = 4;                    // outputs per task
+  static constexpr int TY = TY_;
   static constexpr int VW = RW / R;               // vectors per task row segment
   static constexpr int HB = ME <= 4 ? 4 : ME;     // B and E^{n+1} halo (>= ME, multiple of 4)
   static constexpr int WB = TX + 2 * HB, WE = TX + 4 * HB;
@@ -685,11 +686,45 @@ struct YeeGeom {
   static constexpr size_t lds_bytes = sizeof(T) * (size_t)NLDS;
   static constexpr int CG = sizeof(T) == 8 ? 8 : 16, CR = 16 / CG;  // task groups x rows per 16 lanes
   static constexpr int NCX = (NGX + CG - 1) / CG;
-  static constexpr int NTASK = (PYB + CR - 1) / CR * NCX * 16;
+  // task slots: the NT3 tile positions, the halo groups of the tile rows, then
+  // rows TY .. PYB-1 (see yee_task)
+  static constexpr int NT3 = TY * NGT, NH = 2 * GT0 * TY;
+  static constexpr int NTASK = NT3 + NH + (PYB - TY + CR - 1) / CR * NCX * 16;
   // E plane loader: 16-byte vectors of E3 (PYE x WE), E1 (PYE x WB), E2 ((PYE-1) x WE)
   static constexpr int L3 = PYE * (WE / R), L1 = PYE * (WB / R), L2 = (PYE - 1) * (WE / R);
   static constexpr int NLV = L3 + L1 + L2;
 };
+
+// Task position (row tr, group tg) of task slot t.  Slots [0, NT3) hold the
+// tile positions (rows 0..TY-1, groups GT0..GT0+NGT-1) in chunks of CG groups
+// x CR rows per 16 lanes, so that they fill whole waves, one per SIMD at 256
+// slots; slots [NT3, NT3+NH) the 2 GT0 halo groups of each tile row, row by
+// row; then rows TY..PYB-1 in CG x CR chunks.  A slot past the last position
+// gets tr = PYB (no task).  16 consecutive lanes read 16-byte LDS vectors at
+// distinct bank quads in each part (row pitches of 2 mod 4 elements at FP64).
+template <class G>
+__device__ __forceinline__ void yee_task(int t, int& tr, int& tg) {
+  const int l16 = t & 15, gl = l16 % G::CG, rl = l16 / G::CG;
+  static_assert(G::NGT % G::CG == 0 && G::NT3 % 16 == 0 && G::NH % 16 == 0, "task layout");
+  if (t < G::NT3) {
+    constexpr int cpr = G::NGT / G::CG;  // chunks per band of CR rows
+    const int c = t >> 4;
+    tr = (c / cpr) * G::CR + rl;
+    tg = G::GT0 + (c % cpr) * G::CG + gl;
+    return;
+  }
+  t -= G::NT3;
+  if (t < G::NH) {
+    const int h = t % (2 * G::GT0);
+    tr = t / (2 * G::GT0);
+    tg = h < G::GT0 ? h : G::NGT + h;
+    return;
+  }
+  const int c = (t - G::NH) >> 4;
+  tr = G::TY + (c / G::NCX) * G::CR + rl;
+  tg = (c % G::NCX) * G::CG + gl;
+  if (tg >= G::NGX || tr >= G::PYB) tr = G::PYB;
+}
 
 // RW aligned consecutive elements as 16-byte vectors (LDS or global memory)
 template <typename T, int RW>
@@ -771,18 +806,25 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
   };
 
   // this thread's task: group tg (columns x .. x+RW-1), row tr
-  const int chunk = tid >> 4, l16 = tid & 15;
-  const int rp = chunk / G::NCX, cx = chunk - rp * G::NCX;
-  const int tg = cx * G::CG + l16 % G::CG;
-  const int tr = rp * G::CR + l16 / G::CG;
+  int tr, tg;
+  yee_task<G>(tid, tr, tg);
   const int x = -HB + RW * tg;
-  const bool t1 = chunk < G::NTASK / 16 && tg < G::NGX && tr < G::PYB;  // B^{n+1/2} row tr-1
-  const bool t2 = t1 && tr < G::PYF;                                      // E^{n+1} row tr
-  const bool t3 = t2 && tr < TY && tg >= G::GT0 && tg < G::GT0 + G::NGT;   // tile output
+  const bool t1 = tr < G::PYB;        // B^{n+1/2} row tr-1
+  const bool t2 = tr < G::PYF;        // E^{n+1} row tr
+  const bool t3 = tid < G::NT3;       // tile output (B1, B2 of stage 3)
+  // stage 3's B3 at tile position tid - NT3 is computed by this thread: the
+  // two waves of each SIMD share the tile's stage 3
+  static_assert(2 * G::NT3 <= NT, "stage-3 split needs two slots per tile position");
+  const bool w3 = tid >= G::NT3 && tid < 2 * G::NT3;
+  int tr3, tg3;
+  yee_task<G>(w3 ? tid - G::NT3 : 0, tr3, tg3);
+  const int x3 = -HB + RW * tg3, wcol3 = RW * tg3;
   // in-plane offsets of the task's first element (a plane holds < 2^31 cells)
   const int g1 = t1 ? gj(tr - 1) * m.n1 + gi(x) : 0;
   const int g2 = t2 ? gj(tr) * m.n1 + gi(x) : 0;
   const bool out = t3 && j0 + tr < m.n2 && i0 + x < m.n1;
+  const bool out3 = w3 && j0 + tr3 < m.n2 && i0 + x3 < m.n1;
+  const int g3 = out3 ? gj(tr3) * m.n1 + gi(x3) : 0;
   // stage-1 tasks on the tile also write B^{n+1/2} (when oH1 is given)
   const bool out_h = oH1 && t1 && tr >= 1 && tr <= TY && tg >= G::GT0 && tg < G::GT0 + G::NGT &&
                      j0 + tr - 1 < m.n2 && i0 + x < m.n1;
@@ -958,44 +1000,43 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
     }
     load_J(ka + 1);
     // ---- stage 3: B^{n+1}(ka-1) on the tile ----
-    if (t3 && ka - 1 >= k0) {
+    if (t3 && ka - 1 >= k0) {  // B2 and B1 at the thread's own tile position
       const T* f = sF + ((ka - 1) & 1) * 3 * G::SF + tr * G::PB;
-      const size_t o = poff(ka - 1) + g2;
-      T f1c[RW], f2w[RW];
+      T w[G::NWIN], f1c[RW], f2c[RW], f3n[RW], o1[RW], o2[RW];
       ld_run<T, RW>(f + wcol, f1c);
-      {  // B3 from the x1 derivative of E2 and the x2 difference of E1
-        T w[G::NWIN], f1n[RW], o3[RW];
-        load_window<T, G::NWV, R>(f + G::SF + wcol - HB, w);
-        ld_run<T, RW>(f + G::PB + wcol, f1n);
+      ld_run<T, RW>(f + G::SF + wcol, f2c);
+      load_window<T, G::NWV, R>(f + 2 * G::SF + wcol - HB, w);
+      ld_run<T, RW>(f + 2 * G::SF + G::PB + wcol, f3n);
 #pragma unroll
-        for (int u = 0; u < RW; ++u) {
-          f2w[u] = w[u + HB];
-          o3[u] = cb[2][u] - (faraday_w<T, ME, HB>(w, c.ae, u) - c.hy * (f1n[u] - f1c[u]));
-        }
-        if (out) st_run<T, RW>(oB3 + o, o3);
+      for (int u = 0; u < RW; ++u) {
+        o2[u] = cb[1][u] - (c.hz * (g1c[u] - f1c[u]) - faraday_w<T, ME, HB>(w, c.ae, u));
+        o1[u] = cb[0][u] - (c.hy * (f3n[u] - w[u + HB]) - c.hz * (g2c[u] - f2c[u]));
       }
-      {  // B2 and B1
-        T w[G::NWIN], f3n[RW], o1[RW], o2[RW];
-        load_window<T, G::NWV, R>(f + 2 * G::SF + wcol - HB, w);
-        ld_run<T, RW>(f + 2 * G::SF + G::PB + wcol, f3n);
-#pragma unroll
-        for (int u = 0; u < RW; ++u) {
-          o2[u] = cb[1][u] - (c.hz * (g1c[u] - f1c[u]) - faraday_w<T, ME, HB>(w, c.ae, u));
-          o1[u] = cb[0][u] - (c.hy * (f3n[u] - w[u + HB]) - c.hz * (g2c[u] - f2w[u]));
-        }
-        if (out) {
-          st_run<T, RW>(oB1 + o, o1);
-          st_run<T, RW>(oB2 + o, o2);
-        }
+      if (out) {
+        const size_t o = poff(ka - 1) + g2;
+        st_run<T, RW>(oB1 + o, o1);
+        st_run<T, RW>(oB2 + o, o2);
       }
     }
-    // B^{n+1/2}(ka) at this task's positions, for stage 2 at ka+1 and stage 3 at ka
+    if (w3 && ka - 1 >= k0) {  // B3 from the x1 derivative of E2 and the x2 difference of E1
+      const T* f = sF + ((ka - 1) & 1) * 3 * G::SF + tr3 * G::PB;
+      T w[G::NWIN], f1c[RW], f1n[RW], o3[RW];
+      ld_run<T, RW>(f + wcol3, f1c);
+      load_window<T, G::NWV, R>(f + G::SF + wcol3 - HB, w);
+      ld_run<T, RW>(f + G::PB + wcol3, f1n);
+#pragma unroll
+      for (int u = 0; u < RW; ++u)
+        o3[u] = cb[2][u] - (faraday_w<T, ME, HB>(w, c.ae, u) - c.hy * (f1n[u] - f1c[u]));
+      if (out3) st_run<T, RW>(oB3 + poff(ka - 1) + g3, o3);
+    }
+    // B^{n+1/2}(ka) for stage 2 at ka+1 (components 1, 2 at the task's
+    // position) and stage 3 at ka (component 3 at the B3 position)
     if (t2) {
       const T* b = sB + (tr + 1) * G::PB + wcol;
       ld_run<T, RW>(b, cb[0]);
       ld_run<T, RW>(b + G::SB, cb[1]);
-      ld_run<T, RW>(b + 2 * G::SB, cb[2]);
     }
+    if (w3) ld_run<T, RW>(sB + 2 * G::SB + (tr3 + 1) * G::PB + wcol3, cb[2]);
     __syncthreads();
     if (more) store_E();
     __syncthreads();
