@@ -850,8 +850,7 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
   // branch, stage 1 waits only for the loads of the plane before, not for the
   // E-plane prefetch issued at the top of the iteration.
   V pe3[N3S], pe1[N1S], pe2[N2S];
-  auto load_E = [&](int k) {
-    const size_t o = poff(k);
+  auto load_E = [&](size_t o) {  // o: offset of the plane
 #pragma unroll
     for (int s = 0; s < N3S; ++s) pe3[s] = *reinterpret_cast<const V*>(iE3 + o + ga3[s]);
 #pragma unroll
@@ -882,17 +881,17 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
   };
 
   T bn[3][RW], nn[2][RW], cb[3][RW], jv[HAS_J ? 3 : 1][RW];
-  auto load_own = [&](int k) {  // B^n(k), E1/E2(k+1) at the stage-1 positions
-    const size_t o = poff(k) + g1, on = poff(k + 1) + g1;
+  auto load_own = [&](size_t pk, size_t pk1) {  // B^n(k), E1/E2(k+1) at the stage-1 positions
+    const size_t o = pk + g1, on = pk1 + g1;
     ld_run<T, RW>(iB1 + o, bn[0]);
     ld_run<T, RW>(iB2 + o, bn[1]);
     ld_run<T, RW>(iB3 + o, bn[2]);
     ld_run<T, RW>(iE1 + on, nn[0]);
     ld_run<T, RW>(iE2 + on, nn[1]);
   };
-  auto load_J = [&](int k) {
+  auto load_J = [&](size_t pk) {
     if constexpr (HAS_J) {
-      const size_t o = poff(k) + g2;
+      const size_t o = pk + g2;
       ld_run<T, RW>(J1 + o, jv[0]);
       ld_run<T, RW>(J2 + o, jv[1]);
       ld_run<T, RW>(J3 + o, jv[2]);
@@ -902,10 +901,16 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
   // ---- prologue: E(k0-1) in LDS; B^n(k0-1), E1/E2(k0) own, J(k0-1) ----
   // (the march covers planes k0 .. kend-1: one x3 chunk of KZ planes)
   const int k0 = blockIdx.y * KZ, kend = min(m.n3, k0 + KZ);
-  load_E(k0 - 1);
+  // offsets of planes ka-1 .. ka+2: at FP64 carried from plane to plane (a
+  // quarter of the loop's scalar instructions), at FP32 recomputed (carried
+  // offsets push the 128-VGPR FP32 build into spilling)
+  constexpr bool carry = sizeof(T) == 8;
+  const size_t wrap = (size_t)m.n3 * plane_sz;
+  size_t cm1 = poff(k0 - 2), c0 = poff(k0 - 1), c1 = poff(k0), c2 = poff(k0 + 1);
+  load_E(c0);
   store_E();
-  load_own(k0 - 1);
-  load_J(k0 - 1);
+  load_own(c0, c1);
+  load_J(c0);
 #pragma unroll
   for (int q = 0; q < 3; ++q)
 #pragma unroll
@@ -914,7 +919,11 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
 
   for (int ka = k0 - 1; ka <= kend; ++ka) {
     const bool more = ka < kend;
-    load_E(ka + 1);
+    auto pl = [&](int d) -> size_t {  // offset of plane ka+d, d = -1 .. 2
+      if constexpr (carry) return d < 0 ? cm1 : d == 0 ? c0 : d == 1 ? c1 : c2;
+      else return poff(ka + d);
+    };
+    load_E(pl(1));
     // ---- stage 1: B^{n+1/2}(ka) on the B extent ----
     if (t1) {
       T* bo = sB + tr * G::PB + wcol;
@@ -930,7 +939,7 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
           o3[u] = bn[2][u] - (faraday_w<T, ME, HB>(w, c.ae, u) - c.hy * (e1n[u] - e1c[u]));
         }
         st_run<T, RW>(bo + 2 * G::SB, o3);
-        if (out_h && ka >= k0 && ka < kend) st_run<T, RW>(oH3 + poff(ka) + g1, o3);
+        if (out_h && ka >= k0 && ka < kend) st_run<T, RW>(oH3 + pl(0) + g1, o3);
       }
       {  // B2 and B1
         T w[G::NWIN], e3n[RW], o1[RW], o2[RW];
@@ -944,13 +953,13 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
         st_run<T, RW>(bo, o1);
         st_run<T, RW>(bo + G::SB, o2);
         if (out_h && ka >= k0 && ka < kend) {
-          const size_t o = poff(ka) + g1;
+          const size_t o = pl(0) + g1;
           st_run<T, RW>(oH1 + o, o1);
           st_run<T, RW>(oH2 + o, o2);
         }
       }
     }
-    load_own(ka + 1);
+    load_own(pl(1), pl(2));
     __syncthreads();
     // ---- stage 2: E^{n+1}(ka) on the E^{n+1} extent ----
     T g1c[RW], g2c[RW];
@@ -992,13 +1001,13 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
       st_run<T, RW>(f + G::SF, g2c);
       st_run<T, RW>(f + 2 * G::SF, f3);
       if (out && ka >= k0 && ka < kend) {
-        const size_t o = poff(ka) + g2;
+        const size_t o = pl(0) + g2;
         st_run<T, RW>(oE1 + o, g1c);
         st_run<T, RW>(oE2 + o, g2c);
         st_run<T, RW>(oE3 + o, f3);
       }
     }
-    load_J(ka + 1);
+    load_J(pl(1));
     // ---- stage 3: B^{n+1}(ka-1) on the tile ----
     if (t3 && ka - 1 >= k0) {  // B2 and B1 at the thread's own tile position
       const T* f = sF + ((ka - 1) & 1) * 3 * G::SF + tr * G::PB;
@@ -1013,7 +1022,7 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
         o1[u] = cb[0][u] - (c.hy * (f3n[u] - w[u + HB]) - c.hz * (g2c[u] - f2c[u]));
       }
       if (out) {
-        const size_t o = poff(ka - 1) + g2;
+        const size_t o = pl(-1) + g2;
         st_run<T, RW>(oB1 + o, o1);
         st_run<T, RW>(oB2 + o, o2);
       }
@@ -1027,7 +1036,7 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
 #pragma unroll
       for (int u = 0; u < RW; ++u)
         o3[u] = cb[2][u] - (faraday_w<T, ME, HB>(w, c.ae, u) - c.hy * (f1n[u] - f1c[u]));
-      if (out3) st_run<T, RW>(oB3 + poff(ka - 1) + g3, o3);
+      if (out3) st_run<T, RW>(oB3 + pl(-1) + g3, o3);
     }
     // B^{n+1/2}(ka) for stage 2 at ka+1 (components 1, 2 at the task's
     // position) and stage 3 at ka (component 3 at the B3 position)
@@ -1040,6 +1049,13 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
     __syncthreads();
     if (more) store_E();
     __syncthreads();
+    if constexpr (carry) {
+      cm1 = c0;
+      c0 = c1;
+      c1 = c2;
+      c2 += plane_sz;
+      if (c2 >= wrap) c2 -= wrap;
+    }
   }
 }
 
