@@ -20,7 +20,9 @@ fdtd        leapfrog field step on the Yee mesh with different x1 operators in
 particles   staggered linear-shape gather (App. A), Boris pusher, exact
             constant-field pusher, leapfrog position update, Esirkepov
             charge-conserving deposit (Sec. 3.3)
-pic         the per-step driver: push, deposit, fused field sweep
+current     x1 current correction for a wide Ampere stencil (Sec. 3.3)
+pic         the per-step driver: push, deposit, current correction, fused
+            field sweep
 trajectory  closed-form electron trajectory in a plane wave (Sec. 4.1,
             canonical momentum conservation)
 adjoint     FP64 adjoint of the field sweep, gather and pushers

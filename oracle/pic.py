@@ -5,17 +5,17 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 Per step (Eq. pusher time levels; Sec. 3.3 for the source):
   1. gather E^n, B^n at x^n (App. A) and push u^{n-1/2} -> u^{n+1/2}
   2. advance x^n -> x^{n+1} (second order, Sec. 4.1)
-  3. deposit J^{n+1/2} from (x^n, x^{n+1}) (charge conserving, Sec. 3.3).
-     The x1 current correction of Eq. (correction) is the identity when
-     [k]_B1 equals the Yee symbol, which is exactly the case dt = dx1/2 of
-     the proposed solver; other cases are rejected here.
+  3. deposit J^{n+1/2} from (x^n, x^{n+1}) (charge conserving, Sec. 3.3),
+     then the x1 current correction of Eq. (correction) (``current``), which
+     is the identity when [k]_B1 equals the Yee symbol (the proposed solver
+     at dt = dx1/2) and is skipped there.
   4. field sweep (E^n, B^n) -> (E^{n+1}, B^{n+1}) with J^{n+1/2}.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import fdtd, particles
+from . import current, fdtd, particles
 
 
 def _ampere_is_yee(CB):
@@ -32,8 +32,6 @@ def step(E, B, species, CE, CB, dx, dt, *, pusher="boris", deposit=False, ndim=3
     n3, n2, n1 = shape
     L = [n1 * dx[0], n2 * dx[1], n3 * dx[2]][:ndim]
     J = [np.zeros(shape) for _ in range(3)] if deposit else None
-    if deposit and not _ampere_is_yee(CB):
-        raise ValueError("current correction other than the identity is not implemented")
     for sp in species:
         Ep, Bp = particles.gather(E, B, sp["x"], dx, ndim)
         qm = sp["q"] / sp["m"]
@@ -51,6 +49,8 @@ def step(E, B, species, CE, CB, dx, dt, *, pusher="boris", deposit=False, ndim=3
             Js = particles.deposit(x_old, x_new, sp["q"], sp["w"], dx, dt, shape, ndim, u=u)
             J = [a + b for a, b in zip(J, Js)]
         sp["x"], sp["u"] = x_new, u
+    if deposit and not _ampere_is_yee(CB):
+        J[0] = current.correct_x1(J[0], CB, dx[0])
     return fdtd.sweep(E, B, J, CE, CB, dx, dt)
 
 

@@ -86,6 +86,12 @@ def target(kind: str, kappa, r):
     kind 'E': [k]_E1 / k_g1 = tan(pi kappa r)/(pi r)      (Eq. new_op)
     kind 'B': [k]_B1 / k_g1 = sin(2 pi kappa r)/(2 pi r)  (Eq. new_op)
     kind 'xu': [k]_{1,t} / k_g1 = sin(pi kappa r)/(pi r)  (Xu solver, Sec. 4)
+    kind 'yeet_E', 'yeet_B': the Yee t-stagger solver (Sec. 4, third solver
+        of the comparison), read as Eq. (new_op) with [k]_{1,t} replaced by
+        the Yee symbol, so that [k]_E1 [k]_B1 = [k]_Yee^2 (Yee dispersion) and
+        [k]_E1/[k]_B1 = 1/cos^2(k1 dt/2) (time-stagger correction):
+        [k]_E1/k_g1 = sin(pi kappa)/(pi cos(pi kappa r)),
+        [k]_B1/k_g1 = sin(pi kappa) cos(pi kappa r)/pi.
     Works for mpmath or numpy arguments.
     """
     lib = mp if isinstance(kappa, mp.mpf) or isinstance(r, mp.mpf) else np
@@ -96,6 +102,10 @@ def target(kind: str, kappa, r):
         return lib.sin(2 * pi * kappa * r) / (2 * pi * r)
     if kind == "xu":
         return lib.sin(pi * kappa * r) / (pi * r)
+    if kind == "yeet_E":
+        return lib.sin(pi * kappa) / (pi * lib.cos(pi * kappa * r))
+    if kind == "yeet_B":
+        return lib.sin(pi * kappa) * lib.cos(pi * kappa * r) / pi
     raise ValueError(kind)
 
 

@@ -26,3 +26,11 @@ def coeffs16():
     oracle's App. B fit (printed weight, n = 10, w_k1 = 0.4)."""
     from oracle import stencil
     return stencil.fit_pair(16, 0.5)
+
+
+@pytest.fixture(scope="session")
+def coeffs16_quarter():
+    """Proposed-solver coefficients (C^E, C^B), M = 16, dt = dx1/4 (the
+    paper's Sec. 4.1 ratio), where C^B is a wide Ampere stencil."""
+    from oracle import stencil
+    return stencil.fit_pair(16, 0.25)

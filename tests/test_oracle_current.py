@@ -1,0 +1,96 @@
+"""Pins of the oracle's x1 current correction (Sec. 3.3) and of the Yee
+t-stagger coefficient targets (Sec. 4), at dt = dx1/4 where the proposed
+solver's Ampere stencil is wide (CPU only)."""
+import numpy as np
+import pytest
+
+from oracle import current, fdtd, particles as pt, pic, stencil
+from paper_2004_03754_amd import workloads as wl
+
+DX = (wl.DX1, wl.DX2, wl.DX3)
+DT4 = wl.DX1 / 4
+
+
+def test_corrected_current_has_the_yee_divergence(coeffs16_quarter):
+    """Sec. 3.3: the corrected current's x1 divergence with the wide Ampere
+    stencil equals the deposited current's Yee divergence, both taken with
+    the field step's real-space stencils (no FFT); the x1 mean is kept."""
+    _, CB = coeffs16_quarter
+    J1 = np.random.default_rng(5).standard_normal((3, 4, 64))
+    JA = current.correct_x1(J1, CB, wl.DX1)
+    lhs = fdtd.d1_ampere(JA, CB, wl.DX1)
+    rhs = fdtd.d1_ampere(J1, [1.0], wl.DX1)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-12 * np.max(np.abs(rhs))
+    assert np.max(np.abs(JA.mean(-1) - J1.mean(-1))) <= 1e-14 * np.max(np.abs(J1))
+    assert np.max(np.abs(JA - J1)) > 1e-3 * np.max(np.abs(J1))  # not the identity here
+
+
+def test_correction_is_identity_for_yee_stencil():
+    J1 = np.random.default_rng(6).standard_normal((2, 3, 48))
+    CB = np.r_[1.0, np.zeros(15)]
+    assert np.max(np.abs(current.correct_x1(J1, CB, wl.DX1) - J1)) <= 1e-15 * np.max(np.abs(J1))
+
+
+def test_correction_rejects_vanishing_ampere_symbol():
+    """[k]_B1 = 0 at the x1 Nyquist mode for C^B = (1/4, 1/4) (which meets
+    the order constraint): no ratio exists."""
+    with pytest.raises(ValueError):
+        current.correction_ratio([0.25, 0.25], 16, wl.DX1)
+
+
+def _plasma(n, seed, npart):
+    L = [n[d] * DX[d] for d in range(3)]
+    E, B = wl.random_fields(n, seed=seed, scale=0.05)
+    x, u = wl.uniform_particles(npart, [0, 0, 0], L, seed=seed + 1, u_th=0.3)
+    return E, B, {"x": x, "u": u, "q": -1.0, "m": 1.0, "w": 0.01}
+
+
+@pytest.mark.parametrize("pusher", ["boris", "analytic"])
+def test_gauss_law_preserved_with_wide_ampere_stencil(pusher, coeffs16_quarter):
+    """Sec. 3.3: with the corrected current, div_B E - rho stays at its
+    initial value to roundoff for the wide C^B of dt = dx1/4."""
+    CE, CB = coeffs16_quarter
+    n = (32, 6, 5)
+    shape = (n[2], n[1], n[0])
+    E, B, sp = _plasma(n, 41, 400)
+    gauss0 = fdtd.div_ampere(E, CB, DX) - pt.charge_density(sp["x"], -1.0, 0.01, DX, shape)
+    for _ in range(8):
+        E, B = pic.step(E, B, [sp], CE, CB, DX, DT4, pusher=pusher, deposit=True)
+    gauss = fdtd.div_ampere(E, CB, DX) - pt.charge_density(sp["x"], -1.0, 0.01, DX, shape)
+    scale = np.max(np.abs(fdtd.div_ampere(E, CB, DX)))
+    assert np.max(np.abs(gauss - gauss0)) < 1e-12 * scale
+
+
+def test_gauss_law_drifts_without_correction(coeffs16_quarter, monkeypatch):
+    """The same run with the correction replaced by the identity (a planted
+    mistake) breaks Gauss's law by many orders more than roundoff."""
+    CE, CB = coeffs16_quarter
+    monkeypatch.setattr(current, "correct_x1", lambda J1, CB_, dx1: J1)
+    n = (32, 6, 5)
+    shape = (n[2], n[1], n[0])
+    E, B, sp = _plasma(n, 41, 400)
+    gauss0 = fdtd.div_ampere(E, CB, DX) - pt.charge_density(sp["x"], -1.0, 0.01, DX, shape)
+    for _ in range(8):
+        E, B = pic.step(E, B, [sp], CE, CB, DX, DT4, deposit=True)
+    gauss = fdtd.div_ampere(E, CB, DX) - pt.charge_density(sp["x"], -1.0, 0.01, DX, shape)
+    scale = np.max(np.abs(fdtd.div_ampere(E, CB, DX)))
+    assert np.max(np.abs(gauss - gauss0)) > 1e-6 * scale
+
+
+def test_yee_t_stagger_coefficients():
+    """Sec. 4 (third solver): the fitted pair keeps Yee's dispersion,
+    [k]_E1 [k]_B1 = [k]_Yee^2, and carries the time-stagger correction,
+    [k]_E1/[k]_B1 = 1/cos^2(k1 dt/2), over the fitted band; the symbols are
+    evaluated from the coefficients, not from the targets."""
+    r = 0.25
+    CE = np.array([float(c) for c in stencil.fit_coeffs(16, r, "yeet_E")])
+    CB = np.array([float(c) for c in stencil.fit_coeffs(16, r, "yeet_B")])
+    kappa = np.linspace(0.005, 0.15, 60)
+    k = 2 * np.pi * kappa / wl.DX1
+    kE, kB = stencil.symbol(CE, k, wl.DX1), stencil.symbol(CB, k, wl.DX1)
+    kY = stencil.yee_symbol(k, wl.DX1)
+    dt = r * wl.DX1
+    assert np.max(np.abs(kE * kB / kY**2 - 1)) < 1e-10
+    assert np.max(np.abs(kE / kB * np.cos(k * dt / 2) ** 2 - 1)) < 1e-10
+    # and it is neither the Yee pair nor the proposed one
+    assert abs(CE[0] - 1) > 1e-3 and abs(CB[0] - 1) > 1e-3
