@@ -56,7 +56,18 @@ typedef enum {
 
 typedef enum { PIC_FP64 = 0, PIC_FP32_FIELDS = 1 } pic_precision;
 typedef enum { PIC_PUSH_BORIS = 0, PIC_PUSH_ANALYTIC = 1 } pic_pusher;
-typedef enum { PIC_TARGET_E = 0, PIC_TARGET_B = 1, PIC_TARGET_XU = 2 } pic_target;
+/* Coefficient targets (k-space operators divided by k_g1 = 2 pi/dx1, at
+ * kappa = k1/k_g1, r = dt/dx1): Eq. (new_op) E and B; the Xu solver's
+ * [k]_{1,t} (Sec. 4); the Yee t-stagger pair of Sec. 4, read as Eq. (new_op)
+ * with the Yee symbol in place of [k]_{1,t}: sin(pi kappa)/(pi cos(pi kappa r))
+ * for E and sin(pi kappa) cos(pi kappa r)/pi for B. */
+typedef enum {
+  PIC_TARGET_E = 0,
+  PIC_TARGET_B = 1,
+  PIC_TARGET_XU = 2,
+  PIC_TARGET_YEET_E = 3,
+  PIC_TARGET_YEET_B = 4
+} pic_target;
 
 #define PIC_MAX_M 16
 
@@ -131,17 +142,37 @@ int pic_set_fields(pic_grid *g, void *const E[3], void *const B[3], void *const 
  * pic_advance_B_half: B <- B - (dt/2) d_E x E, where along x1
  *   d^E f_i = (1/dx1) sum_j C^E_j (f_{i+j} - f_{i-j+1}) and x2, x3 use Yee
  *   forward differences.  In place.
- * pic_advance_E: E <- E + dt (d_B x B - J) with
+ * pic_advance_E: E <- E + dt (d_B x B - J_A) with
  *   d^B f_i = (1/dx1) sum_j C^B_j (f_{i+j-1} - f_{i-j}) and Yee backward
  *   differences along x2, x3; J is used only when use_J != 0 (it must then
  *   be set).  In place.
  * pic_field_sweep: one full step (E^n, B^n) -> (E^{n+1}, B^{n+1}) as a
  *   B half step, an E step and a B half step fused in one pass over the
  *   mesh (reads E, B, [J]; writes E, B).  The result ends in the caller's
- *   arrays. */
+ *   arrays.
+ * J_A, the current of Ampere's law, is J itself when C^B is the Yee stencil;
+ * otherwise its x1 component is the corrected one of pic_current_correction
+ * (Sec. 3.3), computed into library-owned memory on each such call.  J, which
+ * holds the deposited (charge-conserving) current, is never modified. */
 int pic_advance_B_half(pic_grid *g);
 int pic_advance_E(pic_grid *g, int use_J);
 int pic_field_sweep(pic_grid *g, int use_J);
+
+/* ---- x1 current correction (Sec. 3.3, Eq. correction) ----------------------
+ * Writes into J1_out the x1 current that Ampere's law uses with the grid's
+ * C^B: per Fourier mode along x1,  J_A1 = ([k]_Yee / [k]_B1) J1,  where J1 =
+ * J[0] is the deposited current (continuity holds with the Yee divergence) and
+ * [k]_B1 = sum_j C^B_j sin((2j-1) k1 dx1/2)/(dx1/2).  This is the direction for
+ * which div_B E - rho keeps its initial value; the k1 = 0 mode is kept (the
+ * order constraint makes the ratio 1 there).  The multiplier is applied as a
+ * periodic x1 convolution whose taps the library computes at pic_init_grid
+ * from the ratio on the n1 discrete modes, truncated where they fall below
+ * 2^-56 of their sum (at most 64 cells each side).  With the Yee stencil it
+ * is a copy.  J1_out: device, caller-owned, one array in the field layout and
+ * precision, 16-byte aligned, not overlapping J[0].  Returns PIC_EINVAL
+ * without J, PIC_EUNSUPPORTED if [k]_B1 vanishes at a nonzero mode or the
+ * taps do not decay within 64 cells (or n1/2 - 1). */
+int pic_current_correction(pic_grid *g, void *J1_out);
 
 /* ---- particles (App. A gather, Sec. 1 / 4.1 pushers) ---------------------
  * Gathers E^n and B^n at x^n with the linear shape, each component from its
@@ -157,16 +188,17 @@ int pic_gather_push(pic_grid *g, pic_particles *p, int pusher, double *const x_o
  * Adds the charge-conserving (Esirkepov, linear shape) current J^{n+1/2} of
  * particles that moved from x_old to p->x (less than one cell per step; the
  * periodic wrap is undone by minimum image) to the grid's J.  If zero_first
- * is non-zero J is cleared first.  The x1 correction of Eq. (correction) is
- * the identity when C^B is the Yee stencil (the proposed solver at
- * dt = dx1/2); any other C^B returns PIC_EUNSUPPORTED, and so does a 2D
- * grid without u (never: u is always present). */
+ * is non-zero J is cleared first.  J keeps the deposited current for every
+ * C^B: the x1 correction of Eq. (correction) is applied where Ampere's law
+ * reads J (see pic_advance_E and pic_current_correction). */
 int pic_deposit_J(pic_grid *g, const pic_particles *p, double *const x_old[3], int zero_first);
 
 /* ---- the step loop ----------------------------------------------------------
  * nsteps times: [clear J], for each species gather + push + position update
- * [and charge-conserving deposit], then the fused field sweep.  No host
- * synchronisation inside; the fields end in the caller's arrays.
+ * [and charge-conserving deposit], [the x1 current correction when C^B is not
+ * the Yee stencil], then the fused field sweep.  No host synchronisation
+ * inside; the fields end in the caller's arrays, J holds the last step's
+ * deposited current.
  * With deposit on a 3D grid the particles of every species are sorted by
  * spatial tile (8^3 cells) at the first step and then every
  * pic_set_sort_interval steps, and the current of each tile is accumulated in

@@ -18,7 +18,7 @@ _lib = None
 PIC_FP64, PIC_FP32_FIELDS = 0, 1
 PIC_MAX_M = 16
 PIC_PUSH_BORIS, PIC_PUSH_ANALYTIC = 0, 1
-PIC_TARGET_E, PIC_TARGET_B, PIC_TARGET_XU = 0, 1, 2
+PIC_TARGET_E, PIC_TARGET_B, PIC_TARGET_XU, PIC_TARGET_YEET_E, PIC_TARGET_YEET_B = 0, 1, 2, 3, 4
 STATUS = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ECFL", -3: "PIC_EHIP", -4: "PIC_ESHAPE",
           -5: "PIC_ENOMEM", -6: "PIC_EUNSUPPORTED", -7: "PIC_ENONFINITE"}
 PUSHERS = {"boris": PIC_PUSH_BORIS, "analytic": PIC_PUSH_ANALYTIC}
@@ -52,7 +52,8 @@ class _Adjoint(ctypes.Structure):
 
 EXPORTS = ["pic_design_coeffs", "pic_init_grid", "pic_set_fields", "pic_advance_B_half", "pic_advance_E",
            "pic_field_sweep", "pic_gather_push", "pic_deposit_J", "pic_step_n", "pic_sync", "pic_check",
-           "pic_grid_widths", "pic_destroy", "pic_last_error", "pic_set_sort_interval", "pic_adjoint_step", "pic_step_to"]
+           "pic_grid_widths", "pic_destroy", "pic_last_error", "pic_set_sort_interval", "pic_adjoint_step", "pic_step_to",
+           "pic_current_correction"]
 
 
 def lib():
@@ -70,6 +71,7 @@ def lib():
         L.pic_advance_B_half.argtypes = [vp]
         L.pic_advance_E.argtypes = [vp, i]
         L.pic_field_sweep.argtypes = [vp, i]
+        L.pic_current_correction.argtypes = [vp, vp]
         L.pic_gather_push.argtypes = [vp, ctypes.POINTER(_Particles), i, vp]
         L.pic_deposit_J.argtypes = [vp, ctypes.POINTER(_Particles), vp, i]
         L.pic_step_n.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(_Particles)), i, i, i, i]
@@ -93,7 +95,8 @@ def _check(rc):
 
 def design_coeffs(M, r, target="E", p=2, n=10, wk1=0.4, width_factor=2.0):
     """App. B customized coefficients computed by the library (host)."""
-    t = {"E": PIC_TARGET_E, "B": PIC_TARGET_B, "xu": PIC_TARGET_XU}[target]
+    t = {"E": PIC_TARGET_E, "B": PIC_TARGET_B, "xu": PIC_TARGET_XU, "yeet_E": PIC_TARGET_YEET_E,
+         "yeet_B": PIC_TARGET_YEET_B}[target]
     out = (ctypes.c_double * M)()
     _check(lib().pic_design_coeffs(M, float(r), t, p, n, float(wk1), float(width_factor), out))
     return np.array(out[:], dtype=np.float64)
@@ -219,6 +222,11 @@ class Grid:
 
     def sweep(self, use_J=False):
         _check(lib().pic_field_sweep(self._h, int(use_J)))
+
+    def current_correction(self, J1_out):
+        """The x1 current Ampere's law uses (pic_current_correction) from the
+        grid's J[0] into J1_out (one array of the field layout and precision)."""
+        _check(lib().pic_current_correction(self._h, J1_out.data_ptr()))
 
     def gather_push(self, p: Particles, pusher="boris", x_old=None):
         xo = None

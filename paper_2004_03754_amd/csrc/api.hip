@@ -1,6 +1,7 @@
 // C ABI of the yeepic library: validation, buffers, dispatch, the step loop.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -49,6 +50,13 @@ struct pic_grid {
   std::vector<SortState> vsort_a, vsort_b;
   double* partial = nullptr;  // per-block partial sums of the coefficient gradients
   int64_t partial_cap = 0;
+  // x1 current correction for a non-Yee C^B (Sec. 3.3): taps of the periodic
+  // kernel, zero-padded to corr_kw + 1, and the corrected x1 current
+  int corr_status = 0;     // PIC_OK, or why no kernel could be built
+  int corr_kw = 0;         // tap half-width used by the kernel (8, 16, 32, 64)
+  int corr_w = 0;          // last nonzero tap
+  double* corr_taps = nullptr;
+  void* Jc = nullptr;
   yeepic::Mesh mesh = {};
 };
 
@@ -102,6 +110,99 @@ static int swap_into_caller(pic_grid* g) {
 }
 
 static bool ampere_is_yee(const pic_grid* g) { return g->MB == 1 && g->CB[0] == 1.0; }
+
+// Taps of the x1 current correction (Sec. 3.3, Eq. correction): the periodic
+// kernel h whose discrete Fourier transform on the n1 modes of the x1 axis is
+//   R(theta) = [k]_Yee/[k]_B1 = sin(theta/2) / sum_j C^B_j sin((2j-1) theta/2),
+// theta = k1 dx1, with R(0) = 1/sum_j (2j-1) C^B_j.  h[m] = (1/N) sum_q
+// R(theta_q) cos(m theta_q), theta_q = 2 pi q/N, evaluated in long double with
+// N = n1 (exactly the mesh's periodic kernel) up to 16384; for longer rows
+// N = 16384, whose aliases lie 16384 cells away (negligible for any kernel
+// that passes the decay test).  The taps are cut after the last one above
+// 2^-56 of their absolute sum, looking 128 cells out; the cut must fall within
+// 64 cells and below n1/2.
+static int build_correction(pic_grid* g) {
+  const int MB = g->MB;
+  const int n1 = (int)g->n[0];
+  const int N = n1 < 16384 ? n1 : 16384;
+  const int mmax = std::min(128, N / 2);
+  std::vector<long double> h(mmax + 1, 0.0L);
+  long double csum = 0, kmax = 0;
+  for (int j = 0; j < MB; ++j) csum += (2 * j + 1) * (long double)g->CB[j];
+  const long double pi = 3.141592653589793238462643383279502884L;
+  std::vector<long double> kb(N), R(N);
+  for (int q = 0; q < N; ++q) {
+    const long double th = 2 * pi * q / N;
+    long double v = 0;
+    for (int j = 0; j < MB; ++j) v += g->CB[j] * sinl((2 * j + 1) * th / 2);
+    kb[q] = v;
+    kmax = std::max(kmax, fabsl(v));
+  }
+  for (int q = 1; q < N; ++q)
+    if (fabsl(kb[q]) <= 1e-12L * kmax) return PIC_EUNSUPPORTED;  // [k]_B1 vanishes at a mode
+  R[0] = 1.0L / csum;
+  for (int q = 1; q < N; ++q) R[q] = sinl(pi * q / N) / kb[q];
+  for (int q = 0; q < N; ++q) {
+    // cos(m theta) by the three-term recurrence
+    const long double c1 = cosl(2 * pi * q / N);
+    long double cm1 = c1, cm = 1;  // cos(-theta), cos(0)
+    for (int mm = 0; mm <= mmax; ++mm) {
+      h[mm] += R[q] * cm;
+      const long double nx = 2 * c1 * cm - cm1;
+      cm1 = cm;
+      cm = nx;
+    }
+  }
+  long double asum = 0;
+  for (int mm = 0; mm <= mmax; ++mm) {
+    h[mm] /= N;
+    asum += (mm ? 2 : 1) * fabsl(h[mm]);
+  }
+  int W = 0;
+  for (int mm = 1; mm <= mmax; ++mm)
+    if (fabsl(h[mm]) > ldexpl(asum, -56)) W = mm;
+  if (W > 64 || 2 * W >= n1) return PIC_EUNSUPPORTED;
+  const int kw = W <= 8 ? 8 : W <= 16 ? 16 : W <= 32 ? 32 : W <= 40 ? 40 : W <= 48 ? 48 : 64;
+  std::vector<double> taps(kw + 1, 0.0);
+  for (int mm = 0; mm <= W; ++mm) taps[mm] = (double)h[mm];
+  if (hipMalloc((void**)&g->corr_taps, taps.size() * sizeof(double)) != hipSuccess) return PIC_ENOMEM;
+  if (hipMemcpy(g->corr_taps, taps.data(), taps.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return PIC_EHIP;
+  g->corr_kw = kw;
+  g->corr_w = W;
+  return PIC_OK;
+}
+
+static int correction_error(const pic_grid* g) {
+  if (g->corr_status == PIC_ENOMEM) return set_error(PIC_ENOMEM, "cannot allocate the current-correction buffers");
+  if (g->corr_status == PIC_EHIP) return set_error(PIC_EHIP, "cannot upload the current-correction taps");
+  return set_error(PIC_EUNSUPPORTED,
+                   "x1 current correction: [k]_B1 vanishes at a mode or its kernel is wider than 64 cells");
+}
+
+// The corrected x1 current's buffer, for a grid with a current and a non-Yee
+// C^B (allocated once, when J is first set).
+static int ensure_jc(pic_grid* g) {
+  if (g->Jc || !g->J[0] || ampere_is_yee(g) || g->corr_status) return PIC_OK;
+  const size_t bytes = (size_t)g->n[0] * g->n[1] * g->n[2] * g->elem;
+  if (hipMalloc(&g->Jc, bytes) != hipSuccess) {
+    g->Jc = nullptr;
+    return set_error(PIC_ENOMEM, "cannot allocate the corrected x1 current");
+  }
+  return PIC_OK;
+}
+
+// The current Ampere's law uses: J, with its x1 component replaced by the
+// corrected one (written to g->Jc) when C^B is not the Yee stencil.
+static int ampere_current(pic_grid* g, void* Ja[3]) {
+  for (int c = 0; c < 3; ++c) Ja[c] = g->J[c];
+  if (ampere_is_yee(g)) return PIC_OK;
+  if (g->corr_status) return correction_error(g);
+  int rc = ensure_jc(g);
+  if (rc == PIC_OK) rc = launch_correct_j1(g->prec, g->mesh, g->J[0], g->Jc, g->corr_taps, g->corr_kw, g->stream);
+  if (rc == PIC_OK) Ja[0] = g->Jc;
+  return rc;
+}
 
 static int check_particles(const pic_grid* g, const pic_particles* p) {
   if (!p) return set_error(PIC_EINVAL, "particles is NULL");
@@ -237,6 +338,14 @@ int pic_init_grid(const pic_grid_desc* d, pic_grid** out) {
     pic_destroy(g);
     return set_error(PIC_ENOMEM, "cannot allocate the flag word");
   }
+  if (!ampere_is_yee(g)) {
+    g->corr_status = build_correction(g);
+    int rc = g->corr_status == PIC_ENOMEM || g->corr_status == PIC_EHIP ? correction_error(g) : ensure_jc(g);
+    if (rc) {
+      pic_destroy(g);
+      return rc;
+    }
+  }
   *out = g;
   return PIC_OK;
 }
@@ -252,7 +361,7 @@ int pic_set_fields(pic_grid* g, void* const E[3], void* const B[3], void* const 
     g->B[c] = B[c];
     g->J[c] = J ? J[c] : nullptr;
   }
-  return PIC_OK;
+  return ensure_jc(g);
 }
 
 int pic_grid_widths(const pic_grid* g, int* ME, int* MB) {
@@ -270,15 +379,38 @@ int pic_advance_B_half(pic_grid* g) {
 int pic_advance_E(pic_grid* g, int use_J) {
   if (!g) return set_error(PIC_EINVAL, "grid is NULL");
   if (use_J && !(g->J[0] && g->J[1] && g->J[2])) return set_error(PIC_EINVAL, "use_J set but J is not");
-  void* none[3] = {nullptr, nullptr, nullptr};
-  return launch_advance_e(g->prec, g->mesh, g->E, g->B, use_J ? g->J : none, g->CB, g->MB, g->dt, g->stream);
+  void* Ja[3] = {nullptr, nullptr, nullptr};
+  if (use_J) {
+    const int rc = ampere_current(g, Ja);
+    if (rc) return rc;
+  }
+  return launch_advance_e(g->prec, g->mesh, g->E, g->B, Ja, g->CB, g->MB, g->dt, g->stream);
 }
 
 static int sweep_once(pic_grid* g, void* const inE[3], void* const inB[3], void* const outE[3],
                       void* const outB[3], int use_J, void* const half[3] = nullptr) {
-  void* none[3] = {nullptr, nullptr, nullptr};
-  return launch_sweep(g->prec, g->mesh, inE, inB, use_J ? g->J : none, outE, outB, half, g->CE, g->ME, g->CB,
-                      g->MB, g->dt, g->stream);
+  void* Ja[3] = {nullptr, nullptr, nullptr};
+  if (use_J) {
+    const int rc = ampere_current(g, Ja);
+    if (rc) return rc;
+  }
+  return launch_sweep(g->prec, g->mesh, inE, inB, Ja, outE, outB, half, g->CE, g->ME, g->CB, g->MB, g->dt,
+                      g->stream);
+}
+
+int pic_current_correction(pic_grid* g, void* J1_out) {
+  if (!g || !J1_out) return set_error(PIC_EINVAL, "pic_current_correction: NULL argument");
+  if (!g->J[0]) return set_error(PIC_EINVAL, "grid has no current arrays");
+  if ((uintptr_t)J1_out & 15) return set_error(PIC_ESHAPE, "J1_out must be 16-byte aligned");
+  const size_t bytes = (size_t)g->n[0] * g->n[1] * g->n[2] * g->elem;
+  const uintptr_t a = (uintptr_t)J1_out, b = (uintptr_t)g->J[0];
+  if (a < b + bytes && b < a + bytes) return set_error(PIC_EINVAL, "J1_out overlaps J[0]");
+  if (ampere_is_yee(g))
+    return hipMemcpyAsync(J1_out, g->J[0], bytes, hipMemcpyDeviceToDevice, g->stream) == hipSuccess
+               ? PIC_OK
+               : set_error(PIC_EHIP, "current copy");
+  if (g->corr_status) return correction_error(g);
+  return launch_correct_j1(g->prec, g->mesh, g->J[0], J1_out, g->corr_taps, g->corr_kw, g->stream);
 }
 
 int pic_field_sweep(pic_grid* g, int use_J) {
@@ -308,8 +440,6 @@ int pic_deposit_J(pic_grid* g, const pic_particles* p, double* const x_old[3], i
   if (!x_old) return set_error(PIC_EINVAL, "x_old is NULL");
   for (int d = 0; d < g->ndim; ++d)
     if (!x_old[d]) return set_error(PIC_EINVAL, "x_old[%d] is NULL", d);
-  if (!ampere_is_yee(g))
-    return set_error(PIC_EUNSUPPORTED, "deposit needs the Yee Ampere stencil (x1 current correction not built)");
   if (zero_first) {
     const size_t bytes = (size_t)g->n[0] * g->n[1] * g->n[2] * g->elem;
     for (int c = 0; c < 3; ++c) {
@@ -331,8 +461,7 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
   }
   if (deposit) {
     if (!(g->J[0] && g->J[1] && g->J[2])) return set_error(PIC_EINVAL, "deposit requested without J");
-    if (!ampere_is_yee(g))
-      return set_error(PIC_EUNSUPPORTED, "deposit needs the Yee Ampere stencil (x1 current correction not built)");
+    if (!ampere_is_yee(g) && g->corr_status) return correction_error(g);
   }
   // scratch for x^n of the largest species (kept across calls)
   int64_t npmax = 0;
@@ -633,6 +762,8 @@ void pic_destroy(pic_grid* g) {
   for (SortState& st : g->vsort_b) free_sort(st);
   if (g->d_flag) (void)hipFree(g->d_flag);
   if (g->partial) (void)hipFree(g->partial);
+  if (g->corr_taps) (void)hipFree(g->corr_taps);
+  if (g->Jc) (void)hipFree(g->Jc);
   delete g;
 }
 

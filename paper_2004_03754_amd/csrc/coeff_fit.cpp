@@ -59,6 +59,9 @@ q128 target_value(int kind, q128 kappa, q128 r) {
   switch (kind) {
     case PIC_TARGET_E: return tanq(kPi * kappa * r) / (kPi * r);
     case PIC_TARGET_B: return sinq(2 * kPi * kappa * r) / (2 * kPi * r);
+    // Yee t-stagger (Sec. 4): Eq. (new_op) with the Yee symbol in place of [k]_{1,t}
+    case PIC_TARGET_YEET_E: return sinq(kPi * kappa) / (kPi * cosq(kPi * kappa * r));
+    case PIC_TARGET_YEET_B: return sinq(kPi * kappa) * cosq(kPi * kappa * r) / kPi;
     default: return sinq(kPi * kappa * r) / (kPi * r);
   }
 }
@@ -113,7 +116,7 @@ extern "C" int pic_design_coeffs(int M, double r_d, int target, int p, int n, do
   if (!(r_d > 0 && r_d < 1)) return set_error(PIC_EINVAL, "pic_design_coeffs: r = dt/dx1 must be in (0, 1)");
   if (n < 1 || !(wk1_d > 0) || !(width_factor_d > 0))
     return set_error(PIC_EINVAL, "pic_design_coeffs: bad weight parameters");
-  if (target < PIC_TARGET_E || target > PIC_TARGET_XU)
+  if (target < PIC_TARGET_E || target > PIC_TARGET_YEET_B)
     return set_error(PIC_EINVAL, "pic_design_coeffs: bad target");
 
   const int nc = p / 2;             // constraint rows

@@ -1059,6 +1059,82 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
   }
 }
 
+// ---------------------------------------------------------------------------
+// x1 current correction (Sec. 3.3, Eq. correction): the Ampere-law x1 current
+// is the deposited one times [k]_Yee/[k]_B1 per x1 mode, applied here as the
+// periodic convolution out_i = sum_{|m| <= KW} h_|m| J1_{i-m} along each x1
+// row (the host computes the taps from that ratio).  A wave owns 512
+// consecutive outputs of one row, 8 per lane.  The row window
+// [s0 - KW, s0 + 512 + KW) is staged in LDS with one pad word after every 8
+// values, so that lanes 8 values apart read different banks; the taps are
+// uniform (scalar) loads.  Accumulation in FP64 for either precision.
+// ---------------------------------------------------------------------------
+template <typename T, int KW>
+__global__ __launch_bounds__(256) void correct_j1_kernel(const T* __restrict__ J1, T* __restrict__ out,
+                                                         const double* __restrict__ h, int n1, int64_t units,
+                                                         int nseg) {
+  constexpr int SEG = 512, RWc = 8, WIN = SEG + 2 * KW, WINP = WIN + WIN / 8 + 1;
+  __shared__ double win[4][WINP];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t unit = (int64_t)blockIdx.x * 4 + wave;
+  const bool live = unit < units;
+  const int64_t row = live ? unit / nseg : 0;
+  const int s0 = live ? (int)(unit - row * nseg) * SEG : 0;
+  const T* src = J1 + row * (int64_t)n1;
+  double* w = win[wave];
+  for (int t = lane; t < WIN; t += 64) {
+    int i = (s0 - KW + t) % n1;
+    if (i < 0) i += n1;
+    w[t + (t >> 3)] = live ? (double)src[i] : 0.0;
+  }
+  __syncthreads();  // the only barrier: every thread reaches it
+  if (!live) return;
+  // output s0 + 8 lane + u takes the window value at index 8 lane + t with tap
+  // m = u + KW - t (its source lies m cells to the left)
+  const double* wl = w + 9 * lane;
+  double acc[RWc] = {};
+#pragma unroll
+  for (int t = 0; t < RWc + 2 * KW; ++t) {
+    const double v = wl[t + (t >> 3)];
+#pragma unroll
+    for (int u = 0; u < RWc; ++u) {
+      constexpr int lo = -KW;
+      const int mm = u + KW - t;
+      if (mm >= lo && mm <= KW) acc[u] += h[mm < 0 ? -mm : mm] * v;
+    }
+  }
+  T* dst = out + row * (int64_t)n1;
+#pragma unroll
+  for (int u = 0; u < RWc; ++u) {
+    const int i = s0 + RWc * lane + u;
+    if (i < n1) dst[i] = (T)acc[u];
+  }
+}
+
+template <typename T, int KW>
+int run_correct_j1(const Mesh& m, const void* J1, void* out, const double* taps, hipStream_t s) {
+  const int nseg = (m.n1 + 511) / 512;
+  const int64_t units = (int64_t)m.n2 * m.n3 * nseg;
+  const int64_t blocks = (units + 3) / 4;
+  if (blocks > 0x7fffffff) return set_error(PIC_ESHAPE, "current correction: too many rows");
+  hipLaunchKernelGGL((correct_j1_kernel<T, KW>), dim3((unsigned)blocks), dim3(256), 0, s, (const T*)J1, (T*)out,
+                     taps, m.n1, units, nseg);
+  return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "current correction launch failed");
+}
+
+template <typename T>
+int dispatch_correct_j1(const Mesh& m, const void* J1, void* out, const double* taps, int kw, hipStream_t s) {
+  switch (kw) {
+    case 8: return run_correct_j1<T, 8>(m, J1, out, taps, s);
+    case 16: return run_correct_j1<T, 16>(m, J1, out, taps, s);
+    case 32: return run_correct_j1<T, 32>(m, J1, out, taps, s);
+    case 40: return run_correct_j1<T, 40>(m, J1, out, taps, s);
+    case 48: return run_correct_j1<T, 48>(m, J1, out, taps, s);
+    case 64: return run_correct_j1<T, 64>(m, J1, out, taps, s);
+    default: return set_error(PIC_EINVAL, "current correction: tap width %d", kw);
+  }
+}
+
 // compute units of the current device (queried once per device)
 int device_cus() {
   static int cached[64] = {};
@@ -1201,6 +1277,13 @@ int launch_sweep(int prec, const Mesh& m, void* const Ein[3], void* const Bin[3]
   if (prec == PIC_FP64)
     return dispatch_sweep<double, 64, 4, 512>(m, Ein, Bin, J, Eout, Bout, Bh, CE, ME, CB, MB, dt, s);
   return dispatch_sweep<float, 128, 8, 512>(m, Ein, Bin, J, Eout, Bout, Bh, CE, ME, CB, MB, dt, s);
+}
+
+int launch_correct_j1(int prec, const Mesh& m, const void* J1, void* out, const double* taps, int kw,
+                      void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  return prec == PIC_FP64 ? dispatch_correct_j1<double>(m, J1, out, taps, kw, s)
+                          : dispatch_correct_j1<float>(m, J1, out, taps, kw, s);
 }
 
 int launch_advance_e(int prec, const Mesh& m, void* const E[3], void* const B[3], void* const J[3],

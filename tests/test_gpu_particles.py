@@ -141,16 +141,30 @@ def test_deposit(ndim, prec, coeffs16):
     grid.close()
 
 
-def test_deposit_rejects_wide_ampere(coeffs16):
-    """The x1 current correction is the identity only for the Yee Ampere
-    stencil; other C^B are refused instead of breaking Gauss's law."""
+def test_deposit_with_wide_ampere_keeps_the_deposited_current(coeffs16):
+    """With a non-Yee C^B, pic_deposit_J still writes the deposited
+    (charge-conserving) current; the x1 correction of Sec. 3.3 is applied
+    where Ampere's law reads J.  A C^B whose correction kernel is wider than
+    64 cells is refused there (PIC_EUNSUPPORTED), not in the deposit."""
     CE, CB = coeffs16
     n = (128, 4, 4)
+    L = _box(n)
+    x0, u = _particles(n, 500, seed=3, u_scale=0.1)
+    x1, _ = wl.small_moves(x0, DX, L, seed=4)
     zeros = [np.zeros((n[2], n[1], n[0])) for _ in range(3)]
-    grid = b.Grid([dev(z) for z in zeros], [dev(z) for z in zeros], DX, wl.DT, CE, CB + np.r_[0, 0.01, np.zeros(14)],
-                  J=[dev(z) for z in zeros])
-    x0, u = _particles(n, 10, seed=3, u_scale=0.1)
-    with pytest.raises(b.YeePICError) as e:
-        grid.deposit_J(b.Particles(dev(x0), dev(u)), dev(x0))
-    assert e.value.code == -6
-    grid.close()
+    noise = np.random.default_rng(7).standard_normal(15)
+    ref = pt.deposit(x0, x1, -1.0, 0.37, DX, wl.DT, (n[2], n[1], n[0]), 3, u=u)
+    for CBw, supported in ((CB + np.r_[0, 0.01, np.zeros(14)], True), (CB + np.r_[0, 0.01 * noise], False)):
+        Jd = [dev(z) for z in zeros]
+        grid = b.Grid([dev(z) for z in zeros], [dev(z) for z in zeros], DX, wl.DT, CE, CBw, J=Jd)
+        grid.deposit_J(b.Particles(dev(x1), dev(u), q=-1.0, m=1.0, w=0.37), dev(x0), zero_first=True)
+        grid.sync()
+        assert_fields_close(Jd, ref, 1e-12, "deposit J, wide Ampere stencil")
+        if supported:
+            grid.advance_E(use_J=True)
+            grid.sync()
+        else:
+            with pytest.raises(b.YeePICError) as e:
+                grid.advance_E(use_J=True)
+            assert e.value.code == -6
+        grid.close()

@@ -27,7 +27,8 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("M,r,target", [(16, 0.5, "E"), (16, 0.5, "B"), (8, 0.5, "E"), (8, 0.25, "E"),
-                                        (8, 0.25, "B"), (4, 0.3, "xu")])
+                                        (8, 0.25, "B"), (4, 0.3, "xu"), (8, 0.25, "yeet_E"),
+                                        (8, 0.25, "yeet_B")])
 def test_design_coeffs_matches_oracle_fit(M, r, target):
     """App. B: the library's binary128 null-space QR fit agrees with the
     oracle's 60-digit KKT solve (both approximate the same integrals)."""
