@@ -177,10 +177,14 @@ def run_plane_wave(torch, b, wl, CE, CB, steps):
     return out
 
 
-def run_plasma(torch, b, wl, CE, CB, steps):
+def run_plasma(torch, b, wl, CE, CB, steps, dt=None):
     """Plasma workload: 512 x 256 x 256 cells, electrons at n = 0.01 n_c with
     8 per cell (268,435,456), u_th = 0.01, Gaussian laser a0 = 10, w0 = 4
-    lambda0; Boris pusher, Esirkepov deposit; FP32 fields, FP64 particles."""
+    lambda0; Boris pusher, Esirkepov deposit; FP32 fields, FP64 particles.
+    ``dt`` defaults to dx1/2; at dt = dx1/4 the proposed solver's Ampere
+    stencil is wide, so each step also runs the x1 current correction, which
+    is then timed alone as well."""
+    dt = wl.DT if dt is None else dt
     dx = (wl.DX1, wl.DX2, wl.DX3)
     n = (512, 256, 256)
     L0 = wl.LAMBDA0
@@ -189,7 +193,7 @@ def run_plasma(torch, b, wl, CE, CB, steps):
     J = [torch.zeros_like(E[0]) for _ in range(3)]
     xd, ud = _device_plasma(n, dx, 2, 0.01, 3, torch)
     npart = xd.shape[1]
-    grid = b.Grid(E, B, dx, wl.DT, CE, CB, J=J, prec="fp32")
+    grid = b.Grid(E, B, dx, dt, CE, CB, J=J, prec="fp32")
     p = b.Particles(xd, ud, q=-1.0, m=1.0, w=0.01 / 8)
     grid.step_n([p], 2, pusher="boris", deposit=True)
     torch.cuda.synchronize()
@@ -214,10 +218,34 @@ def run_plasma(torch, b, wl, CE, CB, steps):
     out = {"ms_per_step": ms, "particles": npart, "particle_pushes_per_s": npart / (ms * 1e-3),
            "cell_updates_per_s": n[0] * n[1] * n[2] / (ms * 1e-3),
            "gather_push_ms": q0.elapsed_time(q1), "deposit_ms": d0.elapsed_time(d1)}
+    if abs(dt - wl.DT) > 1e-15:
+        jc = torch.empty_like(J[0])
+        grid.current_correction(jc)
+        c0, c1 = _events(torch)
+        c0.record()
+        for _ in range(10):
+            grid.current_correction(jc)
+        c1.record()
+        torch.cuda.synchronize()
+        cms = c0.elapsed_time(c1) / 10
+        cells = n[0] * n[1] * n[2]
+        out["dt_over_dx1"] = dt / dx[0]
+        out["current_correction_ms"] = cms
+        out["current_correction_GBps"] = 8 * cells / (cms * 1e-3) / 1e9  # FP32: read J1 + write 4 B/cell
+        del jc
     grid.close()
     del E, B, J, xd, ud, xo, grid, p
     torch.cuda.empty_cache()
     return out
+
+
+def run_plasma_quarter(torch, b, wl, steps):
+    """The plasma workload at dt = dx1/4 (the ratio of the paper's Sec. 4.1
+    runs) with the proposed solver's coefficients for that ratio: a 16-wide
+    Ampere stencil, the general fused sweep and the x1 current correction."""
+    CE = b.design_coeffs(16, 0.25, "E")
+    CB = b.design_coeffs(16, 0.25, "B")
+    return run_plasma(torch, b, wl, CE, CB, steps, dt=wl.DX1 / 4)
 
 
 def run_adjoint(torch, b, wl, CE, CB, steps, K=64):
@@ -355,6 +383,8 @@ def main():
                     help="steps of the differentiated 2D batch run (checkpoint every 64)")
     ap.add_argument("--adjoint-only", action="store_true", help="run only the adjoint workload")
     ap.add_argument("--plasma-only", action="store_true", help="run only the plasma workload")
+    ap.add_argument("--plasma-quarter-only", action="store_true",
+                    help="run only the plasma workload at dt = dx1/4 (wide Ampere stencil, current correction)")
     ap.add_argument("--plasma-steps", type=int, default=10, help="timed steps of the plasma workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
@@ -384,6 +414,9 @@ def main():
         return
     if args.plasma_only:
         print(json.dumps({"plasma_512x256x256": run_plasma(torch, b, wl, CE, CB, steps=args.plasma_steps)}))
+        return
+    if args.plasma_quarter_only:
+        print(json.dumps({"plasma_512x256x256_dt_quarter": run_plasma_quarter(torch, b, wl, args.plasma_steps)}))
         return
     L = wl.LAMBDA0
     n = (1024, 256, 256)
@@ -435,6 +468,7 @@ def main():
             "speedup_vs_fp64_sweep": main_run["ms_sweep"] / fp32["ms_sweep"]}
         res["plane_wave_2048x512x512"] = run_plane_wave(torch, b, wl, CE, CB, steps=20)
         res["plasma_512x256x256"] = run_plasma(torch, b, wl, CE, CB, steps=args.plasma_steps)
+        res["plasma_512x256x256_dt_quarter"] = run_plasma_quarter(torch, b, wl, args.plasma_steps)
         res["adjoint_2d_2048x256_x16"] = run_adjoint(torch, b, wl, CE, CB, steps=args.adjoint_steps)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline()

@@ -167,7 +167,8 @@ int pic_field_sweep(pic_grid *g, int use_J);
  * order constraint makes the ratio 1 there).  The multiplier is applied as a
  * periodic x1 convolution whose taps the library computes at pic_init_grid
  * from the ratio on the n1 discrete modes, truncated where they fall below
- * 2^-56 of their sum (at most 64 cells each side).  With the Yee stencil it
+ * 2^-56 of their sum for FP64 fields, 2^-32 for FP32 fields (at most 64
+ * cells each side).  With the Yee stencil it
  * is a copy.  J1_out: device, caller-owned, one array in the field layout and
  * precision, 16-byte aligned, not overlapping J[0].  Returns PIC_EINVAL
  * without J, PIC_EUNSUPPORTED if [k]_B1 vanishes at a nonzero mode or the

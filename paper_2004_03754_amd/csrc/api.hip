@@ -119,8 +119,9 @@ static bool ampere_is_yee(const pic_grid* g) { return g->MB == 1 && g->CB[0] == 
 // N = n1 (exactly the mesh's periodic kernel) up to 16384; for longer rows
 // N = 16384, whose aliases lie 16384 cells away (negligible for any kernel
 // that passes the decay test).  The taps are cut after the last one above
-// 2^-56 of their absolute sum, looking 128 cells out; the cut must fall within
-// 64 cells and below n1/2.
+// 2^-56 (FP64 fields) or 2^-32 (FP32 fields, well below the output's rounding)
+// of their absolute sum, looking 128 cells out; the cut must fall within 64
+// cells and below n1/2.
 static int build_correction(pic_grid* g) {
   const int MB = g->MB;
   const int n1 = (int)g->n[0];
@@ -159,10 +160,11 @@ static int build_correction(pic_grid* g) {
     asum += (mm ? 2 : 1) * fabsl(h[mm]);
   }
   int W = 0;
+  const int cut = g->prec == PIC_FP64 ? -56 : -32;
   for (int mm = 1; mm <= mmax; ++mm)
-    if (fabsl(h[mm]) > ldexpl(asum, -56)) W = mm;
+    if (fabsl(h[mm]) > ldexpl(asum, cut)) W = mm;
   if (W > 64 || 2 * W >= n1) return PIC_EUNSUPPORTED;
-  const int kw = W <= 8 ? 8 : W <= 16 ? 16 : W <= 32 ? 32 : W <= 40 ? 40 : W <= 48 ? 48 : 64;
+  const int kw = W <= 8 ? 8 : W <= 16 ? 16 : W <= 24 ? 24 : W <= 32 ? 32 : W <= 40 ? 40 : W <= 48 ? 48 : 64;
   std::vector<double> taps(kw + 1, 0.0);
   for (int mm = 0; mm <= W; ++mm) taps[mm] = (double)h[mm];
   if (hipMalloc((void**)&g->corr_taps, taps.size() * sizeof(double)) != hipSuccess) return PIC_ENOMEM;

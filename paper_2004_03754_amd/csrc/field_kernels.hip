@@ -1082,10 +1082,18 @@ __global__ __launch_bounds__(256) void correct_j1_kernel(const T* __restrict__ J
   const int s0 = live ? (int)(unit - row * nseg) * SEG : 0;
   const T* src = J1 + row * (int64_t)n1;
   double* w = win[wave];
-  for (int t = lane; t < WIN; t += 64) {
-    int i = (s0 - KW + t) % n1;
-    if (i < 0) i += n1;
-    w[t + (t >> 3)] = live ? (double)src[i] : 0.0;
+  if (n1 >= WIN) {  // the window wraps at most once
+    for (int t = lane; t < WIN; t += 64) {
+      int i = s0 - KW + t;
+      i += i < 0 ? n1 : (i >= n1 ? -n1 : 0);
+      w[t + (t >> 3)] = live ? (double)src[i] : 0.0;
+    }
+  } else {
+    for (int t = lane; t < WIN; t += 64) {
+      int i = (s0 - KW + t) % n1;
+      if (i < 0) i += n1;
+      w[t + (t >> 3)] = live ? (double)src[i] : 0.0;
+    }
   }
   __syncthreads();  // the only barrier: every thread reaches it
   if (!live) return;
@@ -1127,6 +1135,7 @@ int dispatch_correct_j1(const Mesh& m, const void* J1, void* out, const double* 
   switch (kw) {
     case 8: return run_correct_j1<T, 8>(m, J1, out, taps, s);
     case 16: return run_correct_j1<T, 16>(m, J1, out, taps, s);
+    case 24: return run_correct_j1<T, 24>(m, J1, out, taps, s);
     case 32: return run_correct_j1<T, 32>(m, J1, out, taps, s);
     case 40: return run_correct_j1<T, 40>(m, J1, out, taps, s);
     case 48: return run_correct_j1<T, 48>(m, J1, out, taps, s);

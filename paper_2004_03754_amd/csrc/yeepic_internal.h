@@ -41,7 +41,7 @@ int launch_advance_e(int prec, const Mesh& m, void* const E[3], void* const B[3]
 // all-null; Bh, if not NULL, also receives B^{n+1/2}.  In and out must not
 // alias.
 // x1 current correction (Sec. 3.3): out = periodic convolution along x1 of
-// J1 with the symmetric taps h[0..kw] (h[-m] = h[m]); kw is 8, 16, 32, 40, 48 or 64
+// J1 with the symmetric taps h[0..kw] (h[-m] = h[m]); kw is 8, 16, 24, 32, 40, 48 or 64
 int launch_correct_j1(int prec, const Mesh& m, const void* J1, void* out, const double* taps, int kw,
                       void* stream);
 int launch_sweep(int prec, const Mesh& m, void* const Ein[3], void* const Bin[3],
