@@ -390,7 +390,7 @@ __global__ __launch_bounds__(NT) void sweep_kernel(const T* __restrict__ iE1, co
     const size_t voff = poff(k) / R; /* plane offsets are multiples of R */     \
     _Pragma("unroll") for (int s = 0; s < NLE; ++s) {                           \
       const V* src = le_c[s] == 0 ? vE1 : (le_c[s] == 1 ? vE2 : vE3);           \
-      if (le_c[s] >= 0) pfE[s] = src[voff + le_g[s]];                           \
+      pfE[s] = src[voff + le_g[s]]; /* idle slots read offset 0 */            \
     }                                                                           \
   }
 #define YP_STORE_PLANE(k)                                                       \
@@ -407,28 +407,30 @@ __global__ __launch_bounds__(NT) void sweep_kernel(const T* __restrict__ iE1, co
   T curB[NS1][R][3], nxtB[NS1][R][3];
   constexpr int NJ = HAS_J ? NS2 : 1;  // current prefetch only when there is a current
   T curJ[NJ][3], nxtJ[NJ][3];
+  // Every thread issues every global load of the march (idle slots read the
+  // plane's first cells, planes past the march wrap): with no load under a
+  // branch, the compiler's wait counts stay exact (see sweep_yee_kernel).
   auto load_B = [&](int k, T (&dst)[NS1][R][3]) {
     const size_t off = poff(k);
 #pragma unroll
-    for (int s = 0; s < NS1; ++s)
-      if (tid + s * NT < NG1) {
+    for (int s = 0; s < NS1; ++s) {
 #pragma unroll
-        for (int u = 0; u < R; ++u) {
-          int col = s1_col[s] + u;
-          col -= col >= m.n1 ? m.n1 : 0;
-          const size_t g = off + s1_row[s] + col;
-          dst[s][u][0] = iB1[g];
-          dst[s][u][1] = iB2[g];
-          dst[s][u][2] = iB3[g];
-        }
+      for (int u = 0; u < R; ++u) {
+        int col = s1_col[s] + u;
+        col -= col >= m.n1 ? m.n1 : 0;
+        const size_t g = off + s1_row[s] + col;
+        dst[s][u][0] = iB1[g];
+        dst[s][u][1] = iB2[g];
+        dst[s][u][2] = iB3[g];
       }
+    }
   };
   auto load_J = [&](int k, T (&dst)[NJ][3]) {
     const size_t off = poff(k);
 #pragma unroll
     for (int s = 0; s < NJ; ++s) {
       dst[s][0] = dst[s][1] = dst[s][2] = 0;
-      if (HAS_J && tid + s * NT < G::SF) {
+      if (HAS_J) {
         dst[s][0] = J1[off + s2_g[s]];
         dst[s][1] = J2[off + s2_g[s]];
         dst[s][2] = J3[off + s2_g[s]];
@@ -444,11 +446,9 @@ __global__ __launch_bounds__(NT) void sweep_kernel(const T* __restrict__ iE1, co
     const bool more = kk + 1 < kend;
     // prefetch for the next plane: E^n(kk+3) -> LDS at the end of this
     // iteration; B^n, J of plane ka+1 for the next stages 1 and 2
-    if (more) {
-      YP_LOAD_PLANE(kk + 3);
-      load_B(ka + 1, nxtB);
-      load_J(ka + 1, nxtJ);
-    }
+    YP_LOAD_PLANE(kk + 3);
+    load_B(ka + 1, nxtB);
+    load_J(ka + 1, nxtJ);
     // ---- stage 1: B^{n+1/2}(ka) ----
     {
       const T* e1 = sE + (ka & 1) * 3 * G::SE;
