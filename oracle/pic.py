@@ -39,6 +39,8 @@ def step(E, B, species, CE, CB, dx, dt, *, pusher="boris", deposit=False, ndim=3
             u = particles.boris(sp["u"], Ep, Bp, qm, dt)
         elif pusher == "analytic":
             u = particles.analytic(sp["u"], Ep, Bp, qm, dt)
+        elif pusher == "hc":
+            u = particles.higuera_cary(sp["u"], Ep, Bp, qm, dt)
         else:
             raise ValueError(pusher)
         x_old = sp["x"]

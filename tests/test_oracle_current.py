@@ -45,7 +45,7 @@ def _plasma(n, seed, npart):
     return E, B, {"x": x, "u": u, "q": -1.0, "m": 1.0, "w": 0.01}
 
 
-@pytest.mark.parametrize("pusher", ["boris", "analytic"])
+@pytest.mark.parametrize("pusher", ["boris", "analytic", "hc"])
 def test_gauss_law_preserved_with_wide_ampere_stencil(pusher, coeffs16_quarter):
     """Sec. 3.3: with the corrected current, div_B E - rho stays at its
     initial value to roundoff for the wide C^B of dt = dx1/4."""

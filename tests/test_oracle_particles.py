@@ -70,9 +70,9 @@ def _rand_fields(np_, seed, scale=1.0):
     return scale * g.standard_normal((3, np_)), scale * g.standard_normal((3, np_))
 
 
-@pytest.mark.parametrize("push", [pt.boris, pt.analytic])
+@pytest.mark.parametrize("push", [pt.boris, pt.analytic, pt.higuera_cary])
 def test_pure_electric_field(push):
-    """Both pushers: with B = 0 the lab-time momentum change is q E dt."""
+    """Every pusher: with B = 0 the lab-time momentum change is q E dt."""
     g = np.random.default_rng(1)
     u = g.standard_normal((3, 20)) * 3
     E = g.standard_normal((3, 20)) * 5
@@ -127,6 +127,40 @@ def test_pure_magnetic_field_rotation():
         got = np.arctan2(un[1], un[0])
         # u x B with B along z rotates u clockwise for positive qm B
         assert np.allclose(got, -angle, rtol=1e-11, atol=1e-13)
+
+
+def test_higuera_cary_magnetic_rotation_keeps_speed():
+    """Higuera-Cary in a pure B field (any orientation of u and B): a
+    rotation, so |u| is kept to roundoff."""
+    g = np.random.default_rng(3)
+    u = g.standard_normal((3, 32)) * g.uniform(0.1, 30, 32)
+    B = g.standard_normal((3, 32)) * g.uniform(1, 50, 32)
+    un = pt.higuera_cary(u, np.zeros_like(B), B, -1.0, 0.1)
+    assert np.allclose(np.linalg.norm(un, axis=0), np.linalg.norm(u, axis=0), rtol=1e-13)
+
+
+@pytest.mark.parametrize("vd", [0.5, 0.9, 0.99])
+def test_higuera_cary_keeps_relativistic_exb_drift(vd):
+    """The property the paper cites the Higuera-Cary pusher for (Sec. 4.1:
+    right for relativistically drifting particles): in crossed fields with
+    |E| < |B| a particle moving at the E x B drift v_d = E x B / B^2 has
+    constant u = gamma_d v_d, and the push keeps it over 50 steps to
+    roundoff for any orientation; Boris does not."""
+    g = np.random.default_rng(4)
+    Bv = g.standard_normal(3)
+    Bv *= 3.0 / np.linalg.norm(Bv)
+    e = np.cross(Bv, g.standard_normal(3))
+    Ev = e / np.linalg.norm(e) * vd * 3.0  # E perpendicular to B, |E| = v_d |B|
+    v = np.cross(Ev, Bv) / (Bv @ Bv)
+    u0 = (v / np.sqrt(1 - v @ v))[:, None]
+    E, B = Ev[:, None], Bv[:, None]
+    u = u0.copy()
+    ub = u0.copy()
+    for _ in range(50):
+        u = pt.higuera_cary(u, E, B, -1.0, 0.2)
+        ub = pt.boris(ub, E, B, -1.0, 0.2)
+    assert np.max(np.abs(u - u0)) <= 1e-12 * np.max(np.abs(u0))
+    assert np.max(np.abs(ub - u0)) > 1e-5 * np.max(np.abs(u0))
 
 
 def test_null_field_from_rest():
