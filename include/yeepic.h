@@ -55,7 +55,11 @@ typedef enum {
 } pic_status;
 
 typedef enum { PIC_FP64 = 0, PIC_FP32_FIELDS = 1 } pic_precision;
-typedef enum { PIC_PUSH_BORIS = 0, PIC_PUSH_ANALYTIC = 1 } pic_pusher;
+/* Pushers (Sec. 1, Sec. 4.1): Boris; the exact constant-field (analytic)
+ * pusher; Higuera-Cary (the published method the paper cites and uses in its
+ * single-particle runs: the Boris splitting with the rotation at the Lorentz
+ * factor that keeps relativistic E x B drift exact). */
+typedef enum { PIC_PUSH_BORIS = 0, PIC_PUSH_ANALYTIC = 1, PIC_PUSH_HC = 2 } pic_pusher;
 /* Coefficient targets (k-space operators divided by k_g1 = 2 pi/dx1, at
  * kappa = k1/k_g1, r = dt/dx1): Eq. (new_op) E and B; the Xu solver's
  * [k]_{1,t} (Sec. 4); the Yee t-stagger pair of Sec. 4, read as Eq. (new_op)
@@ -177,8 +181,8 @@ int pic_current_correction(pic_grid *g, void *J1_out);
 
 /* ---- particles (App. A gather, Sec. 1 / 4.1 pushers) ---------------------
  * Gathers E^n and B^n at x^n with the linear shape, each component from its
- * own staggered points; pushes u^{n-1/2} -> u^{n+1/2} with the Boris
- * pusher or the exact constant-field (analytic) pusher; advances
+ * own staggered points; pushes u^{n-1/2} -> u^{n+1/2} with the Boris, the
+ * exact constant-field (analytic) or the Higuera-Cary pusher; advances
  * x^{n+1} = x^n + dt u/gamma and wraps it periodically.  If x_old is not
  * NULL, x^n is also written to x_old[d] (device, np doubles each; x_old[2]
  * may be NULL in 2D).  Positions outside [0, L) are clamped into the mesh
@@ -249,7 +253,8 @@ int pic_set_sort_interval(pic_grid *g, int steps);
  * derivative taken is the one of the cell the particle is in.  The exact
  * pusher's proper time tau_r solves t(tau) = dt; its derivative is taken
  * implicitly: d tau_r / d theta = -(d t / d theta at fixed tau) / gamma(tau_r).
- * PIC_EUNSUPPORTED for FP32-field grids; PIC_EINVAL for another pusher; the
+ * PIC_EUNSUPPORTED for FP32-field grids and for the Higuera-Cary pusher;
+ * PIC_EINVAL for an unknown pusher; the
  * coefficient reduction allocates a scratch of 16 doubles per 1024 cells of
  * 8 x1 rows at the first call (PIC_ENOMEM if that fails).  Scatter into lE, lB
  * uses atomics, so the field cotangents vary in the last bits between runs. */

@@ -28,13 +28,14 @@ from . import binding as b
 class RunConfig:
     """Grid and run constants: cell sizes, time step, number of dimensions
     (2D grids may stack independent planes along n3), species constants,
-    step count, checkpoint interval and pusher ("boris" or "analytic")."""
+    step count, checkpoint interval and pusher ("boris" or "analytic": the
+    pushers the hand-written adjoint covers)."""
 
     def __init__(self, dx, dt, nsteps, K=64, ndim=3, q=-1.0, m=1.0, w=1.0, pusher="boris"):
         self.dx, self.dt, self.nsteps, self.K = tuple(dx), float(dt), int(nsteps), int(K)
         self.ndim, self.q, self.m, self.w = int(ndim), float(q), float(m), float(w)
         self.pusher = str(pusher)
-        assert self.nsteps >= 0 and self.K >= 1 and self.pusher in b.PUSHERS
+        assert self.nsteps >= 0 and self.K >= 1 and self.pusher in ("boris", "analytic")
 
 
 def _clone_state(E, B, x, u):

@@ -17,11 +17,11 @@ _lib = None
 
 PIC_FP64, PIC_FP32_FIELDS = 0, 1
 PIC_MAX_M = 16
-PIC_PUSH_BORIS, PIC_PUSH_ANALYTIC = 0, 1
+PIC_PUSH_BORIS, PIC_PUSH_ANALYTIC, PIC_PUSH_HC = 0, 1, 2
 PIC_TARGET_E, PIC_TARGET_B, PIC_TARGET_XU, PIC_TARGET_YEET_E, PIC_TARGET_YEET_B = 0, 1, 2, 3, 4
 STATUS = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ECFL", -3: "PIC_EHIP", -4: "PIC_ESHAPE",
           -5: "PIC_ENOMEM", -6: "PIC_EUNSUPPORTED", -7: "PIC_ENONFINITE"}
-PUSHERS = {"boris": PIC_PUSH_BORIS, "analytic": PIC_PUSH_ANALYTIC}
+PUSHERS = {"boris": PIC_PUSH_BORIS, "analytic": PIC_PUSH_ANALYTIC, "hc": PIC_PUSH_HC}
 
 
 class YeePICError(RuntimeError):

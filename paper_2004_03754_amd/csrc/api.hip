@@ -427,7 +427,8 @@ int pic_gather_push(pic_grid* g, pic_particles* p, int pusher, double* const x_o
   if (!g) return set_error(PIC_EINVAL, "grid is NULL");
   int rc = check_particles(g, p);
   if (rc) return rc;
-  if (pusher != PIC_PUSH_BORIS && pusher != PIC_PUSH_ANALYTIC) return set_error(PIC_EINVAL, "bad pusher");
+  if (pusher != PIC_PUSH_BORIS && pusher != PIC_PUSH_ANALYTIC && pusher != PIC_PUSH_HC)
+    return set_error(PIC_EINVAL, "bad pusher");
   if (x_old)
     for (int d = 0; d < g->ndim; ++d)
       if (!x_old[d]) return set_error(PIC_EINVAL, "x_old[%d] is NULL", d);
@@ -456,7 +457,8 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
   if (!g) return set_error(PIC_EINVAL, "grid is NULL");
   if (nsteps < 0 || nspecies < 0) return set_error(PIC_EINVAL, "negative count");
   if (nspecies > 0 && !species) return set_error(PIC_EINVAL, "species is NULL");
-  if (pusher != PIC_PUSH_BORIS && pusher != PIC_PUSH_ANALYTIC) return set_error(PIC_EINVAL, "bad pusher");
+  if (pusher != PIC_PUSH_BORIS && pusher != PIC_PUSH_ANALYTIC && pusher != PIC_PUSH_HC)
+    return set_error(PIC_EINVAL, "bad pusher");
   for (int s = 0; s < nspecies; ++s) {
     int rc = check_particles(g, species[s]);
     if (rc) return rc;
@@ -603,7 +605,8 @@ int pic_step_to(pic_grid* g, pic_particles* const* species, int nspecies, int pu
   if (!g || !Eout || !Bout) return set_error(PIC_EINVAL, "pic_step_to: NULL argument");
   if (nspecies < 0) return set_error(PIC_EINVAL, "negative count");
   if (nspecies > 0 && !species) return set_error(PIC_EINVAL, "species is NULL");
-  if (pusher != PIC_PUSH_BORIS && pusher != PIC_PUSH_ANALYTIC) return set_error(PIC_EINVAL, "bad pusher");
+  if (pusher != PIC_PUSH_BORIS && pusher != PIC_PUSH_ANALYTIC && pusher != PIC_PUSH_HC)
+    return set_error(PIC_EINVAL, "bad pusher");
   for (int c = 0; c < 3; ++c) {
     if (!Eout[c] || !Bout[c]) return set_error(PIC_EINVAL, "output field pointer is NULL");
     if (((uintptr_t)Eout[c] | (uintptr_t)Bout[c]) & 15) return set_error(PIC_ESHAPE, "fields must be 16-byte aligned");
@@ -634,6 +637,7 @@ int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* c
                      pic_particles* const* lambda, int nspecies, int pusher) {
   if (!g || !adj) return set_error(PIC_EINVAL, "pic_adjoint_step: NULL argument");
   if (g->prec != PIC_FP64) return set_error(PIC_EUNSUPPORTED, "the adjoint is built for FP64 grids only");
+  if (pusher == PIC_PUSH_HC) return set_error(PIC_EUNSUPPORTED, "the adjoint covers the Boris and exact pushers");
   if (pusher != PIC_PUSH_BORIS && pusher != PIC_PUSH_ANALYTIC) return set_error(PIC_EINVAL, "bad pusher");
   if (nspecies < 0) return set_error(PIC_EINVAL, "negative count");
   if (nspecies > 0 && (!species || !lambda)) return set_error(PIC_EINVAL, "species or lambda is NULL");

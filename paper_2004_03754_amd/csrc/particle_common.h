@@ -86,6 +86,32 @@ __device__ __forceinline__ void boris(double u[3], const double E[3], const doub
   u[2] = um[2] + (up[0] * s[1] - up[1] * s[0]) + eps * E[2];
 }
 
+// Higuera-Cary push (Sec. 1, Sec. 4.1: the published method the paper cites):
+// the Boris splitting with the rotation vector t = tau/gamma_r, tau =
+// (q dt/2m) B, at the Lorentz factor
+//   gamma_r^2 = (sigma + sqrt(sigma^2 + 4 (tau^2 + (u-.tau)^2)))/2,
+//   sigma = 1 + u-^2 - tau^2,
+// then u+ = (u- + (u-.t) t + u- x t)/(1 + t^2) and u = u+ + (q dt/2m) E + u+ x t.
+__device__ __forceinline__ void higuera_cary(double u[3], const double E[3], const double B[3], double qm,
+                                             double dt) {
+  const double eps = 0.5 * qm * dt;
+  const double um[3] = {u[0] + eps * E[0], u[1] + eps * E[1], u[2] + eps * E[2]};
+  const double tau[3] = {eps * B[0], eps * B[1], eps * B[2]};
+  const double tau2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
+  const double ust = um[0] * tau[0] + um[1] * tau[1] + um[2] * tau[2];
+  const double sigma = 1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2] - tau2;
+  const double gr = sqrt(0.5 * (sigma + sqrt(sigma * sigma + 4.0 * (tau2 + ust * ust))));
+  const double t[3] = {tau[0] / gr, tau[1] / gr, tau[2] / gr};
+  const double s = 1.0 / (1.0 + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+  const double ut = um[0] * t[0] + um[1] * t[1] + um[2] * t[2];
+  const double up[3] = {s * (um[0] + ut * t[0] + (um[1] * t[2] - um[2] * t[1])),
+                        s * (um[1] + ut * t[1] + (um[2] * t[0] - um[0] * t[2])),
+                        s * (um[2] + ut * t[2] + (um[0] * t[1] - um[1] * t[0]))};
+  u[0] = up[0] + eps * E[0] + (up[1] * t[2] - up[2] * t[1]);
+  u[1] = up[1] + eps * E[1] + (up[2] * t[0] - up[0] * t[2]);
+  u[2] = up[2] + eps * E[2] + (up[0] * t[1] - up[1] * t[0]);
+}
+
 // ---------------------------------------------------------------------------
 // Exact push for fields constant over the step (Sec. 1, Sec. 4.1).
 //

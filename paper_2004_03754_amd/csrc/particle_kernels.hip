@@ -29,6 +29,8 @@ __global__ __launch_bounds__(256) void gather_push_kernel(const T* __restrict__ 
   gather6<T, NDIM>(E1, E2, E3, B1, B2, B3, m, x, E, B);
   if (PUSH == PIC_PUSH_BORIS)
     boris(u, E, B, qm, dt);
+  else if (PUSH == PIC_PUSH_HC)
+    higuera_cary(u, E, B, qm, dt);
   else
     analytic(u, E, B, qm, dt);
   const double ig = dt / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
@@ -144,9 +146,13 @@ int run_gather_push(const Mesh& m, void* const E[3], void* const B[3], const pic
                      (const T*)E[2], (const T*)B[0], (const T*)B[1], (const T*)B[2], m, p.x[0], p.x[1],       \
                      p.x[2], p.u[0], p.u[1], p.u[2], p.np, qm, dt, o1, o2, o3)
   if (m.ndim == 3) {
-    if (pusher == PIC_PUSH_BORIS) YP_GP(PIC_PUSH_BORIS, 3); else YP_GP(PIC_PUSH_ANALYTIC, 3);
+    if (pusher == PIC_PUSH_BORIS) YP_GP(PIC_PUSH_BORIS, 3);
+    else if (pusher == PIC_PUSH_HC) YP_GP(PIC_PUSH_HC, 3);
+    else YP_GP(PIC_PUSH_ANALYTIC, 3);
   } else {
-    if (pusher == PIC_PUSH_BORIS) YP_GP(PIC_PUSH_BORIS, 2); else YP_GP(PIC_PUSH_ANALYTIC, 2);
+    if (pusher == PIC_PUSH_BORIS) YP_GP(PIC_PUSH_BORIS, 2);
+    else if (pusher == PIC_PUSH_HC) YP_GP(PIC_PUSH_HC, 2);
+    else YP_GP(PIC_PUSH_ANALYTIC, 2);
   }
 #undef YP_GP
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "gather_push launch failed");

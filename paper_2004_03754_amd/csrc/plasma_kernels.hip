@@ -199,6 +199,8 @@ __global__ __launch_bounds__(256) void tile_push_kernel(
     gather6<T, 3>(E1, E2, E3, B1, B2, B3, m, x, E, B);
     if (PUSH == PIC_PUSH_BORIS)
       boris(u, E, B, qm, dt);
+    else if (PUSH == PIC_PUSH_HC)
+      higuera_cary(u, E, B, qm, dt);
     else
       analytic(u, E, B, qm, dt);
     const double ig = dt / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
@@ -263,7 +265,9 @@ int run_tile_push(const Mesh& m, const TileGeom& tg, void* const E[3], void* con
                   hipStream_t s) {
   const size_t lds = sizeof(unsigned long long) * 3 * (size_t)tg.r[0] * tg.r[1] * tg.r[2];
   if (lds > 160 * 1024) return set_error(PIC_EUNSUPPORTED, "plasma tile needs %zu bytes of LDS", lds);
-  auto k = pusher == PIC_PUSH_BORIS ? tile_push_kernel<T, PIC_PUSH_BORIS> : tile_push_kernel<T, PIC_PUSH_ANALYTIC>;
+  auto k = pusher == PIC_PUSH_BORIS ? tile_push_kernel<T, PIC_PUSH_BORIS>
+            : pusher == PIC_PUSH_HC  ? tile_push_kernel<T, PIC_PUSH_HC>
+                                     : tile_push_kernel<T, PIC_PUSH_ANALYTIC>;
   if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return set_error(PIC_EHIP, "tile push: cannot reserve %zu bytes of LDS", lds);
   const double qm = src.q / src.m, qw = src.q * src.w;
@@ -277,7 +281,9 @@ int run_tile_push(const Mesh& m, const TileGeom& tg, void* const E[3], void* con
                      (T*)J[1], (T*)J[2], m, tg, offsets, src.x[0], src.x[1], src.x[2], src.u[0], src.u[1],     \
                      src.u[2], src.id, dst.x[0], dst.x[1], dst.x[2], dst.u[0], dst.u[1], dst.u[2], dst.id, qm, qw, \
                      dt, scale, unscale)
-  if (pusher == PIC_PUSH_BORIS) YP_TP(PIC_PUSH_BORIS); else YP_TP(PIC_PUSH_ANALYTIC);
+  if (pusher == PIC_PUSH_BORIS) YP_TP(PIC_PUSH_BORIS);
+  else if (pusher == PIC_PUSH_HC) YP_TP(PIC_PUSH_HC);
+  else YP_TP(PIC_PUSH_ANALYTIC);
 #undef YP_TP
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "tile push launch failed");
 }

@@ -44,7 +44,7 @@ def _pos_err(got, ref, L):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("pusher", ["boris", "analytic"])
+@pytest.mark.parametrize("pusher", ["boris", "analytic", "hc"])
 @pytest.mark.parametrize("ndim", [3, 2])
 @pytest.mark.parametrize("field_scale", [1.0, 50.0])
 def test_gather_push(ndim, pusher, prec, field_scale, coeffs16):
@@ -67,7 +67,7 @@ def test_gather_push(ndim, pusher, prec, field_scale, coeffs16):
     grid.gather_push(p, pusher, x_old=xo)
     grid.sync()
     Ep, Bp = pt.gather(E, B, x, DX, ndim)
-    push = pt.boris if pusher == "boris" else pt.analytic
+    push = {"boris": pt.boris, "analytic": pt.analytic, "hc": pt.higuera_cary}[pusher]
     un = push(u, Ep, Bp, -1.0, wl.DT)
     L = _box(n)[:ndim]
     xn, _ = pt.advance_position(x, un, wl.DT, L, ndim)
@@ -168,3 +168,41 @@ def test_deposit_with_wide_ampere_keeps_the_deposited_current(coeffs16):
                 grid.advance_E(use_J=True)
             assert e.value.code == -6
         grid.close()
+
+
+def test_higuera_cary_keeps_relativistic_exb_drift_on_gpu(coeffs16):
+    """Uniform crossed fields (|E| = 0.9 |B|) on a 2D plane: electrons moving
+    at the E x B drift keep u = gamma_d v_d over 40 GPU steps with the
+    Higuera-Cary pusher (to 1e-12), as the method promises."""
+    CE, CB = coeffs16
+    n = (64, 4, 1)
+    shape = (1, n[1], n[0])
+    Ev, Bv = np.array([0.0, 0.9 * 3.0, 0.0]), np.array([0.0, 0.0, 3.0])
+    E = [np.full(shape, Ev[c]) for c in range(3)]
+    B = [np.full(shape, Bv[c]) for c in range(3)]
+    v = np.cross(Ev, Bv) / (Bv @ Bv)
+    u0 = v / np.sqrt(1 - v @ v)
+    x = np.zeros((3, 32))
+    x[0] = np.linspace(0.05, 0.95, 32) * n[0] * DX[0]
+    x[1] = 0.5 * n[1] * DX[1]
+    u = np.repeat(u0[:, None], 32, axis=1)
+    grid = b.Grid([dev(e) for e in E], [dev(e) for e in B], DX[:2], wl.DT, CE, CB, ndim=2)
+    ud = dev(u)
+    grid.step_n([b.Particles(dev(x), ud, q=-1.0, m=1.0)], 40, pusher="hc")
+    grid.sync()
+    assert np.max(np.abs(host(ud) - u)) <= 1e-12 * np.max(np.abs(u0))
+    grid.close()
+
+
+def test_adjoint_refuses_higuera_cary(coeffs16):
+    CE, CB = coeffs16
+    shape = (2, 4, 64)
+    z = [dev(np.zeros(shape)) for _ in range(6)]
+    grid = b.Grid(z[:3], z[3:], DX, wl.DT, CE, CB)
+    lE = [dev(np.zeros(shape)) for _ in range(3)]
+    lB = [dev(np.zeros(shape)) for _ in range(3)]
+    g = [torch.zeros(16, dtype=torch.float64, device="cuda:0") for _ in range(2)]
+    with pytest.raises(b.YeePICError) as e:
+        grid.adjoint_step(lE, lB, g[0], g[1], pusher="hc")
+    assert e.value.code == -6
+    grid.close()

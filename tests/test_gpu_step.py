@@ -20,7 +20,7 @@ def _by_id(t, ids):
     return host(t)[:, order]
 
 
-@pytest.mark.parametrize("pusher", ["boris", "analytic"])
+@pytest.mark.parametrize("pusher", ["boris", "analytic", "hc"])
 @pytest.mark.parametrize("nsteps", [1, 4, 9])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_step_n_plasma(pusher, nsteps, prec, coeffs16):
@@ -149,7 +149,7 @@ def test_step_n_odd_and_even_counts_agree(coeffs16):
     g2.close()
 
 
-@pytest.mark.parametrize("pusher", ["boris", "analytic"])
+@pytest.mark.parametrize("pusher", ["boris", "analytic", "hc"])
 def test_vacuum_tile_ordered_push_is_bit_exact(pusher, coeffs16):
     """A 3D vacuum step_n over many particles pushes a tile-ordered copy
     (re-sorted every 16 steps) and scatters it back: 37 steps in one call
