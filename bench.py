@@ -466,6 +466,12 @@ def main():
             "sweep_GBps": fp32["sweep_bytes"] / (fp32["ms_sweep"] * 1e-3) / 1e9,
             "speedup_vs_fp64_step": main_run["ms_step"] / fp32["ms_step"],
             "speedup_vs_fp64_sweep": main_run["ms_sweep"] / fp32["ms_sweep"]}
+        # the headline workload with the Higuera-Cary pusher (Sec. 4.1's default pusher)
+        hc = run_vacuum(torch, b, wl, n, "fp64", pulse, 12 * L, 4 * L, 1 << 20, box, max(50, args.steps // 5),
+                        args.warmup, "hc", 2, CE, CB)
+        res["hc_pusher"] = {"cell_updates_per_s": cells / (hc["ms_step"] * 1e-3), "ms_per_step": hc["ms_step"],
+                            "gather_push_ms": hc["ms_push"],
+                            "particle_pushes_per_s": hc["npart"] / (hc["ms_push"] * 1e-3)}
         res["plane_wave_2048x512x512"] = run_plane_wave(torch, b, wl, CE, CB, steps=20)
         res["plasma_512x256x256"] = run_plasma(torch, b, wl, CE, CB, steps=args.plasma_steps)
         res["plasma_512x256x256_dt_quarter"] = run_plasma_quarter(torch, b, wl, args.plasma_steps)
