@@ -9,8 +9,9 @@ Normalised units c = m_e = e = 1 (Sec. 2.1); a species has charge q, mass m.
 Passages followed
 -----------------
 * App. A: each field component is interpolated from its own staggered grid
-  points with the shape S; here S is the linear (first-order) shape, one
-  factor per direction.  Staggering offsets (in cells) of the components:
+  points with the shape S, one factor per direction: the linear
+  (first-order) shape, or the quadratic B-spline that the Sec. 4.2 run lists
+  in its parameter table (three nodes around the nearest one).  Staggering offsets (in cells) of the components:
   E1 (1/2,0,0) E2 (0,1/2,0) E3 (0,0,1/2) B1 (0,1/2,1/2) B2 (1/2,0,1/2)
   B3 (1/2,1/2,0).
 * Sec. 1 (Boris pusher): half electric kick, magnetic rotation, half kick.
@@ -63,8 +64,22 @@ def _axis_weights(xd, dx, off, n):
     return i0 % n, (i0 + 1) % n, 1.0 - w1, w1
 
 
-def gather_component(f, x, dx, off, ndim):
-    """App. A: sum over the component's own grid points of f S(X - x)."""
+def _axis_nodes_quadratic(xd, dx, off, n):
+    """Quadratic B-spline shape along one direction (the Sec. 4.2 run's
+    choice): the three nodes around the nearest one, i = round(u), with
+    weights (1/2 - d)^2/2, 3/4 - d^2, (1/2 + d)^2/2 for d = u - i."""
+    u = xd / dx - off
+    i = np.floor(u + 0.5)
+    d = u - i
+    i = i.astype(np.int64)
+    return [(i - 1) % n, i % n, (i + 1) % n], [0.5 * (0.5 - d) ** 2, 0.75 - d * d, 0.5 * (0.5 + d) ** 2]
+
+
+def gather_component(f, x, dx, off, ndim, order=1):
+    """App. A: sum over the component's own grid points of f S(X - x);
+    ``order`` 1 is the linear shape, 2 the quadratic B-spline."""
+    if order == 2:
+        return _gather_quadratic(f, x, dx, off, ndim)
     n3, n2, n1 = f.shape
     a0, a1, wa0, wa1 = _axis_weights(x[0], dx[0], off[0], n1)
     b0, b1, wb0, wb1 = _axis_weights(x[1], dx[1], off[1], n2)
@@ -79,10 +94,28 @@ def gather_component(f, x, dx, off, ndim):
                      + wb1 * (wa0 * f[c1, b1, a0] + wa1 * f[c1, b1, a1])))
 
 
-def gather(E, B, x, dx, ndim=3):
+def _gather_quadratic(f, x, dx, off, ndim):
+    n3, n2, n1 = f.shape
+    ia, wa = _axis_nodes_quadratic(x[0], dx[0], off[0], n1)
+    ib, wb = _axis_nodes_quadratic(x[1], dx[1], off[1], n2)
+    out = np.zeros(x.shape[1])
+    if ndim == 2:
+        for b in range(3):
+            for a in range(3):
+                out += wb[b] * wa[a] * f[0][ib[b], ia[a]]
+        return out
+    ic, wc = _axis_nodes_quadratic(x[2], dx[2], off[2], n3)
+    for c in range(3):
+        for b in range(3):
+            for a in range(3):
+                out += wc[c] * wb[b] * wa[a] * f[ic[c], ib[b], ia[a]]
+    return out
+
+
+def gather(E, B, x, dx, ndim=3, order=1):
     """Fields at the particles: (E_p, B_p), each (3, np)."""
-    Ep = np.stack([gather_component(E[c], x, dx, E_OFF[c], ndim) for c in range(3)])
-    Bp = np.stack([gather_component(B[c], x, dx, B_OFF[c], ndim) for c in range(3)])
+    Ep = np.stack([gather_component(E[c], x, dx, E_OFF[c], ndim, order) for c in range(3)])
+    Bp = np.stack([gather_component(B[c], x, dx, B_OFF[c], ndim, order) for c in range(3)])
     return Ep, Bp
 
 
@@ -221,8 +254,34 @@ def min_image(x_new, x_old, L):
 # ----------------------------------------------------------------------------
 
 
-def _shapes(x0, x1, dx):
-    """Local 3-node linear shapes before/after a move of less than one cell."""
+def _shapes_quadratic(x0, x1, dx):
+    """Local 4-node quadratic shapes before/after a move of less than one
+    cell (the nearest nodes differ by at most one)."""
+    X0 = x0 / dx
+    X1 = x1 / dx
+    i0 = np.floor(X0 + 0.5)
+    i1 = np.floor(X1 + 0.5)
+    d0 = X0 - i0
+    d1 = X1 - i1
+    base = np.minimum(i0, i1) - 1
+    a0 = (i0 - 1 - base).astype(np.int64)
+    a1 = (i1 - 1 - base).astype(np.int64)
+    npart = x0.shape[0]
+    S0 = np.zeros((npart, 4))
+    S1 = np.zeros((npart, 4))
+    r = np.arange(npart)
+    for k, (w0, w1) in enumerate(zip((0.5 * (0.5 - d0) ** 2, 0.75 - d0 * d0, 0.5 * (0.5 + d0) ** 2),
+                                     (0.5 * (0.5 - d1) ** 2, 0.75 - d1 * d1, 0.5 * (0.5 + d1) ** 2))):
+        S0[r, a0 + k] = w0
+        S1[r, a1 + k] = w1
+    return base.astype(np.int64), S0, S1
+
+
+def _shapes(x0, x1, dx, order=1):
+    """Local 3-node linear shapes before/after a move of less than one cell
+    (``order`` 2: the 4-node quadratic ones)."""
+    if order == 2:
+        return _shapes_quadratic(x0, x1, dx)
     X0 = x0 / dx
     X1 = x1 / dx
     i0 = np.floor(X0)
@@ -243,18 +302,19 @@ def _shapes(x0, x1, dx):
     return base.astype(np.int64), S0, S1
 
 
-def deposit(x_old, x_new, q, w, dx, dt, shape, ndim=3, u=None):
+def deposit(x_old, x_new, q, w, dx, dt, shape, ndim=3, u=None, order=1):
     """Current J^{n+1/2} (3 arrays, E staggering) of particles moving
     x_old -> x_new (wrapped positions; the move is unwrapped by minimum
     image).  In 2D the out-of-plane current is q w v3 times the time-averaged
-    in-plane shape (needs ``u``)."""
+    in-plane shape (needs ``u``).  ``order`` 2: quadratic shapes (the same
+    Esirkepov decomposition on 4-node stencils)."""
     n3, n2, n1 = shape
     L = [n1 * dx[0], n2 * dx[1], n3 * dx[2]][:ndim]
     disp = min_image(x_new[:ndim], x_old[:ndim], L)
     J = [np.zeros(shape) for _ in range(3)]
     bases, S0s, S1s = [], [], []
     for d in range(ndim):
-        b, s0, s1 = _shapes(x_old[d], x_old[d] + disp[d], dx[d])
+        b, s0, s1 = _shapes(x_old[d], x_old[d] + disp[d], dx[d], order)
         bases.append(b)
         S0s.append(s0)
         S1s.append(s1)
@@ -277,10 +337,11 @@ def deposit(x_old, x_new, q, w, dx, dt, shape, ndim=3, u=None):
         C1 = -qw * dx[0] / dt * np.cumsum(W1, axis=1)
         C2 = -qw * dx[1] / dt * np.cumsum(W2, axis=2)
         C3 = -qw * dx[2] / dt * np.cumsum(W3, axis=3)
+        K = S0x.shape[1]
         for comp, Cc in enumerate((C1, C2, C3)):
-            for a in range(3):
-                for b in range(3):
-                    for c in range(3):
+            for a in range(K):
+                for b in range(K):
+                    for c in range(K):
                         ia = (bases[0] + a) % ns[0]
                         ib = (bases[1] + b) % ns[1]
                         ic = (bases[2] + c) % ns[2]
@@ -298,20 +359,36 @@ def deposit(x_old, x_new, q, w, dx, dt, shape, ndim=3, u=None):
     C1 = -qw * dx[0] / dt * np.cumsum(W1, axis=1)
     C2 = -qw * dx[1] / dt * np.cumsum(W2, axis=2)
     C3 = qw * v3[:, None, None] * W3
+    K = S0x.shape[1]
     for comp, Cc in enumerate((C1, C2, C3)):
-        for a in range(3):
-            for b in range(3):
+        for a in range(K):
+            for b in range(K):
                 ia = (bases[0] + a) % ns[0]
                 ib = (bases[1] + b) % ns[1]
                 np.add.at(J[comp], (np.zeros_like(ia), ib, ia), Cc[:, a, b])
     return J
 
 
-def charge_density(x, q, w, dx, shape, ndim=3):
-    """rho on the nodes: q w times the linear shape (Sec. 3.3 continuity)."""
+def charge_density(x, q, w, dx, shape, ndim=3, order=1):
+    """rho on the nodes: q w times the linear shape (Sec. 3.3 continuity);
+    ``order`` 2: the quadratic B-spline."""
     n3, n2, n1 = shape
     rho = np.zeros(shape)
     ns = (n1, n2, n3)
+    if order == 2:
+        nodes = [_axis_nodes_quadratic(x[d], dx[d], 0.0, ns[d]) for d in range(ndim)]
+        if ndim == 2:
+            for a in range(3):
+                for b in range(3):
+                    np.add.at(rho, (np.zeros_like(nodes[0][0][a]), nodes[1][0][b], nodes[0][0][a]),
+                              q * w * nodes[0][1][a] * nodes[1][1][b])
+            return rho
+        for a in range(3):
+            for b in range(3):
+                for c in range(3):
+                    np.add.at(rho, (nodes[2][0][c], nodes[1][0][b], nodes[0][0][a]),
+                              q * w * nodes[0][1][a] * nodes[1][1][b] * nodes[2][1][c])
+        return rho
     idx, wts = [], []
     for d in range(ndim):
         i0, i1, w0, w1 = _axis_weights(x[d], dx[d], 0.0, ns[d])

@@ -25,15 +25,16 @@ def _ampere_is_yee(CB):
     return abs(CB[0] - 1.0) <= 1e-20 and bool(np.all(np.abs(CB[1:]) <= 1e-20))
 
 
-def step(E, B, species, CE, CB, dx, dt, *, pusher="boris", deposit=False, ndim=3):
+def step(E, B, species, CE, CB, dx, dt, *, pusher="boris", deposit=False, ndim=3, order=1):
     """Advance fields and every species by one step; species entries are
-    dicts with keys x, u, q, m, w (x and u are replaced)."""
+    dicts with keys x, u, q, m, w (x and u are replaced).  ``order``: shape
+    function of gather and deposit, 1 linear, 2 quadratic."""
     shape = E[0].shape
     n3, n2, n1 = shape
     L = [n1 * dx[0], n2 * dx[1], n3 * dx[2]][:ndim]
     J = [np.zeros(shape) for _ in range(3)] if deposit else None
     for sp in species:
-        Ep, Bp = particles.gather(E, B, sp["x"], dx, ndim)
+        Ep, Bp = particles.gather(E, B, sp["x"], dx, ndim, order)
         qm = sp["q"] / sp["m"]
         if pusher == "boris":
             u = particles.boris(sp["u"], Ep, Bp, qm, dt)
@@ -48,7 +49,7 @@ def step(E, B, species, CE, CB, dx, dt, *, pusher="boris", deposit=False, ndim=3
         if ndim == 2 and x_old.shape[0] == 3:
             x_new = np.concatenate([x_new, x_old[2:3]], axis=0)
         if deposit:
-            Js = particles.deposit(x_old, x_new, sp["q"], sp["w"], dx, dt, shape, ndim, u=u)
+            Js = particles.deposit(x_old, x_new, sp["q"], sp["w"], dx, dt, shape, ndim, u=u, order=order)
             J = [a + b for a, b in zip(J, Js)]
         sp["x"], sp["u"] = x_new, u
     if deposit and not _ampere_is_yee(CB):
