@@ -189,6 +189,15 @@ int pic_current_correction(pic_grid *g, void *J1_out);
  * for the gather (never out of bounds) and reported by pic_check. */
 int pic_gather_push(pic_grid *g, pic_particles *p, int pusher, double *const x_old[3]);
 
+/* Particle shape of the gather and the deposit: order 1 the linear shape (the
+ * default), order 2 the quadratic B-spline the Sec. 4.2 run lists (three
+ * nodes around the nearest one per direction in the gather; the Esirkepov
+ * decomposition of Sec. 3.3 on four-node stencils in the deposit, so
+ * continuity with the Yee divergence still holds exactly).  Applies to every
+ * later call on the grid.  PIC_EINVAL for another order; the adjoint refuses
+ * order 2 (PIC_EUNSUPPORTED). */
+int pic_set_shape(pic_grid *g, int order);
+
 /* ---- current (Sec. 3.3) ----------------------------------------------------
  * Adds the charge-conserving (Esirkepov, linear shape) current J^{n+1/2} of
  * particles that moved from x_old to p->x (less than one cell per step; the

@@ -53,7 +53,7 @@ class _Adjoint(ctypes.Structure):
 EXPORTS = ["pic_design_coeffs", "pic_init_grid", "pic_set_fields", "pic_advance_B_half", "pic_advance_E",
            "pic_field_sweep", "pic_gather_push", "pic_deposit_J", "pic_step_n", "pic_sync", "pic_check",
            "pic_grid_widths", "pic_destroy", "pic_last_error", "pic_set_sort_interval", "pic_adjoint_step", "pic_step_to",
-           "pic_current_correction"]
+           "pic_current_correction", "pic_set_shape"]
 
 
 def lib():
@@ -76,6 +76,7 @@ def lib():
         L.pic_deposit_J.argtypes = [vp, ctypes.POINTER(_Particles), vp, i]
         L.pic_step_n.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(_Particles)), i, i, i, i]
         L.pic_set_sort_interval.argtypes = [vp, i]
+        L.pic_set_shape.argtypes = [vp, i]
         PP = ctypes.POINTER(ctypes.POINTER(_Particles))
         L.pic_adjoint_step.argtypes = [vp, ctypes.POINTER(_Adjoint), PP, PP, i, i]
         L.pic_step_to.argtypes = [vp, PP, i, i, ctypes.c_void_p * 3, ctypes.c_void_p * 3, ctypes.c_void_p]
@@ -263,6 +264,10 @@ class Grid:
         half = _ptr3(B_half) if B_half is not None else None
         _check(lib().pic_step_to(self._h, arr, len(species), PUSHERS[pusher], _ptr3(E_out), _ptr3(B_out),
                                  ctypes.cast(half, ctypes.c_void_p) if half is not None else None))
+
+    def set_shape(self, order):
+        """Particle shape of gather and deposit: 1 linear, 2 quadratic."""
+        _check(lib().pic_set_shape(self._h, int(order)))
 
     def set_sort_interval(self, steps):
         _check(lib().pic_set_sort_interval(self._h, int(steps)))

@@ -320,6 +320,7 @@ int pic_init_grid(const pic_grid_desc* d, pic_grid** out) {
   m.n2 = (int)g->n[1];
   m.n3 = (int)g->n[2];
   m.ndim = g->ndim;
+  m.order = 1;
   m.dx1 = g->dx[0];
   m.dx2 = g->dx[1];
   m.dx3 = g->dx[2];
@@ -638,6 +639,7 @@ int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* c
   if (!g || !adj) return set_error(PIC_EINVAL, "pic_adjoint_step: NULL argument");
   if (g->prec != PIC_FP64) return set_error(PIC_EUNSUPPORTED, "the adjoint is built for FP64 grids only");
   if (pusher == PIC_PUSH_HC) return set_error(PIC_EUNSUPPORTED, "the adjoint covers the Boris and exact pushers");
+  if (g->mesh.order != 1) return set_error(PIC_EUNSUPPORTED, "the adjoint covers the linear particle shape");
   if (pusher != PIC_PUSH_BORIS && pusher != PIC_PUSH_ANALYTIC) return set_error(PIC_EINVAL, "bad pusher");
   if (nspecies < 0) return set_error(PIC_EINVAL, "negative count");
   if (nspecies > 0 && (!species || !lambda)) return set_error(PIC_EINVAL, "species or lambda is NULL");
@@ -718,6 +720,13 @@ int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* c
   for (int s = 0; s < nspecies && !rc; ++s)
     rc = launch_adjoint_push(m, g->E, g->B, lE, lB, *species[s], *lambda[s], pusher, dt, g->stream);
   return rc;
+}
+
+int pic_set_shape(pic_grid* g, int order) {
+  if (!g) return set_error(PIC_EINVAL, "grid is NULL");
+  if (order != 1 && order != 2) return set_error(PIC_EINVAL, "shape order must be 1 or 2");
+  g->mesh.order = order;
+  return PIC_OK;
 }
 
 int pic_set_sort_interval(pic_grid* g, int steps) {

@@ -325,14 +325,19 @@ __device__ __forceinline__ double wrap_pos(double x, double L) {
 }
 
 // ---------------------------------------------------------------------------
-// Esirkepov deposit, linear shape (Sec. 3.3).  Local 3-node stencils per
-// direction starting at min(floor(X0), floor(X1)); J_d is the running sum of
-// W_d along d times -q w dx_d/dt.
+// Esirkepov deposit (Sec. 3.3).  Local K-node stencils per direction: linear
+// shape K = 3 starting at min(floor(X0), floor(X1)); quadratic B-spline
+// (the Sec. 4.2 run's shape) K = 4 starting one node left of the smaller of
+// the nearest nodes round(X0), round(X1).  J_d is the running sum of W_d
+// along d times -q w dx_d/dt.
 // ---------------------------------------------------------------------------
-struct Shape3 {
+template <int K>
+struct ShapeK {
   int base;
-  double s0[3], ds[3];
+  double s0[K], ds[K];
 };
+using Shape3 = ShapeK<3>;
+using Shape4 = ShapeK<4>;
 
 __device__ __forceinline__ Shape3 shape3(double xo, double xn, double idx, double L) {
   double d = xn - xo;  // minimum image
@@ -354,6 +359,38 @@ __device__ __forceinline__ Shape3 shape3(double xo, double xn, double idx, doubl
   s1[a1 + 1] = r1;
   for (int q = 0; q < 3; ++q) s.ds[q] = s1[q] - s.s0[q];
   s.base = (int)fmin(fmax(b, -2.0), 1e9);
+  return s;
+}
+
+// quadratic B-spline weights at offset d = X - round(X) from the nearest node
+__device__ __forceinline__ void bspline2(double d, double w[3]) {
+  w[0] = 0.5 * (0.5 - d) * (0.5 - d);
+  w[1] = 0.75 - d * d;
+  w[2] = 0.5 * (0.5 + d) * (0.5 + d);
+}
+
+__device__ __forceinline__ Shape4 shape4(double xo, double xn, double idx, double L) {
+  double d = xn - xo;  // minimum image
+  if (d > 0.5 * L) d -= L;
+  if (d < -0.5 * L) d += L;
+  const double X0 = xo * idx, X1 = (xo + d) * idx;
+  const double i0 = floor(X0 + 0.5), i1 = floor(X1 + 0.5);
+  const double b = fmin(i0, i1) - 1.0;
+  int a0 = (int)(i0 - 1.0 - b), a1 = (int)(i1 - 1.0 - b);
+  a0 = a0 < 0 ? 0 : (a0 > 1 ? 1 : a0);
+  a1 = a1 < 0 ? 0 : (a1 > 1 ? 1 : a1);
+  double w0[3], w1[3];
+  bspline2(X0 - i0, w0);
+  bspline2(X1 - i1, w1);
+  Shape4 s;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {  // selects, not indexed stores: the arrays stay in registers
+    const double s0 = k == a0 ? w0[0] : (k == a0 + 1 ? w0[1] : (k == a0 + 2 ? w0[2] : 0.0));
+    const double s1 = k == a1 ? w1[0] : (k == a1 + 1 ? w1[1] : (k == a1 + 2 ? w1[2] : 0.0));
+    s.s0[k] = s0;
+    s.ds[k] = s1 - s0;
+  }
+  s.base = (int)fmin(fmax(b, -3.0), 1e9);
   return s;
 }
 
@@ -401,48 +438,145 @@ __device__ __forceinline__ void gather6(const T* __restrict__ E1, const T* __res
   }
 }
 
+// Quadratic B-spline gather (the Sec. 4.2 run's shape): the three nodes
+// around the nearest one, round(X), along each direction, wrapped
+// periodically (positions outside the box are clamped as in ``axis``).
+struct AxisQ {
+  int i[3];
+  double w[3];
+};
+
+__device__ __forceinline__ AxisQ axisq(double x, double idx, double off, int n) {
+  const double u = x * idx - off;
+  double c = floor(u + 0.5);
+  c = fmin(fmax(c, -1.0), (double)n);
+  AxisQ a;
+  bspline2(u - c, a.w);
+  const int ic = (int)c;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int i = (ic - 1 + k) % n;
+    a.i[k] = i < 0 ? i + n : i;
+  }
+  return a;
+}
+
+template <typename T>
+__device__ __forceinline__ double interp3q(const T* __restrict__ f, const AxisQ& a, const AxisQ& b, const AxisQ& c,
+                                           int n1, size_t plane) {
+  double acc = 0;
+#pragma unroll
+  for (int kc = 0; kc < 3; ++kc) {
+    double accb = 0;
+#pragma unroll
+    for (int kb = 0; kb < 3; ++kb) {
+      const T* r = f + (size_t)c.i[kc] * plane + (size_t)b.i[kb] * n1;
+      accb += b.w[kb] * (a.w[0] * (double)r[a.i[0]] + a.w[1] * (double)r[a.i[1]] + a.w[2] * (double)r[a.i[2]]);
+    }
+    acc += c.w[kc] * accb;
+  }
+  return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ double interp2q(const T* __restrict__ f, const AxisQ& a, const AxisQ& b, int n1) {
+  double acc = 0;
+#pragma unroll
+  for (int kb = 0; kb < 3; ++kb) {
+    const T* r = f + (size_t)b.i[kb] * n1;
+    acc += b.w[kb] * (a.w[0] * (double)r[a.i[0]] + a.w[1] * (double)r[a.i[1]] + a.w[2] * (double)r[a.i[2]]);
+  }
+  return acc;
+}
+
+template <typename T, int NDIM>
+__device__ __forceinline__ void gather6q(const T* __restrict__ E1, const T* __restrict__ E2, const T* __restrict__ E3,
+                                         const T* __restrict__ B1, const T* __restrict__ B2, const T* __restrict__ B3,
+                                         const Mesh& m, const double x[3], double E[3], double B[3]) {
+  const AxisQ a0 = axisq(x[0], m.idx1, 0.0, m.n1), ah = axisq(x[0], m.idx1, 0.5, m.n1);
+  const AxisQ b0 = axisq(x[1], m.idx2, 0.0, m.n2), bh = axisq(x[1], m.idx2, 0.5, m.n2);
+  if (NDIM == 3) {
+    const AxisQ c0 = axisq(x[2], m.idx3, 0.0, m.n3), ch = axisq(x[2], m.idx3, 0.5, m.n3);
+    const size_t pl = (size_t)m.n1 * m.n2;
+    E[0] = interp3q(E1, ah, b0, c0, m.n1, pl);
+    E[1] = interp3q(E2, a0, bh, c0, m.n1, pl);
+    E[2] = interp3q(E3, a0, b0, ch, m.n1, pl);
+    B[0] = interp3q(B1, a0, bh, ch, m.n1, pl);
+    B[1] = interp3q(B2, ah, b0, ch, m.n1, pl);
+    B[2] = interp3q(B3, ah, bh, c0, m.n1, pl);
+  } else {
+    const size_t o = plane_offset(m, x[2]);
+    E[0] = interp2q(E1 + o, ah, b0, m.n1);
+    E[1] = interp2q(E2 + o, a0, bh, m.n1);
+    E[2] = interp2q(E3 + o, a0, b0, m.n1);
+    B[0] = interp2q(B1 + o, a0, bh, m.n1);
+    B[1] = interp2q(B2 + o, ah, b0, m.n1);
+    B[2] = interp2q(B3 + o, ah, bh, m.n1);
+  }
+}
+
+// the gather of shape order ORDER (1 linear, 2 quadratic)
+template <typename T, int NDIM, int ORDER>
+__device__ __forceinline__ void gather_o(const T* __restrict__ E1, const T* __restrict__ E2, const T* __restrict__ E3,
+                                         const T* __restrict__ B1, const T* __restrict__ B2, const T* __restrict__ B3,
+                                         const Mesh& m, const double x[3], double E[3], double B[3]) {
+  if constexpr (ORDER == 2)
+    gather6q<T, NDIM>(E1, E2, E3, B1, B2, B3, m, x, E, B);
+  else
+    gather6<T, NDIM>(E1, E2, E3, B1, B2, B3, m, x, E, B);
+}
+
+// the deposit stencil of shape order ORDER
+template <int ORDER>
+__device__ __forceinline__ ShapeK<ORDER + 2> shape_o(double xo, double xn, double idx, double L) {
+  if constexpr (ORDER == 2)
+    return shape4(xo, xn, idx, L);
+  else
+    return shape3(xo, xn, idx, L);
+}
+
 // Esirkepov 3D decomposition (Sec. 3.3, cited method): for each node
-// (a, b, c) of the 3x3x3 local stencil, add the current contributions
+// (a, b, c) of the K x K x K local stencil, add the current contributions
 // J_d = -q w (dx_d/dt) * (running sum of W_d along d).  ``add(comp, a, b, c, v)``
 // receives stencil-local node indices.
-template <typename Add>
-__device__ __forceinline__ void esirkepov3(const Shape3& sx, const Shape3& sy, const Shape3& sz, double c1,
-                                           double c2, double c3, Add add) {
+template <int K, typename Add>
+__device__ __forceinline__ void esirkepov(const ShapeK<K>& sx, const ShapeK<K>& sy, const ShapeK<K>& sz, double c1,
+                                          double c2, double c3, Add add) {
 #pragma unroll
-  for (int b = 0; b < 3; ++b)
+  for (int b = 0; b < K; ++b)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < K; ++c) {
       const double w = sy.s0[b] * sz.s0[c] + 0.5 * sy.ds[b] * sz.s0[c] + 0.5 * sy.s0[b] * sz.ds[c] +
                        sy.ds[b] * sz.ds[c] * (1.0 / 3.0);
       double run = 0;
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
+      for (int a = 0; a < K - 1; ++a) {
         run += sx.ds[a] * w;
         if (run != 0.0) add(0, a, b, c, c1 * run);
       }
     }
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < K; ++a)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < K; ++c) {
       const double w = sx.s0[a] * sz.s0[c] + 0.5 * sx.ds[a] * sz.s0[c] + 0.5 * sx.s0[a] * sz.ds[c] +
                        sx.ds[a] * sz.ds[c] * (1.0 / 3.0);
       double run = 0;
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
+      for (int b = 0; b < K - 1; ++b) {
         run += sy.ds[b] * w;
         if (run != 0.0) add(1, a, b, c, c2 * run);
       }
     }
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < K; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
+    for (int b = 0; b < K; ++b) {
       const double w = sx.s0[a] * sy.s0[b] + 0.5 * sx.ds[a] * sy.s0[b] + 0.5 * sx.s0[a] * sy.ds[b] +
                        sx.ds[a] * sy.ds[b] * (1.0 / 3.0);
       double run = 0;
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
+      for (int c = 0; c < K - 1; ++c) {
         run += sz.ds[c] * w;
         if (run != 0.0) add(2, a, b, c, c3 * run);
       }

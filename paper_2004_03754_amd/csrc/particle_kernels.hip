@@ -11,7 +11,7 @@ namespace {
 using namespace pdev;
 
 
-template <typename T, int PUSH, int NDIM>
+template <typename T, int PUSH, int NDIM, int ORDER>
 __global__ __launch_bounds__(256) void gather_push_kernel(const T* __restrict__ E1, const T* __restrict__ E2,
                                                           const T* __restrict__ E3, const T* __restrict__ B1,
                                                           const T* __restrict__ B2, const T* __restrict__ B3,
@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void gather_push_kernel(const T* __restrict__ 
   double x[3] = {x1[p], x2[p], (NDIM == 3 || m.n3 > 1) ? x3[p] : 0.0};
   double u[3] = {u1[p], u2[p], u3[p]};
   double E[3], B[3];
-  gather6<T, NDIM>(E1, E2, E3, B1, B2, B3, m, x, E, B);
+  gather_o<T, NDIM, ORDER>(E1, E2, E3, B1, B2, B3, m, x, E, B);
   if (PUSH == PIC_PUSH_BORIS)
     boris(u, E, B, qm, dt);
   else if (PUSH == PIC_PUSH_HC)
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void gather_push_kernel(const T* __restrict__ 
   u3[p] = u[2];
 }
 
-template <typename T, int NDIM>
+template <typename T, int NDIM, int ORDER>
 __global__ __launch_bounds__(256) void deposit_kernel(T* __restrict__ J1, T* __restrict__ J2, T* __restrict__ J3,
                                                       Mesh m, const double* __restrict__ x1,
                                                       const double* __restrict__ x2, const double* __restrict__ x3,
@@ -59,26 +59,27 @@ __global__ __launch_bounds__(256) void deposit_kernel(T* __restrict__ J1, T* __r
                                                       double dt) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= np) return;
-  const Shape3 sx = shape3(xo1[p], x1[p], m.idx1, m.L1);
-  const Shape3 sy = shape3(xo2[p], x2[p], m.idx2, m.L2);
+  constexpr int K = ORDER + 2;  // stencil nodes per direction
+  const ShapeK<K> sx = shape_o<ORDER>(xo1[p], x1[p], m.idx1, m.L1);
+  const ShapeK<K> sy = shape_o<ORDER>(xo2[p], x2[p], m.idx2, m.L2);
   const size_t pl = (size_t)m.n1 * m.n2;
   const double c1 = -qw * m.dx1 / dt, c2 = -qw * m.dx2 / dt;
   if (NDIM == 3) {
-    const Shape3 sz = shape3(xo3[p], x3[p], m.idx3, m.L3);
+    const ShapeK<K> sz = shape_o<ORDER>(xo3[p], x3[p], m.idx3, m.L3);
     const double c3 = -qw * m.dx3 / dt;
-    int ia[3], jb[3], kc[3];
-    for (int q = 0; q < 3; ++q) {
+    int ia[K], jb[K], kc[K];
+    for (int q = 0; q < K; ++q) {
       ia[q] = wrapn(sx.base + q, m.n1);
       jb[q] = wrapn(sy.base + q, m.n2);
       kc[q] = wrapn(sz.base + q, m.n3);
     }
     T* Jg[3] = {J1, J2, J3};
-    esirkepov3(sx, sy, sz, c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
+    esirkepov<K>(sx, sy, sz, c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
       atomic_add(&Jg[comp][(size_t)kc[c] * pl + (size_t)jb[b] * m.n1 + ia[a]], v);
     });
   } else {
-    int ia[3], jb[3];
-    for (int q = 0; q < 3; ++q) {
+    int ia[K], jb[K];
+    for (int q = 0; q < K; ++q) {
       ia[q] = wrapn(sx.base + q, m.n1);
       jb[q] = wrapn(sy.base + q, m.n2);
     }
@@ -90,25 +91,25 @@ __global__ __launch_bounds__(256) void deposit_kernel(T* __restrict__ J1, T* __r
     }
     const double g = sqrt(1.0 + u1[p] * u1[p] + u2[p] * u2[p] + u3[p] * u3[p]);
     const double c3 = qw * u3[p] / g;
-    for (int b = 0; b < 3; ++b) {
+    for (int b = 0; b < K; ++b) {
       const double w = sy.s0[b] + 0.5 * sy.ds[b];
       double run = 0;
-      for (int a = 0; a < 2; ++a) {
+      for (int a = 0; a < K - 1; ++a) {
         run += sx.ds[a] * w;
         if (run != 0.0) atomic_add(&J1[(size_t)jb[b] * m.n1 + ia[a]], c1 * run);
       }
     }
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < K; ++a) {
       const double w = sx.s0[a] + 0.5 * sx.ds[a];
       double run = 0;
-      for (int b = 0; b < 2; ++b) {
+      for (int b = 0; b < K - 1; ++b) {
         run += sy.ds[b] * w;
         if (run != 0.0) atomic_add(&J2[(size_t)jb[b] * m.n1 + ia[a]], c2 * run);
       }
     }
     if (c3 != 0.0)
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) {
+      for (int a = 0; a < K; ++a)
+        for (int b = 0; b < K; ++b) {
           const double w = sx.s0[a] * sy.s0[b] + 0.5 * sx.ds[a] * sy.s0[b] + 0.5 * sx.s0[a] * sy.ds[b] +
                            sx.ds[a] * sy.ds[b] * (1.0 / 3.0);
           if (w != 0.0) atomic_add(&J3[(size_t)jb[b] * m.n1 + ia[a]], c3 * w);
@@ -141,10 +142,17 @@ int run_gather_push(const Mesh& m, void* const E[3], void* const B[3], const pic
   double* o1 = xo ? xo[0] : nullptr;
   double* o2 = xo ? xo[1] : nullptr;
   double* o3 = xo ? xo[2] : nullptr;
-#define YP_GP(PUSH, ND)                                                                                       \
-  hipLaunchKernelGGL((gather_push_kernel<T, PUSH, ND>), grid, dim3(bs), 0, s, (const T*)E[0], (const T*)E[1], \
-                     (const T*)E[2], (const T*)B[0], (const T*)B[1], (const T*)B[2], m, p.x[0], p.x[1],       \
-                     p.x[2], p.u[0], p.u[1], p.u[2], p.np, qm, dt, o1, o2, o3)
+#define YP_GP1(PUSH, ND, ORD)                                                                                  \
+  hipLaunchKernelGGL((gather_push_kernel<T, PUSH, ND, ORD>), grid, dim3(bs), 0, s, (const T*)E[0],            \
+                     (const T*)E[1], (const T*)E[2], (const T*)B[0], (const T*)B[1], (const T*)B[2], m, p.x[0], \
+                     p.x[1], p.x[2], p.u[0], p.u[1], p.u[2], p.np, qm, dt, o1, o2, o3)
+#define YP_GP(PUSH, ND)            \
+  do {                             \
+    if (m.order == 2)              \
+      YP_GP1(PUSH, ND, 2);         \
+    else                           \
+      YP_GP1(PUSH, ND, 1);         \
+  } while (0)
   if (m.ndim == 3) {
     if (pusher == PIC_PUSH_BORIS) YP_GP(PIC_PUSH_BORIS, 3);
     else if (pusher == PIC_PUSH_HC) YP_GP(PIC_PUSH_HC, 3);
@@ -155,6 +163,7 @@ int run_gather_push(const Mesh& m, void* const E[3], void* const B[3], const pic
     else YP_GP(PIC_PUSH_ANALYTIC, 2);
   }
 #undef YP_GP
+#undef YP_GP1
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "gather_push launch failed");
 }
 
@@ -165,12 +174,17 @@ int run_deposit(const Mesh& m, void* const J[3], const pic_particles& p, double*
   const int bs = 256;
   const dim3 grid((unsigned)((p.np + bs - 1) / bs));
   const double qw = p.q * p.w;
-  if (m.ndim == 3)
-    hipLaunchKernelGGL((deposit_kernel<T, 3>), grid, dim3(bs), 0, s, (T*)J[0], (T*)J[1], (T*)J[2], m, p.x[0],
-                       p.x[1], p.x[2], xo[0], xo[1], xo[2], p.u[0], p.u[1], p.u[2], p.np, qw, dt);
-  else
-    hipLaunchKernelGGL((deposit_kernel<T, 2>), grid, dim3(bs), 0, s, (T*)J[0], (T*)J[1], (T*)J[2], m, p.x[0],
-                       p.x[1], nullptr, xo[0], xo[1], nullptr, p.u[0], p.u[1], p.u[2], p.np, qw, dt);
+#define YP_DEP(ND, ORD, X3, XO3)                                                                                 \
+  hipLaunchKernelGGL((deposit_kernel<T, ND, ORD>), grid, dim3(bs), 0, s, (T*)J[0], (T*)J[1], (T*)J[2], m, p.x[0], \
+                     p.x[1], X3, xo[0], xo[1], XO3, p.u[0], p.u[1], p.u[2], p.np, qw, dt)
+  if (m.ndim == 3) {
+    if (m.order == 2) YP_DEP(3, 2, p.x[2], xo[2]);
+    else YP_DEP(3, 1, p.x[2], xo[2]);
+  } else {
+    if (m.order == 2) YP_DEP(2, 2, p.x[2], nullptr);
+    else YP_DEP(2, 1, p.x[2], nullptr);
+  }
+#undef YP_DEP
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "deposit launch failed");
 }
 

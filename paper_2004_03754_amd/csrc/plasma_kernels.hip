@@ -168,7 +168,7 @@ __device__ __forceinline__ void lds_add(unsigned long long* p, double v, double 
   atomicAdd(p, (unsigned long long)llrint(v * scale));
 }
 
-template <typename T, int PUSH>
+template <typename T, int PUSH, int ORDER>
 __global__ __launch_bounds__(256) void tile_push_kernel(
     const T* __restrict__ E1, const T* __restrict__ E2, const T* __restrict__ E3, const T* __restrict__ B1,
     const T* __restrict__ B2, const T* __restrict__ B3, T* __restrict__ J1, T* __restrict__ J2, T* __restrict__ J3,
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(256) void tile_push_kernel(
     const double x[3] = {sx1[i], sx2[i], sx3[i]};
     double u[3] = {su1[i], su2[i], su3[i]};
     double E[3], B[3];
-    gather6<T, 3>(E1, E2, E3, B1, B2, B3, m, x, E, B);
+    gather_o<T, 3, ORDER>(E1, E2, E3, B1, B2, B3, m, x, E, B);
     if (PUSH == PIC_PUSH_BORIS)
       boris(u, E, B, qm, dt);
     else if (PUSH == PIC_PUSH_HC)
@@ -206,6 +206,7 @@ __global__ __launch_bounds__(256) void tile_push_kernel(
     const double ig = dt / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     const double xn[3] = {wrap_pos(x[0] + ig * u[0], m.L1), wrap_pos(x[1] + ig * u[1], m.L2),
                           wrap_pos(x[2] + ig * u[2], m.L3)};
+    constexpr int K = ORDER + 2;  // stencil nodes per direction
     dx1[i] = xn[0];
     dx2[i] = xn[1];
     dx3[i] = xn[2];
@@ -213,8 +214,8 @@ __global__ __launch_bounds__(256) void tile_push_kernel(
     du2[i] = u[1];
     du3[i] = u[2];
     if (sid && sid != did) did[i] = sid[i];
-    const Shape3 sh[3] = {shape3(x[0], xn[0], m.idx1, m.L1), shape3(x[1], xn[1], m.idx2, m.L2),
-                          shape3(x[2], xn[2], m.idx3, m.L3)};
+    const ShapeK<K> sh[3] = {shape_o<ORDER>(x[0], xn[0], m.idx1, m.L1), shape_o<ORDER>(x[1], xn[1], m.idx2, m.L2),
+                             shape_o<ORDER>(x[2], xn[2], m.idx3, m.L3)};
     // stencil origin relative to the LDS current tile (periodic images folded in)
     int rel[3];
     bool inside = true;
@@ -224,20 +225,20 @@ __global__ __launch_bounds__(256) void tile_push_kernel(
       if (bb < -(n[d] / 2)) bb += n[d];
       if (bb > n[d] / 2) bb -= n[d];
       rel[d] = bb + tg.m[d] + 1;
-      inside = inside && rel[d] >= 0 && rel[d] + 2 < tg.r[d];
+      inside = inside && rel[d] >= 0 && rel[d] + K - 1 < tg.r[d];
     }
     if (inside) {
       const int o = (rel[2] * r1 + rel[1]) * r0 + rel[0];
-      esirkepov3(sh[0], sh[1], sh[2], c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
+      esirkepov<K>(sh[0], sh[1], sh[2], c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
         lds_add(&jl[comp * R + o + (c * r1 + b) * r0 + a], v, scale);
       });
     } else {  // outside the on-chip tile (rare): global atomics, stencil nodes wrapped once
-      int gw[3][3];
+      int gw[3][K];
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) gw[d][k] = wrapn(sh[d].base + k, n[d]);
-      esirkepov3(sh[0], sh[1], sh[2], c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
+        for (int k = 0; k < K; ++k) gw[d][k] = wrapn(sh[d].base + k, n[d]);
+      esirkepov<K>(sh[0], sh[1], sh[2], c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
         const size_t gidx = (size_t)gw[2][c] * pl + (size_t)gw[1][b] * m.n1 + gw[0][a];
         atomic_add(&Jg[comp][gidx], v);
       });
@@ -265,9 +266,11 @@ int run_tile_push(const Mesh& m, const TileGeom& tg, void* const E[3], void* con
                   hipStream_t s) {
   const size_t lds = sizeof(unsigned long long) * 3 * (size_t)tg.r[0] * tg.r[1] * tg.r[2];
   if (lds > 160 * 1024) return set_error(PIC_EUNSUPPORTED, "plasma tile needs %zu bytes of LDS", lds);
-  auto k = pusher == PIC_PUSH_BORIS ? tile_push_kernel<T, PIC_PUSH_BORIS>
-            : pusher == PIC_PUSH_HC  ? tile_push_kernel<T, PIC_PUSH_HC>
-                                     : tile_push_kernel<T, PIC_PUSH_ANALYTIC>;
+  const bool q2 = m.order == 2;
+  auto k = pusher == PIC_PUSH_BORIS ? (q2 ? tile_push_kernel<T, PIC_PUSH_BORIS, 2> : tile_push_kernel<T, PIC_PUSH_BORIS, 1>)
+           : pusher == PIC_PUSH_HC  ? (q2 ? tile_push_kernel<T, PIC_PUSH_HC, 2> : tile_push_kernel<T, PIC_PUSH_HC, 1>)
+                                    : (q2 ? tile_push_kernel<T, PIC_PUSH_ANALYTIC, 2>
+                                          : tile_push_kernel<T, PIC_PUSH_ANALYTIC, 1>);
   if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return set_error(PIC_EHIP, "tile push: cannot reserve %zu bytes of LDS", lds);
   const double qm = src.q / src.m, qw = src.q * src.w;
@@ -275,8 +278,15 @@ int run_tile_push(const Mesh& m, const TileGeom& tg, void* const E[3], void* con
   const double cmax = std::fabs(qw) * std::fmax(m.dx1, std::fmax(m.dx2, m.dx3)) / dt;
   const int S = cmax > 0 ? 47 - (int)std::ceil(std::log2(cmax)) : 0;
   const double scale = std::ldexp(1.0, S), unscale = std::ldexp(1.0, -S);
-#define YP_TP(PUSH)                                                                                               \
-  hipLaunchKernelGGL((tile_push_kernel<T, PUSH>), dim3(tg.ntiles), dim3(256), lds, s, (const T*)E[0],          \
+#define YP_TP(PUSH)   \
+  do {                \
+    if (q2)           \
+      YP_TP1(PUSH, 2); \
+    else              \
+      YP_TP1(PUSH, 1); \
+  } while (0)
+#define YP_TP1(PUSH, ORD)                                                                                         \
+  hipLaunchKernelGGL((tile_push_kernel<T, PUSH, ORD>), dim3(tg.ntiles), dim3(256), lds, s, (const T*)E[0],     \
                      (const T*)E[1], (const T*)E[2], (const T*)B[0], (const T*)B[1], (const T*)B[2], (T*)J[0],  \
                      (T*)J[1], (T*)J[2], m, tg, offsets, src.x[0], src.x[1], src.x[2], src.u[0], src.u[1],     \
                      src.u[2], src.id, dst.x[0], dst.x[1], dst.x[2], dst.u[0], dst.u[1], dst.u[2], dst.id, qm, qw, \
@@ -285,6 +295,7 @@ int run_tile_push(const Mesh& m, const TileGeom& tg, void* const E[3], void* con
   else if (pusher == PIC_PUSH_HC) YP_TP(PIC_PUSH_HC);
   else YP_TP(PIC_PUSH_ANALYTIC);
 #undef YP_TP
+#undef YP_TP1
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "tile push launch failed");
 }
 
@@ -301,7 +312,10 @@ TileGeom make_tile_geom(const Mesh& m, double dt, int sort_every) {
     // |v| < 1: at most (S-1) dt/dx cells of drift before the next sort
     tg.m[d] = (int)std::ceil((sort_every - 1) * dt / dx[d] - 1e-12);
     if (tg.m[d] < 0) tg.m[d] = 0;
-    tg.r[d] = tg.t[d] + 2 * tg.m[d] + 3;
+    // LDS current nodes: the tile, the drift margin each side, and the
+    // deposit stencil (3 nodes from min(floor) for the linear shape, 4 from
+    // min(round) - 1 for the quadratic one), origin m + 1 nodes below the tile
+    tg.r[d] = tg.t[d] + 2 * tg.m[d] + 2 + (m.order == 2 ? 2 : 1);
     tg.ntiles *= tg.nt[d];
   }
   return tg;

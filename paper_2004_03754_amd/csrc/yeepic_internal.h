@@ -19,6 +19,7 @@ int round_width(int m);
 struct Mesh {
   int n1, n2, n3;
   int ndim;
+  int order;  // particle shape: 1 linear, 2 quadratic B-spline
   double dx1, dx2, dx3;
   double idx1, idx2, idx3;  // 1/dx: positions become cell coordinates by a multiply
   double L1, L2, L3;
