@@ -177,13 +177,14 @@ def run_plane_wave(torch, b, wl, CE, CB, steps):
     return out
 
 
-def run_plasma(torch, b, wl, CE, CB, steps, dt=None):
+def run_plasma(torch, b, wl, CE, CB, steps, dt=None, order=1):
     """Plasma workload: 512 x 256 x 256 cells, electrons at n = 0.01 n_c with
     8 per cell (268,435,456), u_th = 0.01, Gaussian laser a0 = 10, w0 = 4
     lambda0; Boris pusher, Esirkepov deposit; FP32 fields, FP64 particles.
     ``dt`` defaults to dx1/2; at dt = dx1/4 the proposed solver's Ampere
     stencil is wide, so each step also runs the x1 current correction, which
-    is then timed alone as well."""
+    is then timed alone as well.  ``order`` 2 runs the quadratic particle
+    shape (the Sec. 4.2 run's)."""
     dt = wl.DT if dt is None else dt
     dx = (wl.DX1, wl.DX2, wl.DX3)
     n = (512, 256, 256)
@@ -194,6 +195,7 @@ def run_plasma(torch, b, wl, CE, CB, steps, dt=None):
     xd, ud = _device_plasma(n, dx, 2, 0.01, 3, torch)
     npart = xd.shape[1]
     grid = b.Grid(E, B, dx, dt, CE, CB, J=J, prec="fp32")
+    grid.set_shape(order)
     p = b.Particles(xd, ud, q=-1.0, m=1.0, w=0.01 / 8)
     grid.step_n([p], 2, pusher="boris", deposit=True)
     torch.cuda.synchronize()
@@ -383,6 +385,8 @@ def main():
                     help="steps of the differentiated 2D batch run (checkpoint every 64)")
     ap.add_argument("--adjoint-only", action="store_true", help="run only the adjoint workload")
     ap.add_argument("--plasma-only", action="store_true", help="run only the plasma workload")
+    ap.add_argument("--plasma-quadratic-only", action="store_true",
+                    help="run only the plasma workload with the quadratic particle shape")
     ap.add_argument("--plasma-quarter-only", action="store_true",
                     help="run only the plasma workload at dt = dx1/4 (wide Ampere stencil, current correction)")
     ap.add_argument("--plasma-steps", type=int, default=10, help="timed steps of the plasma workload")
@@ -414,6 +418,10 @@ def main():
         return
     if args.plasma_only:
         print(json.dumps({"plasma_512x256x256": run_plasma(torch, b, wl, CE, CB, steps=args.plasma_steps)}))
+        return
+    if args.plasma_quadratic_only:
+        print(json.dumps({"plasma_512x256x256_quadratic": run_plasma(torch, b, wl, CE, CB, args.plasma_steps,
+                                                                      order=2)}))
         return
     if args.plasma_quarter_only:
         print(json.dumps({"plasma_512x256x256_dt_quarter": run_plasma_quarter(torch, b, wl, args.plasma_steps)}))
@@ -475,6 +483,7 @@ def main():
         res["plane_wave_2048x512x512"] = run_plane_wave(torch, b, wl, CE, CB, steps=20)
         res["plasma_512x256x256"] = run_plasma(torch, b, wl, CE, CB, steps=args.plasma_steps)
         res["plasma_512x256x256_dt_quarter"] = run_plasma_quarter(torch, b, wl, args.plasma_steps)
+        res["plasma_512x256x256_quadratic"] = run_plasma(torch, b, wl, CE, CB, args.plasma_steps, order=2)
         res["adjoint_2d_2048x256_x16"] = run_adjoint(torch, b, wl, CE, CB, steps=args.adjoint_steps)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline()
