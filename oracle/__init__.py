@@ -23,8 +23,9 @@ particles   staggered linear-shape gather (App. A), Boris pusher, exact
 current     x1 current correction for a wide Ampere stencil (Sec. 3.3)
 pic         the per-step driver: push, deposit, current correction, fused
             field sweep
-trajectory  closed-form electron trajectory in a plane wave (Sec. 4.1,
-            canonical momentum conservation)
+trajectory  closed-form electron trajectory in a plane wave, from rest or
+            drifting (Sec. 4.1, canonical momentum conservation)
+window      moving window along x1 (Sec. 4.1 single-particle runs)
 adjoint     FP64 adjoint of the field sweep, gather and pushers
 
 Every function names the passage of the paper it follows.  Readings of

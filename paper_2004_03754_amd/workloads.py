@@ -70,6 +70,38 @@ class PlaneWave:
         return self.a0 * np.cos(np.asarray(s, dtype=np.float64))
 
 
+@dataclass
+class FlatTopPulse:
+    """Plane-wave pulse with a flat top (the single-particle runs of Sec. 4.1):
+    a(s) = a0 env(s) sin(s - R), env = 1 on the flat top R <= s <= R + Lf,
+    exp(-((R - s)/sigma)^4) before it and exp(-((s - R - Lf)/sigma)^4) after
+    it, and a = 0 outside 0 <= s <= 2R + Lf.  Inside the flat top the vector
+    potential vanishes at s = R + m pi, where E2 = -a' is extremal."""
+    a0: float
+    Lf: float = 100.0
+    sigma: float = 10.0
+    R: float = 30.0
+
+    def _env(self, s):
+        lo = (self.R - s) / self.sigma
+        hi = (s - self.R - self.Lf) / self.sigma
+        env = np.where(s < self.R, np.exp(-lo ** 4), np.where(s > self.R + self.Lf, np.exp(-hi ** 4), 1.0))
+        denv = np.where(s < self.R, 4 * lo ** 3 / self.sigma * np.exp(-lo ** 4),
+                        np.where(s > self.R + self.Lf, -4 * hi ** 3 / self.sigma * np.exp(-hi ** 4), 0.0))
+        inside = (s >= 0) & (s <= 2 * self.R + self.Lf)
+        return np.where(inside, env, 0.0), np.where(inside, denv, 0.0)
+
+    def a(self, s):
+        s = np.asarray(s, dtype=np.float64)
+        env, _ = self._env(s)
+        return self.a0 * env * np.sin(s - self.R)
+
+    def da(self, s):
+        s = np.asarray(s, dtype=np.float64)
+        env, denv = self._env(s)
+        return self.a0 * (denv * np.sin(s - self.R) + env * np.cos(s - self.R))
+
+
 def laser_profiles(n, dx, pulse, x_head=0.0, w0=None, centre=None):
     """Factors of the t = 0 laser fields: E2 = e2[i] prof[k, j] and
     B3 = b3[i] prof[k, j], with e2 = b3 = -a'(x_head - x1) sampled at the E2
