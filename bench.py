@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import subprocess
 import sys
@@ -250,6 +251,69 @@ def run_plasma_quarter(torch, b, wl, steps):
     return run_plasma(torch, b, wl, CE, CB, steps, dt=wl.DX1 / 4)
 
 
+def run_window(torch, b, wl, suite_steps=20000, moves=20):
+    """Moving window along x1 (Sec. 4.1).  (1) The single-particle run: 2D
+    window of 1024 x 4 cells, dx1 = 0.2, dx2 = 20, dt = 0.05 (r = 1/4), the
+    proposed solver fitted for r = 1/4, flat-top plane wave a0 = 0.5, one
+    electron drifting with gamma0 = 20, Higuera-Cary pusher, the window moving
+    one cell every 4 steps (at c) with the electron passed to every move.
+    (2) One-cell moves on the headline mesh (1024 x 256 x 256 FP64) with its
+    1,048,576 electrons passed (count, scan and a host sync; nobody leaves)
+    and without particles (the column clearing alone)."""
+    dx1, dx2, dt = 0.2, 20.0, 0.05
+    dx = (dx1, dx2, dx2)
+    CE = b.design_coeffs(16, dt / dx1, "E")
+    CB = b.design_coeffs(16, dt / dx1, "B")
+    pulse = wl.FlatTopPulse(0.5)
+    E, B = wl.laser_fields((1024, 4, 1), dx, pulse, x_head=180.0)
+    Ed = [torch.as_tensor(e, device="cuda:0").contiguous() for e in E]
+    Bd = [torch.as_tensor(v, device="cuda:0").contiguous() for v in B]
+    grid = b.Grid(Ed, Bd, dx, dt, CE, CB, ndim=2)
+    x = torch.tensor([[180.0 - (pulse.R + 16 * math.pi)], [0.5 * dx2], [0.0]], dtype=torch.float64,
+                     device="cuda:0")
+    u = torch.tensor([[math.sqrt(20.0 ** 2 - 1)], [0.0], [0.0]], dtype=torch.float64, device="cuda:0")
+    p = b.Particles(x, u)
+    for _ in range(25):
+        grid.step_n([p], 4, pusher="hc")
+        grid.move_window(1, [p])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(suite_steps // 4):
+        grid.step_n([p], 4, pusher="hc")
+        grid.move_window(1, [p])
+    torch.cuda.synchronize()
+    ms_suite = (time.perf_counter() - t0) * 1e3 / suite_steps
+    grid.close()
+    # one-cell moves on the headline mesh
+    n = (1024, 256, 256)
+    z = [torch.zeros((n[2], n[1], n[0]), dtype=torch.float64, device="cuda:0") for _ in range(6)]
+    L = wl.LAMBDA0
+    xs, us = wl.uniform_particles(1 << 20, [13 * L, 0.0, 0.0], [15 * L, n[1] * wl.DX2, n[2] * wl.DX3], seed=2)
+    ph = b.Particles(torch.as_tensor(xs, device="cuda:0").contiguous(),
+                     torch.as_tensor(us, device="cuda:0").contiguous())
+    grid = b.Grid(z[:3], z[3:], (wl.DX1, wl.DX2, wl.DX3), wl.DT, [1.0], [1.0])
+    grid.move_window(1, [ph])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(moves):
+        grid.move_window(1, [ph])
+    torch.cuda.synchronize()
+    ms_move_p = (time.perf_counter() - t0) * 1e3 / moves
+    e0, e1 = _events(torch)
+    e0.record()
+    for _ in range(moves):
+        grid.move_window(1, [])
+    e1.record()
+    torch.cuda.synchronize()
+    ms_move = e0.elapsed_time(e1) / moves
+    grid.close()
+    del z, ph
+    torch.cuda.empty_cache()
+    return {"suite_2d_1024x4_ms_per_step": ms_suite, "suite_steps": suite_steps,
+            "headline_move_with_1M_electrons_ms": ms_move_p, "headline_move_fields_only_ms": ms_move,
+            "survivors": int(p.np)}
+
+
 def run_adjoint(torch, b, wl, CE, CB, steps, K=64):
     """Adjoint workload: a batch of 16 2D meshes of 2048 x 256 cells (stacked
     planes of one grid), one sin^2 envelope per plane with a0 = 10^U(0,3)
@@ -389,6 +453,8 @@ def main():
                     help="run only the plasma workload with the quadratic particle shape")
     ap.add_argument("--plasma-quarter-only", action="store_true",
                     help="run only the plasma workload at dt = dx1/4 (wide Ampere stencil, current correction)")
+    ap.add_argument("--window-only", action="store_true",
+                    help="run only the moving-window measurements (Sec. 4.1 single-particle run)")
     ap.add_argument("--plasma-steps", type=int, default=10, help="timed steps of the plasma workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter calibration)")
@@ -422,6 +488,9 @@ def main():
     if args.plasma_quadratic_only:
         print(json.dumps({"plasma_512x256x256_quadratic": run_plasma(torch, b, wl, CE, CB, args.plasma_steps,
                                                                       order=2)}))
+        return
+    if args.window_only:
+        print(json.dumps({"moving_window": run_window(torch, b, wl)}))
         return
     if args.plasma_quarter_only:
         print(json.dumps({"plasma_512x256x256_dt_quarter": run_plasma_quarter(torch, b, wl, args.plasma_steps)}))
@@ -485,6 +554,7 @@ def main():
         res["plasma_512x256x256_dt_quarter"] = run_plasma_quarter(torch, b, wl, args.plasma_steps)
         res["plasma_512x256x256_quadratic"] = run_plasma(torch, b, wl, CE, CB, args.plasma_steps, order=2)
         res["adjoint_2d_2048x256_x16"] = run_adjoint(torch, b, wl, CE, CB, steps=args.adjoint_steps)
+        res["moving_window"] = run_window(torch, b, wl)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res))

@@ -240,6 +240,28 @@ int pic_step_to(pic_grid *g, pic_particles *const *species, int nspecies, int pu
  * on-chip current tile grows with the interval (|v| < c bounds the drift). */
 int pic_set_sort_interval(pic_grid *g, int steps);
 
+/* ---- moving window along x1 (Sec. 4.1, the single-particle runs) -----------
+ * Moves the window forward (+x1) by ``cells`` whole cells, 0 <= cells < n1
+ * (PIC_EINVAL otherwise; 0 does nothing).  The field arrays are a ring along
+ * the periodic x1 axis: array column (origin + i) mod n1 holds window cell i,
+ * origin starting at 0.  A move clears E and B (and J when attached) in the
+ * columns of window cells 0 .. cells-1, which then become the window's last
+ * cells (vacuum entering at the front), and adds ``cells`` to the origin; no
+ * other field value moves.  Particles keep their (ring) coordinates: window
+ * coordinate = (x1 - origin dx1) mod L1, lab coordinate = moved dx1 + window
+ * coordinate.  Particles of the given species whose cell column
+ * floor(x1/dx1) is one of the cleared columns leave the run: the others are
+ * compacted to the front of the caller's arrays in their order (x, u, id
+ * together) and species[s]->np is set to their number.  With particles given
+ * the call synchronises the stream (the count is needed on the host) and
+ * keeps grow-only scratch of 56 bytes per particle; without species it only
+ * queues the clearing kernel.  Every other call sees the ring as the periodic
+ * mesh it is, so a run with moves equals the run on a physically shifted
+ * mesh.  No new plasma is injected at the front. */
+int pic_move_window(pic_grid *g, int64_t cells, pic_particles *const *species, int nspecies);
+/* The window's ring origin (0 <= origin < n1) and the cells moved so far. */
+int pic_window(const pic_grid *g, int64_t *origin, int64_t *moved);
+
 /* ---- adjoint of one vacuum step ---------------------------------------------
  * Reverse mode of one step of pic_step_n without deposit, with the Boris or
  * the exact pusher: gather (App. A) + push (Sec. 1) + position update (Sec. 4.1) of

@@ -53,7 +53,7 @@ class _Adjoint(ctypes.Structure):
 EXPORTS = ["pic_design_coeffs", "pic_init_grid", "pic_set_fields", "pic_advance_B_half", "pic_advance_E",
            "pic_field_sweep", "pic_gather_push", "pic_deposit_J", "pic_step_n", "pic_sync", "pic_check",
            "pic_grid_widths", "pic_destroy", "pic_last_error", "pic_set_sort_interval", "pic_adjoint_step", "pic_step_to",
-           "pic_current_correction", "pic_set_shape"]
+           "pic_current_correction", "pic_set_shape", "pic_move_window", "pic_window"]
 
 
 def lib():
@@ -78,6 +78,8 @@ def lib():
         L.pic_set_sort_interval.argtypes = [vp, i]
         L.pic_set_shape.argtypes = [vp, i]
         PP = ctypes.POINTER(ctypes.POINTER(_Particles))
+        L.pic_move_window.argtypes = [vp, ctypes.c_int64, PP, i]
+        L.pic_window.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.pic_adjoint_step.argtypes = [vp, ctypes.POINTER(_Adjoint), PP, PP, i, i]
         L.pic_step_to.argtypes = [vp, PP, i, i, ctypes.c_void_p * 3, ctypes.c_void_p * 3, ctypes.c_void_p]
         L.pic_sync.argtypes = [vp]
@@ -139,7 +141,14 @@ class Particles:
 
     @property
     def np(self):
-        return self.x.shape[1]
+        """Particles in the run: the leading np entries of each row of x, u
+        (and of id); a window move that drops particles lowers it."""
+        return int(self._s.np)
+
+    def live(self):
+        """Views (x, u, id) of the np particles in the run."""
+        n = self.np
+        return self.x[:, :n], self.u[:, :n], (self.id[:n] if self.id is not None else None)
 
 
 class Grid:
@@ -268,6 +277,21 @@ class Grid:
     def set_shape(self, order):
         """Particle shape of gather and deposit: 1 linear, 2 quadratic."""
         _check(lib().pic_set_shape(self._h, int(order)))
+
+    def move_window(self, cells, species=()):
+        """Move the x1 window forward by ``cells`` (pic_move_window): the
+        field arrays stay a ring (see ``window``); particles of ``species`` in
+        the columns left behind are dropped and each species' np updated."""
+        arr = (ctypes.POINTER(_Particles) * max(1, len(species)))()
+        for s_, p in enumerate(species):
+            arr[s_] = ctypes.pointer(p._s)
+        _check(lib().pic_move_window(self._h, int(cells), arr, len(species)))
+
+    def window(self):
+        """(origin, moved): array column of window cell 0, cells moved."""
+        o, m = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().pic_window(self._h, ctypes.byref(o), ctypes.byref(m)))
+        return o.value, m.value
 
     def set_sort_interval(self, steps):
         _check(lib().pic_set_sort_interval(self._h, int(steps)))

@@ -20,7 +20,8 @@ BUILD = os.path.join(PKG, "_build")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libyeepic.so")
 
-HIP_SOURCES = ["api.hip", "field_kernels.hip", "particle_kernels.hip", "plasma_kernels.hip", "adjoint_kernels.hip"]
+HIP_SOURCES = ["api.hip", "field_kernels.hip", "particle_kernels.hip", "plasma_kernels.hip", "adjoint_kernels.hip",
+               "window_kernels.hip"]
 CXX_SOURCES = ["coeff_fit.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = [

@@ -57,6 +57,14 @@ struct pic_grid {
   int corr_w = 0;          // last nonzero tap
   double* corr_taps = nullptr;
   void* Jc = nullptr;
+  // moving window: array column of window cell 0, cells moved so far, and
+  // the compaction scratch (grow-only)
+  int64_t win_origin = 0, win_moved = 0;
+  int* win_counts = nullptr;
+  int64_t* win_offs = nullptr;
+  int64_t win_nb_cap = 0;
+  double* win_data = nullptr;  // x[3], u[3], id: 7 arrays of win_cap
+  int64_t win_cap = 0;
   yeepic::Mesh mesh = {};
 };
 
@@ -765,6 +773,93 @@ int pic_check(pic_grid* g, const pic_particles* p) {
   return PIC_OK;
 }
 
+static int ensure_window_scratch(pic_grid* g, int64_t np) {
+  const int64_t nb = window_blocks(np);
+  if (nb > g->win_nb_cap) {
+    (void)hipStreamSynchronize(g->stream);
+    if (g->win_counts) (void)hipFree(g->win_counts);
+    if (g->win_offs) (void)hipFree(g->win_offs);
+    g->win_counts = nullptr;
+    g->win_offs = nullptr;
+    g->win_nb_cap = 0;
+    if (hipMalloc((void**)&g->win_counts, (size_t)nb * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&g->win_offs, ((size_t)nb + 1) * sizeof(int64_t)) != hipSuccess)
+      return set_error(PIC_ENOMEM, "cannot allocate the window compaction counters");
+    g->win_nb_cap = nb;
+  }
+  if (np > g->win_cap) {
+    (void)hipStreamSynchronize(g->stream);
+    if (g->win_data) (void)hipFree(g->win_data);
+    g->win_data = nullptr;
+    g->win_cap = 0;
+    if (hipMalloc((void**)&g->win_data, (size_t)np * 7 * sizeof(double)) != hipSuccess)
+      return set_error(PIC_ENOMEM, "cannot allocate %lld particles of window scratch", (long long)np);
+    g->win_cap = np;
+  }
+  return PIC_OK;
+}
+
+int pic_move_window(pic_grid* g, int64_t cells, pic_particles* const* species, int nspecies) {
+  if (!g) return set_error(PIC_EINVAL, "grid is NULL");
+  if (cells < 0 || cells >= g->n[0]) return set_error(PIC_EINVAL, "a window move needs 0 <= cells < n1");
+  if (nspecies < 0 || (nspecies > 0 && !species)) return set_error(PIC_EINVAL, "bad species list");
+  for (int s = 0; s < nspecies; ++s) {
+    int rc = check_particles(g, species[s]);
+    if (rc) return rc;
+  }
+  if (cells == 0) return PIC_OK;
+  void* arrays[9];
+  int na = 0;
+  for (int c = 0; c < 3; ++c) arrays[na++] = g->E[c];
+  for (int c = 0; c < 3; ++c) arrays[na++] = g->B[c];
+  if (g->J[0] && g->J[1] && g->J[2])
+    for (int c = 0; c < 3; ++c) arrays[na++] = g->J[c];
+  const int64_t o = g->win_origin;
+  int rc = launch_zero_columns(g->prec, g->mesh, arrays, na, o, cells, g->stream);
+  if (rc) return rc;
+  for (int s = 0; s < nspecies; ++s) {
+    pic_particles* p = species[s];
+    if (p->np == 0) continue;
+    rc = ensure_window_scratch(g, p->np);
+    if (rc) return rc;
+    rc = launch_window_count(g->mesh, *p, o, cells, g->win_counts, g->win_offs, g->stream);
+    if (rc) return rc;
+    int64_t total = 0;
+    hipError_t e = hipMemcpyAsync(&total, g->win_offs + window_blocks(p->np), sizeof(int64_t),
+                                  hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(e, "window survivor count");
+    if (total == p->np) continue;
+    pic_particles dst = *p;
+    const int64_t cap = g->win_cap;
+    for (int d = 0; d < 3; ++d) {
+      dst.x[d] = g->win_data + d * cap;
+      dst.u[d] = g->win_data + (3 + d) * cap;
+    }
+    dst.id = reinterpret_cast<int64_t*>(g->win_data + 6 * cap);
+    rc = launch_window_scatter(g->mesh, *p, dst, o, cells, g->win_offs, g->stream);
+    if (rc) return rc;
+    const size_t bytes = (size_t)total * sizeof(double);
+    for (int d = 0; d < 3 && e == hipSuccess; ++d) {
+      if (p->x[d]) e = hipMemcpyAsync(p->x[d], dst.x[d], bytes, hipMemcpyDeviceToDevice, g->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(p->u[d], dst.u[d], bytes, hipMemcpyDeviceToDevice, g->stream);
+    }
+    if (e == hipSuccess && p->id) e = hipMemcpyAsync(p->id, dst.id, bytes, hipMemcpyDeviceToDevice, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "window compaction copy");
+    p->np = total;
+  }
+  g->win_origin = (o + cells) % g->n[0];
+  g->win_moved += cells;
+  return PIC_OK;
+}
+
+int pic_window(const pic_grid* g, int64_t* origin, int64_t* moved) {
+  if (!g || !origin || !moved) return set_error(PIC_EINVAL, "pic_window: NULL argument");
+  *origin = g->win_origin;
+  *moved = g->win_moved;
+  return PIC_OK;
+}
+
 void pic_destroy(pic_grid* g) {
   if (!g) return;
   (void)hipStreamSynchronize(g->stream);
@@ -779,6 +874,9 @@ void pic_destroy(pic_grid* g) {
   if (g->partial) (void)hipFree(g->partial);
   if (g->corr_taps) (void)hipFree(g->corr_taps);
   if (g->Jc) (void)hipFree(g->Jc);
+  if (g->win_counts) (void)hipFree(g->win_counts);
+  if (g->win_offs) (void)hipFree(g->win_offs);
+  if (g->win_data) (void)hipFree(g->win_data);
   delete g;
 }
 

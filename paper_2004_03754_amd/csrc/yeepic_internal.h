@@ -85,6 +85,19 @@ int launch_coef_grad(const Mesh& m, int form, const double* la, const double* fa
 int launch_adjoint_push(const Mesh& m, void* const E[3], void* const B[3], void* const lE[3], void* const lB[3],
                         const pic_particles& p, const pic_particles& lam, int pusher, double dt, void* stream);
 
+// Moving window (window_kernels.hip).  launch_zero_columns clears columns
+// [c0, c0 + s) mod n1 of every row of ``narrays`` (<= 9) field arrays;
+// launch_window_count writes per-block survivor counts (window_blocks(np)
+// ints) and their exclusive scan offs[0..nb] (offs[nb] = survivors) for a
+// move of s columns from ring origin ``origin``; launch_window_scatter copies
+// the survivors of src, in order, to dst[0 .. offs[nb]).
+int launch_zero_columns(int prec, const Mesh& m, void* const* arrays, int narrays, int64_t c0, int64_t s,
+                        void* stream);
+int64_t window_blocks(int64_t np);
+int launch_window_count(const Mesh& m, const pic_particles& p, int64_t origin, int64_t s, int* counts,
+                        int64_t* offs, void* stream);
+int launch_window_scatter(const Mesh& m, const pic_particles& src, const pic_particles& dst, int64_t origin,
+                          int64_t s, const int64_t* offs, void* stream);
 int launch_check(int prec, const Mesh& m, void* const E[3], void* const B[3],
                  const pic_particles* p, int* d_flag, void* stream);
 

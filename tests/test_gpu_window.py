@@ -1,0 +1,255 @@
+"""GPU parity of the moving window along x1 (Sec. 4.1 single-particle runs):
+pic_move_window against the oracle's physically shifted window (fields
+bit-exact after undoing the ring origin, the same particles leaving, in the
+same order), runs with steps and moves against the oracle, and the gamma0 = 20
+drift of Sec. 4.1 over a long run against the closed-form trajectory."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import pic, trajectory, window  # noqa: E402
+from paper_2004_03754_amd import binding as b, workloads as wl  # noqa: E402
+
+torch = pytest.importorskip("torch")
+from gpu_util import dev, host  # noqa: E402
+
+# Sec. 4.1 grid: dt = 0.05, dx1 = 0.2 (r = 1/4), dx2 = 20
+DX1, DX2, DT = 0.2, 20.0, 0.05
+DX = (DX1, DX2, DX2)
+GAMMA0 = 20.0
+X_HEAD = 180.0
+
+
+def _species(n, seed, npart):
+    g = wl.rng(seed)
+    n1, n2, n3 = n
+    cell = g.integers(0, n1, npart)
+    frac = 0.05 + 0.9 * g.random(npart)  # away from cell faces
+    x = np.stack([(cell + frac) * DX1, n2 * DX2 * g.random(npart), n3 * DX2 * g.random(npart)])
+    u = g.standard_normal((3, npart))
+    return x, u
+
+
+def _ring_to_window(f, origin):
+    return np.roll(f, -origin, axis=-1)
+
+
+def _window_x1(x1, origin, L1):
+    return np.mod(x1 - origin * DX1, L1)
+
+
+@pytest.mark.parametrize("n,ndim", [((192, 5, 1), 2), ((128, 6, 3), 3)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_moves_match_oracle(n, ndim, prec):
+    """A sequence of moves (37, 1, 0, 90, n1 - 1 cells) with J attached: the
+    fields seen through the ring origin equal the oracle's shifted fields
+    exactly, and the same particles are left, in the same order."""
+    n1, n2, n3 = n
+    dt_ = torch.float64 if prec == "fp64" else torch.float32
+    E, B = wl.random_fields(n, seed=81)
+    J = list(wl.random_fields(n, seed=82)[0])
+    Ed, Bd, Jd = [dev(e, dt_) for e in E], [dev(x, dt_) for x in B], [dev(j, dt_) for j in J]
+    # the oracle starts from exactly the values the GPU holds
+    E, B, J = [host(e) for e in Ed], [host(x) for x in Bd], [host(j) for j in Jd]
+    x, u = _species(n, 83, 2500)
+    ids = np.arange(x.shape[1], dtype=np.int64)
+    xd, ud, idd = dev(x), dev(u), dev(ids, torch.int64)
+    if ndim == 2:
+        xd[2].zero_()
+        x[2] = 0.0
+    c = np.zeros(1)
+    c[0] = 1.0
+    grid = b.Grid(Ed, Bd, DX, DT, c, c.copy(), J=Jd, prec=prec, ndim=ndim)
+    p = b.Particles(xd, ud, id=idd)
+    sp = dict(x=x.copy(), u=u.copy(), id=ids.copy(), q=-1.0, m=1.0, w=1.0)
+    L1 = n1 * DX1
+    for s in (37, 1, 0, 90, n1 - 1):
+        print(f"window move {prec} {n} by {s}", flush=True)
+        grid.move_window(s, [p])
+        grid.sync()
+        E, B, J = window.move(E, B, [sp], s, DX1, J=J)
+        origin, moved = grid.window()
+        assert origin == (moved % n1)
+        for got, ref in zip(Ed + Bd + Jd, E + B + J):
+            np.testing.assert_array_equal(_ring_to_window(host(got), origin), ref)
+        assert p.np == sp["id"].size
+        xg, ug, ig = (host(t) if t.dtype != torch.int64 else t.cpu().numpy() for t in p.live())
+        np.testing.assert_array_equal(ig, sp["id"])
+        np.testing.assert_allclose(_window_x1(xg[0], origin, L1), sp["x"][0], rtol=0, atol=1e-12 * L1)
+        np.testing.assert_array_equal(xg[1:], sp["x"][1:])
+        np.testing.assert_array_equal(ug, sp["u"])
+    assert p.np < 2500
+    grid.close()
+
+
+def test_move_edge_cases():
+    n = (128, 2, 1)
+    E, B = wl.random_fields(n, seed=84)
+    Ed, Bd = [dev(e) for e in E], [dev(x) for x in B]
+    c = np.zeros(1)
+    c[0] = 1.0
+    grid = b.Grid(Ed, Bd, DX, DT, c, c.copy(), ndim=2)
+    x = np.zeros((3, 300))
+    x[0] = (np.arange(300) % 10 + 0.5) * DX1  # every particle in columns 0..9
+    p = b.Particles(dev(x), dev(np.ones((3, 300))), id=dev(np.arange(300), torch.int64))
+    for bad in (-1, 128, 1000):
+        with pytest.raises(b.YeePICError):
+            grid.move_window(bad, [p])
+    print("window edge cases", flush=True)
+    grid.move_window(0, [p])
+    assert grid.window() == (0, 0) and p.np == 300
+    grid.move_window(5, [])  # fields only: particles untouched
+    assert grid.window() == (5, 5) and p.np == 300
+    grid.move_window(5, [p])  # columns 5..9: half of them leave
+    assert p.np == 150
+    np.testing.assert_array_equal(p.live()[2].cpu().numpy(), np.flatnonzero(np.arange(300) % 10 < 5))
+    grid.move_window(123, [p])  # columns 10..132 mod 128 = 0..4 as well: all leave
+    assert p.np == 0 and grid.window() == (5, 133)
+    grid.move_window(3, [p])  # an empty species is fine
+    assert p.np == 0
+    grid.sync()
+    # the vacated columns are zero, the rest untouched
+    o, _ = grid.window()
+    got = _ring_to_window(host(Ed[1]), o)
+    ref = window.shift_field(window.shift_field(window.shift_field(E[1], 10), 123), 3)
+    np.testing.assert_array_equal(got, ref)
+    grid.close()
+
+
+def test_compaction_many_blocks_bit_exact():
+    """1,000,003 particles (977 blocks, ragged tail): the survivors and their
+    order equal the column rule evaluated on the host in the same precision."""
+    n1 = 256
+    n = (n1, 8, 1)
+    E, B = wl.random_fields(n, seed=85)
+    c = np.zeros(1)
+    c[0] = 1.0
+    grid = b.Grid([dev(e) for e in E], [dev(x) for x in B], DX, DT, c, c.copy(), ndim=2)
+    g = wl.rng(86)
+    npart = 1_000_003
+    x = np.zeros((3, npart))
+    x[0] = g.random(npart) * n1 * DX1
+    x[1] = g.random(npart) * 8 * DX2
+    ids = np.arange(npart, dtype=np.int64)
+    p = b.Particles(dev(x), dev(g.standard_normal((3, npart))), id=dev(ids, torch.int64))
+    origin = 0
+    keep = np.ones(npart, dtype=bool)
+    for s in (1, 7, 200):
+        print(f"window compaction {npart} by {s}", flush=True)
+        grid.move_window(s, [p])
+        col = np.clip(np.floor(x[0] * (1.0 / DX1)), 0, n1 - 1).astype(np.int64)
+        keep &= np.mod(col - origin, n1) >= s
+        origin = (origin + s) % n1
+        assert p.np == int(keep.sum())
+        np.testing.assert_array_equal(p.live()[2].cpu().numpy(), ids[keep])
+        np.testing.assert_array_equal(host(p.live()[0]), x[:, keep])
+    grid.close()
+
+
+def _suite_fields(n1, n2, pulse):
+    return wl.laser_fields((n1, n2, 1), DX, pulse, x_head=X_HEAD)
+
+
+def test_window_run_matches_oracle(coeffs16_quarter):
+    """400 steps of the Sec. 4.1 configuration (proposed solver at r = 1/4,
+    Higuera-Cary pusher, window moving at c: one cell every 4 steps) with the
+    gamma0 = 20 electron and a few electrons at rest near the back edge, which
+    leave the window: fields through the ring origin and the particles still
+    inside agree with the oracle to 1e-12."""
+    CE, CB = coeffs16_quarter
+    n1, n2 = 1024, 4
+    pulse = wl.FlatTopPulse(0.5)
+    E, B = _suite_fields(n1, n2, pulse)
+    xp = X_HEAD - (pulse.R + 16 * np.pi)
+    x = np.zeros((3, 9))
+    x[0] = [xp, 0.13, 0.31, 0.52, 0.77, 1.11, 1.9, 4.3, 9.0]
+    x[1] = 0.5 * DX2
+    u = np.zeros((3, 9))
+    u[0, 0] = np.sqrt(GAMMA0 ** 2 - 1)
+    ids = np.arange(9, dtype=np.int64)
+    Ed, Bd = [dev(e) for e in E], [dev(v) for v in B]
+    grid = b.Grid(Ed, Bd, DX, DT, CE, CB, ndim=2)
+    p = b.Particles(dev(x), dev(u), id=dev(ids, torch.int64))
+    sp = dict(x=x.copy(), u=u.copy(), id=ids.copy(), q=-1.0, m=1.0, w=1.0)
+    moved = 0
+    nsteps = 400
+    print("window run 400 steps", flush=True)
+    for n in range(nsteps):
+        E, B = pic.step(E, B, [sp], CE, CB, DX, DT, pusher="hc", ndim=2)
+        due = window.cells_due(n + 1, DT, DX1)
+        if due > moved:
+            E, B = window.move(E, B, [sp], due - moved, DX1)
+            moved = due
+    for k in range(nsteps // 4):
+        grid.step_n([p], 4, pusher="hc")
+        grid.move_window(1, [p])
+    grid.sync()
+    origin, gmoved = grid.window()
+    assert gmoved == moved == 100
+    for got, ref in zip(Ed + Bd, E + B):
+        g_ = _ring_to_window(host(got), origin)
+        assert np.max(np.abs(g_ - ref)) <= 1e-12 * max(np.max(np.abs(r)) for r in E + B)
+    assert p.np == sp["id"].size and p.np < 9
+    xg, ug, ig = p.live()
+    np.testing.assert_array_equal(ig.cpu().numpy(), sp["id"])
+    L1 = n1 * DX1
+    np.testing.assert_allclose(_window_x1(host(xg)[0], origin, L1), sp["x"][0], rtol=0, atol=1e-12 * L1)
+    np.testing.assert_allclose(host(ug), sp["u"], rtol=0, atol=1e-12 * GAMMA0)
+    grid.close()
+
+
+def _suite_gpu(CE, CB, a0, nsteps, prec="fp64"):
+    n1, n2 = 1024, 4
+    pulse = wl.FlatTopPulse(a0)
+    E, B = _suite_fields(n1, n2, pulse)
+    dt_ = torch.float64 if prec == "fp64" else torch.float32
+    Ed, Bd = [dev(e, dt_) for e in E], [dev(v, dt_) for v in B]
+    grid = b.Grid(Ed, Bd, DX, DT, CE, CB, prec=prec, ndim=2)
+    xp = X_HEAD - (pulse.R + 16 * np.pi)
+    x = np.array([[xp], [0.5 * DX2], [0.0]])
+    u = np.array([[np.sqrt(GAMMA0 ** 2 - 1)], [0.0], [0.0]])
+    p = b.Particles(dev(x), dev(u))
+    for _ in range(nsteps // 4):
+        grid.step_n([p], 4, pusher="hc")
+        grid.move_window(1, [p])
+    grid.sync()
+    origin, moved = grid.window()
+    E2 = _ring_to_window(host(Ed[1]), origin)
+    x1 = host(p.x)[0, 0] - origin * DX1
+    x1 = x1 + n1 * DX1 if x1 < 0 else x1
+    out = dict(x1=moved * DX1 + x1, u=host(p.u)[:, 0], E2=E2, E2_0=E[1], xp=xp, pulse=pulse)
+    grid.close()
+    return out
+
+
+@pytest.mark.parametrize("a0", [0.5, 3.0])
+def test_single_particle_suite_long_run(a0, coeffs16_quarter):
+    """20,000 steps (t = 1000, 5,000 window moves) of the gamma0 = 20 drift:
+    the proposed solver follows the closed-form trajectory, the plane wave
+    keeps its shape in the window, and the Yee solver departs from both."""
+    CE, CB = coeffs16_quarter
+    nsteps = 20000
+    T = nsteps * DT
+    print(f"single-particle suite a0={a0}", flush=True)
+    r = _suite_gpu(CE, CB, a0, nsteps)
+    pulse = r["pulse"]
+    x0 = np.array([[r["xp"]], [0.0], [0.0]])
+    a = lambda s: pulse.a(X_HEAD + s)  # noqa: E731
+    x_th, _, _ = trajectory.state_at(a, -1.0, 0.0, x0, T, gamma0=GAMMA0)
+    _, u_th, _ = trajectory.state_at(a, -1.0, 0.0, x0, T - DT / 2, gamma0=GAMMA0)
+    err_u2 = abs(r["u"][1] - u_th[1, 0])
+    err_x1 = abs(r["x1"] - x_th[0, 0])
+    err_f = np.max(np.abs(r["E2"] - r["E2_0"])) / np.max(np.abs(r["E2_0"]))
+    print(f"proposed: u2 {r['u'][1]:.6f} theory {u_th[1, 0]:.6f} x1 err {err_x1:.2e} field err {err_f:.2e}")
+    assert err_u2 <= 5e-3 * a0
+    assert err_x1 <= 3e-6 * x_th[0, 0]
+    assert err_f <= 1e-5
+    yee = np.zeros(16)
+    yee[0] = 1.0
+    ry = _suite_gpu(yee, yee.copy(), a0, nsteps)
+    err_u2y = abs(ry["u"][1] - u_th[1, 0])
+    err_fy = np.max(np.abs(ry["E2"] - ry["E2_0"])) / np.max(np.abs(ry["E2_0"]))
+    print(f"yee: u2 {ry['u'][1]:.6f} field err {err_fy:.2e}")
+    assert err_u2y >= 10 * err_u2
+    assert err_fy >= 1e-1
