@@ -42,19 +42,16 @@ def _momenta(a, qm, psi0, s, h):
 
 
 def _integrals(a, qm, psi0, psi, panels, h=1.0):
-    """int_{psi0}^{psi} (gamma, u1, u2)/h dpsi' for arrays psi0, psi."""
-    step = (psi - psi0) / panels
-    tot = np.zeros((3,) + np.shape(psi))
-    for p in range(panels):
-        lo = psi0 + p * step
-        for xg, wg in zip(_GX, _GW):
-            s = lo + (xg + 1) * step / 2
-            u1, u2, g = _momenta(a, qm, psi0, s, h)
-            wt = wg * step / 2 / h
-            tot[0] += wt * g
-            tot[1] += wt * u1
-            tot[2] += wt * u2
-    return tot
+    """int_{psi0}^{psi} (gamma, u1, u2)/h dpsi' for 1-D arrays psi0, psi:
+    composite 16-point Gauss-Legendre over ``panels`` equal panels, with
+    every node evaluated in one call of ``a``."""
+    psi0 = np.atleast_1d(np.asarray(psi0, dtype=np.float64))
+    step = (np.atleast_1d(np.asarray(psi, dtype=np.float64)) - psi0) / panels
+    frac = np.arange(panels)[:, None] + (_GX[None, :] + 1) / 2  # (panels, 16)
+    s = psi0 + frac[..., None] * step  # (panels, 16, np)
+    u1, u2, g = _momenta(a, qm, psi0, s, h)
+    w = _GW[None, :, None] / 2
+    return np.stack([np.sum(w * q, axis=(0, 1)) for q in (g, u1, u2)]) * step / h
 
 
 def state_at(a, qm, t0, x0, t, max_iter=100, gamma0=None):
