@@ -467,8 +467,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 (the multi-GPU slab "
-              "decomposition is described in DESIGN.md but not built)", file=sys.stderr)
+        print("bench.py: the library runs on one GPU; --gpus must be 1 (no multi-GPU slab "
+              "decomposition is implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
