@@ -223,21 +223,15 @@ __device__ __forceinline__ ExpCoefD exp_coef_dual(Dual k2, Dual w2, Dual tau) {
     Dual h = {1.0, 0.0}, zk = {1.0, 0.0};
     Dual G[7];
     for (int m = 0; m < 7; ++m) G[m] = {0.0, 0.0};
-    double f2 = 1.0 / 2, f3 = 1.0 / 6, f4 = 1.0 / 24, f5 = 1.0 / 120, f6 = 1.0 / 720;
+#pragma unroll
     for (int k = 0; k < 14; ++k) {
-      G[2] = G[2] + f2 * h;
-      G[3] = G[3] + f3 * h;
-      G[4] = G[4] + f4 * h;
-      G[5] = G[5] + f5 * h;
-      G[6] = G[6] + f6 * h;
+      G[2] = G[2] + kInvFact.v[2 * k + 2] * h;
+      G[3] = G[3] + kInvFact.v[2 * k + 3] * h;
+      G[4] = G[4] + kInvFact.v[2 * k + 4] * h;
+      G[5] = G[5] + kInvFact.v[2 * k + 5] * h;
+      G[6] = G[6] + kInvFact.v[2 * k + 6] * h;
       zk = zk * Z;
       h = X * h + zk;
-      const double n2 = 2.0 * k + 2;
-      f2 /= (n2 + 1) * (n2 + 2);
-      f3 /= (n2 + 2) * (n2 + 3);
-      f4 /= (n2 + 3) * (n2 + 4);
-      f5 /= (n2 + 4) * (n2 + 5);
-      f6 /= (n2 + 5) * (n2 + 6);
     }
     const Dual XY = X * Y;
     e.a0 = XY * G[4] + 1.0;

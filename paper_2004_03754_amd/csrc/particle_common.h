@@ -137,6 +137,21 @@ struct ExpCoef {
   double a0, a1, a2, a3, A1, A3;  // A0 = a1, A2 = a3
 };
 
+// 1/n! for n = 0..32, evaluated at compile time: the series reads
+// 1/(2k + m)! for k < 14, m = 2..6 as constants (no divisions at run time).
+struct InvFact {
+  double v[33];
+  constexpr InvFact() : v() {
+    double f = 1.0;
+    v[0] = 1.0;
+    for (int n = 1; n < 33; ++n) {
+      f *= n;
+      v[n] = 1.0 / f;
+    }
+  }
+};
+__device__ constexpr InvFact kInvFact{};
+
 __device__ __forceinline__ ExpCoef exp_coef(double k2, double w2, double tau) {
   const double t2 = tau * tau;
   const double X = k2 * t2, Y = w2 * t2;
@@ -146,22 +161,15 @@ __device__ __forceinline__ ExpCoef exp_coef(double k2, double w2, double tau) {
     const double Z = -Y;
     double h = 1.0, zk = 1.0;
     double G[7] = {0, 0, 0, 0, 0, 0, 0};
-    // inverse factorials 1/(2k+m)! built incrementally per m
-    double f2 = 1.0 / 2, f3 = 1.0 / 6, f4 = 1.0 / 24, f5 = 1.0 / 120, f6 = 1.0 / 720;
+#pragma unroll
     for (int k = 0; k < 14; ++k) {
-      G[2] += h * f2;
-      G[3] += h * f3;
-      G[4] += h * f4;
-      G[5] += h * f5;
-      G[6] += h * f6;
+      G[2] += h * kInvFact.v[2 * k + 2];
+      G[3] += h * kInvFact.v[2 * k + 3];
+      G[4] += h * kInvFact.v[2 * k + 4];
+      G[5] += h * kInvFact.v[2 * k + 5];
+      G[6] += h * kInvFact.v[2 * k + 6];
       zk *= Z;
       h = X * h + zk;  // h_{k+1} = X h_k + Z^{k+1}
-      const double n2 = 2.0 * k + 2;
-      f2 /= (n2 + 1) * (n2 + 2);
-      f3 /= (n2 + 2) * (n2 + 3);
-      f4 /= (n2 + 3) * (n2 + 4);
-      f5 /= (n2 + 4) * (n2 + 5);
-      f6 /= (n2 + 5) * (n2 + 6);
     }
     const double XY = X * Y;
     e.a0 = 1.0 + XY * G[4];
