@@ -114,3 +114,16 @@ def test_cfl_bound_is_the_papers(coeffs16):
     assert b.lib().pic_init_grid(ctypes.byref(d), ctypes.byref(h)) != -2
     if h.value:  # a GPU was present: the grid was created on fake field pointers
         b.lib().pic_destroy(h)
+
+
+def test_null_handles_are_rejected_without_a_device():
+    """Entry points given a NULL grid return PIC_EINVAL before any device
+    call (window, shape, sort interval, correction, step loop)."""
+    L = b.lib()
+    o, m = ctypes.c_int64(), ctypes.c_int64()
+    assert L.pic_move_window(None, 1, None, 0) == -1
+    assert L.pic_window(None, ctypes.byref(o), ctypes.byref(m)) == -1
+    assert L.pic_set_shape(None, 1) == -1
+    assert L.pic_set_sort_interval(None, 3) == -1
+    assert L.pic_current_correction(None, None) == -1
+    assert L.pic_step_n(None, None, 0, 1, 0, 0) == -1
