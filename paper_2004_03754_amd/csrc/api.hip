@@ -808,6 +808,13 @@ int pic_move_window(pic_grid* g, int64_t cells, pic_particles* const* species, i
     if (rc) return rc;
   }
   if (cells == 0) return PIC_OK;
+  // scratch first: a failed allocation leaves the window unmoved
+  int64_t npmax = 0;
+  for (int s = 0; s < nspecies; ++s) npmax = std::max(npmax, species[s]->np);
+  if (npmax > 0) {
+    int rc = ensure_window_scratch(g, npmax);
+    if (rc) return rc;
+  }
   void* arrays[9];
   int na = 0;
   for (int c = 0; c < 3; ++c) arrays[na++] = g->E[c];
@@ -820,8 +827,6 @@ int pic_move_window(pic_grid* g, int64_t cells, pic_particles* const* species, i
   for (int s = 0; s < nspecies; ++s) {
     pic_particles* p = species[s];
     if (p->np == 0) continue;
-    rc = ensure_window_scratch(g, p->np);
-    if (rc) return rc;
     rc = launch_window_count(g->mesh, *p, o, cells, g->win_counts, g->win_offs, g->stream);
     if (rc) return rc;
     int64_t total = 0;
