@@ -751,6 +751,20 @@ __device__ __forceinline__ void st_run(T* __restrict__ p, const T (&o)[RW]) {
   }
 }
 
+// non-temporal variant for the sweep's outputs (written once, never re-read)
+template <typename T, int RW>
+__device__ __forceinline__ void st_run_nt(T* __restrict__ p, const T (&o)[RW]) {
+  using V = typename Vec16<T>::type;
+  constexpr int R = 16 / (int)sizeof(T);
+#pragma unroll
+  for (int v = 0; v < RW / R; ++v) {
+    V a;
+#pragma unroll
+    for (int e = 0; e < R; ++e) a[e] = o[v * R + e];
+    __builtin_nontemporal_store(a, reinterpret_cast<V*>(p + v * R));
+  }
+}
+
 // Faraday taps of output u for a window whose index 0 is HB columns left of
 // the task's first output: sum_q a_q (w[u+HB+q] - w[u+HB-q+1])
 template <typename T, int ME, int HB, int NW>
@@ -1002,9 +1016,9 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
       st_run<T, RW>(f + 2 * G::SF, f3);
       if (out && ka >= k0 && ka < kend) {
         const size_t o = pl(0) + g2;
-        st_run<T, RW>(oE1 + o, g1c);
-        st_run<T, RW>(oE2 + o, g2c);
-        st_run<T, RW>(oE3 + o, f3);
+        st_run_nt<T, RW>(oE1 + o, g1c);
+        st_run_nt<T, RW>(oE2 + o, g2c);
+        st_run_nt<T, RW>(oE3 + o, f3);
       }
     }
     load_J(pl(1));
@@ -1023,8 +1037,8 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
       }
       if (out) {
         const size_t o = pl(-1) + g2;
-        st_run<T, RW>(oB1 + o, o1);
-        st_run<T, RW>(oB2 + o, o2);
+        st_run_nt<T, RW>(oB1 + o, o1);
+        st_run_nt<T, RW>(oB2 + o, o2);
       }
     }
     if (w3 && ka - 1 >= k0) {  // B3 from the x1 derivative of E2 and the x2 difference of E1
@@ -1036,7 +1050,7 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
 #pragma unroll
       for (int u = 0; u < RW; ++u)
         o3[u] = cb[2][u] - (faraday_w<T, ME, HB>(w, c.ae, u) - c.hy * (f1n[u] - f1c[u]));
-      if (out3) st_run<T, RW>(oB3 + pl(-1) + g3, o3);
+      if (out3) st_run_nt<T, RW>(oB3 + pl(-1) + g3, o3);
     }
     // B^{n+1/2}(ka) for stage 2 at ka+1 (components 1, 2 at the task's
     // position) and stage 3 at ka (component 3 at the B3 position)
