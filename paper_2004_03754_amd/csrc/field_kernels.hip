@@ -1233,7 +1233,14 @@ int run_sweep(const Mesh& m, void* const Ein[3], void* const Bin[3], void* const
   c.dt = (T)dt;
   const int tiles_x = (m.n1 + TX - 1) / TX;
   const int tiles_y = (m.n2 + TY - 1) / TY;
-  const int KZ = m.n3;
+  // too few tiles to fill the chip: split the x3 march into chunks, as the
+  // Yee-Ampere sweep does (each chunk re-reads the planes its pipeline needs)
+  const int tiles = tiles_x * tiles_y;
+  const int wgs_per_cu = G::lds_bytes * 2 <= 160 * 1024 ? 2 : 1;
+  int nz = 1;
+  const int want = wgs_per_cu * device_cus();
+  if (tiles < want) nz = min(m.n3, (want + tiles - 1) / tiles);
+  const int KZ = (m.n3 + nz - 1) / nz;
   const bool hasJ = J && J[0];
   auto kern = hasJ ? sweep_kernel<T, ME, MB, TX, TY, NT, true> : sweep_kernel<T, ME, MB, TX, TY, NT, false>;
   static_assert(G::lds_bytes <= 160 * 1024, "sweep tile exceeds LDS");
