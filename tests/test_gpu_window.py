@@ -432,3 +432,46 @@ def test_sec41_solver_and_pusher_comparisons():
     h_yee = errs("yee", "analytic", 10000.0, 20.0, 400.0)
     assert 0.5 <= h_hc[1] / h_an[1] <= 2.0
     assert h_yee[1] >= 5 * max(h_hc[1], h_an[1])
+
+
+def test_window_with_plasma_steps_matches_oracle(coeffs16):
+    """Moves between plasma steps (3D, deposit on, particles sorted by tile
+    and their current accumulated on chip): fields through the ring origin
+    and the surviving particles (by id) agree with the oracle's shifted
+    window to 1e-12 after 12 steps and 3 moves of 2 cells."""
+    CE, CB = coeffs16
+    n = (128, 8, 8)
+    dx = (wl.DX1, wl.DX2, wl.DX3)
+    E, B = wl.random_fields(n, seed=91, scale=0.05)
+    L = [n[0] * dx[0], n[1] * dx[1], n[2] * dx[2]]
+    x, u = wl.uniform_particles(3000, [0, 0, 0], L, seed=92, u_th=0.2)
+    ids = np.arange(x.shape[1], dtype=np.int64)
+    Ed, Bd = [dev(e) for e in E], [dev(v) for v in B]
+    Jd = [dev(np.zeros_like(E[0])) for _ in range(3)]
+    grid = b.Grid(Ed, Bd, dx, wl.DT, CE, CB, J=Jd)
+    p = b.Particles(dev(x), dev(u), q=-1.0, m=1.0, w=1e-3, id=dev(ids, torch.int64))
+    sp = dict(x=x.copy(), u=u.copy(), id=ids.copy(), q=-1.0, m=1.0, w=1e-3)
+    print("window with plasma steps", flush=True)
+    for _ in range(3):
+        for _ in range(4):
+            E, B = pic.step(E, B, [sp], CE, CB, dx, wl.DT, pusher="boris", deposit=True, ndim=3)
+        E, B = window.move(E, B, [sp], 2, wl.DX1)
+        grid.step_n([p], 4, pusher="boris", deposit=True)
+        grid.move_window(2, [p])
+    grid.sync()
+    origin, moved = grid.window()
+    assert moved == 6
+    scale = max(np.max(np.abs(f)) for f in E + B)
+    for got, ref in zip(Ed + Bd, E + B):
+        assert np.max(np.abs(_ring_to_window(host(got), origin) - ref)) <= 1e-12 * scale
+    xg, ug, ig = p.live()
+    ig = ig.cpu().numpy()
+    assert p.np == sp["id"].size < 3000
+    order = np.argsort(ig)
+    np.testing.assert_array_equal(ig[order], np.sort(sp["id"]))
+    ref_order = np.argsort(sp["id"])
+    xw = host(xg)[:, order]
+    xw[0] = np.mod(xw[0] - origin * wl.DX1, L[0])
+    np.testing.assert_allclose(xw, sp["x"][:, ref_order], rtol=0, atol=1e-12 * max(L))
+    np.testing.assert_allclose(host(ug)[:, order], sp["u"][:, ref_order], rtol=0, atol=1e-12)
+    grid.close()
