@@ -161,8 +161,13 @@ __device__ __forceinline__ ExpCoef exp_coef(double k2, double w2, double tau) {
     const double Z = -Y;
     double h = 1.0, zk = 1.0;
     double G[7] = {0, 0, 0, 0, 0, 0, 0};
+    // terms beyond k are below v^k/(2k+2)! with v = max(X, Y): 14 terms reach
+    // 1e-19 at v = 1, 8 at v <= 1/16, 5 at v <= 1/256
+    const double v = fmax(X, Y);
+    const int nk = v > 0.0625 ? 14 : (v > 0.00390625 ? 8 : 5);
 #pragma unroll
     for (int k = 0; k < 14; ++k) {
+      if (k >= nk) break;
       G[2] += h * kInvFact.v[2 * k + 2];
       G[3] += h * kInvFact.v[2 * k + 3];
       G[4] += h * kInvFact.v[2 * k + 4];
