@@ -1211,11 +1211,16 @@ int run_sweep_yee(const Mesh& m, void* const Ein[3], void* const Bin[3], void* c
   c.dt = (T)dt;
   const int tiles_x = (m.n1 + TX - 1) / TX;
   const int tiles = tiles_x * ((m.n2 + TY - 1) / TY);
-  // FP32 tiles fit two workgroups per CU (LDS and 128 VGPRs), with the x3
-  // march split when the mesh has fewer than two tiles per CU.  FP64 takes
-  // one workgroup per CU.
-  if constexpr (sizeof(T) == 4)
+  // FP32 tiles fit two workgroups per CU (LDS and 128 VGPRs); that pays
+  // where the mesh has fewer than two tiles per CU (the x3 march is then
+  // split to fill the slots).  With at least two tiles per CU one workgroup
+  // per CU (144 VGPRs, no spills) streams faster.  FP64 takes one workgroup
+  // per CU.
+  if constexpr (sizeof(T) == 4) {
+    if (tiles >= 2 * device_cus())
+      return launch_sweep_yee<T, ME, TX, TY, NT, 2>(m, Ein, Bin, J, Eout, Bout, Bh, c, tiles_x, tiles, 1, s);
     return launch_sweep_yee<T, ME, TX, TY, NT, 4>(m, Ein, Bin, J, Eout, Bout, Bh, c, tiles_x, tiles, 2, s);
+  }
   return launch_sweep_yee<T, ME, TX, TY, NT, 2>(m, Ein, Bin, J, Eout, Bout, Bh, c, tiles_x, tiles, 1, s);
 }
 
