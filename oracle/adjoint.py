@@ -82,8 +82,9 @@ B_OFF = ((0.0, 0.5, 0.5), (0.5, 0.0, 0.5), (0.5, 0.5, 0.0))
 
 
 def _axis(xd, dx, off, n):
-    """Linear-shape nodes and weights along one direction (App. A)."""
-    u = xd / dx - off
+    """Linear-shape nodes and weights along one direction (App. A); the cell
+    coordinate is x * (1/dx), as in the FP64 oracle."""
+    u = xd * (1.0 / dx) - off
     i0 = torch.floor(u.detach())
     w1 = u - i0
     i0 = i0.to(torch.int64)

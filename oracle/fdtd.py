@@ -113,12 +113,6 @@ def div_ampere(E, CB, dx):
             + d_bwd(E[2], X3, dx[2]))
 
 
-def field_energy(E, B, dx):
-    """Sum of (E^2 + B^2)/2 over the grid times the cell volume."""
-    vol = dx[0] * dx[1] * dx[2]
-    return 0.5 * vol * float(sum(np.sum(f * f) for f in E) + sum(np.sum(f * f) for f in B))
-
-
 def amplification_matrix(k, CE, CB, dx, dt, n=(64, 4, 4)):
     """The 6x6 complex matrix G of one sweep acting on the Fourier amplitudes
     of a single mode exp(i k . X) (X = grid index times dx), measured by

@@ -41,8 +41,15 @@ Passages followed
 Readings
 --------
 * Shape order: linear for every run (the paper's LWFA run uses quadratic).
-* Cell index of a position is floor(x/dx - offset); periodic wrap of a
-  position: x < 0 -> x + L (then 0 if that rounds to L); x >= L -> x - L.
+* Cell coordinate of a position: x/dx is evaluated as x * (1/dx) (one
+  rounding of the reciprocal, one of the product), the cell index is
+  floor(x * (1/dx) - offset) and the weight the remainder.  The index is an
+  integer that floating point decides, so the reading fixes one evaluation
+  order for it (and for the weights that go with it), here and in the HIP
+  library; x/dx correctly rounded would move the index across a face for
+  positions within an ulp of it and the weights by an ulp of the cell
+  coordinate, which random fields of large amplitude amplify.  Periodic wrap
+  of a position: x < 0 -> x + L (then 0 if that rounds to L); x >= L -> x - L.
 * The momentum-conserving choice S_E = S_J (Sec. 3.1.2) holds: both are the
   linear shape at the component's own location.
 """
@@ -57,7 +64,7 @@ B_OFF = ((0.0, 0.5, 0.5), (0.5, 0.0, 0.5), (0.5, 0.5, 0.0))
 
 def _axis_weights(xd, dx, off, n):
     """Linear-shape nodes and weights along one direction."""
-    u = xd / dx - off
+    u = xd * (1.0 / dx) - off
     i0 = np.floor(u)
     w1 = u - i0
     i0 = i0.astype(np.int64)
@@ -68,7 +75,7 @@ def _axis_nodes_quadratic(xd, dx, off, n):
     """Quadratic B-spline shape along one direction (the Sec. 4.2 run's
     choice): the three nodes around the nearest one, i = round(u), with
     weights (1/2 - d)^2/2, 3/4 - d^2, (1/2 + d)^2/2 for d = u - i."""
-    u = xd / dx - off
+    u = xd * (1.0 / dx) - off
     i = np.floor(u + 0.5)
     d = u - i
     i = i.astype(np.int64)
@@ -257,8 +264,8 @@ def min_image(x_new, x_old, L):
 def _shapes_quadratic(x0, x1, dx):
     """Local 4-node quadratic shapes before/after a move of less than one
     cell (the nearest nodes differ by at most one)."""
-    X0 = x0 / dx
-    X1 = x1 / dx
+    X0 = x0 * (1.0 / dx)
+    X1 = x1 * (1.0 / dx)
     i0 = np.floor(X0 + 0.5)
     i1 = np.floor(X1 + 0.5)
     d0 = X0 - i0
@@ -282,8 +289,8 @@ def _shapes(x0, x1, dx, order=1):
     (``order`` 2: the 4-node quadratic ones)."""
     if order == 2:
         return _shapes_quadratic(x0, x1, dx)
-    X0 = x0 / dx
-    X1 = x1 / dx
+    X0 = x0 * (1.0 / dx)
+    X1 = x1 * (1.0 / dx)
     i0 = np.floor(X0)
     i1 = np.floor(X1)
     f0 = X0 - i0

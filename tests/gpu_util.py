@@ -1,4 +1,11 @@
-"""Helpers shared by the GPU parity tests (device transfers, error norms)."""
+"""Helpers shared by the GPU parity tests (device transfers, error norms).
+
+With YEEPIC_ERRLOG set to a file path, every checked error is appended to it
+as one JSON line (test, quantity, error, tolerance), so that the measured
+error of each result can be stated next to its bound."""
+import json
+import os
+
 import numpy as np
 import torch
 
@@ -15,6 +22,22 @@ def host(t):
 
 def fields_dev(E, B, dtype=torch.float64):
     return [dev(e, dtype) for e in E], [dev(x, dtype) for x in B]
+
+
+def record(what, err, tol):
+    """Append a measured error to the YEEPIC_ERRLOG file (if set)."""
+    path = os.environ.get("YEEPIC_ERRLOG")
+    if not path:
+        return
+    test = os.environ.get("PYTEST_CURRENT_TEST", "").split(" ")[0]
+    with open(path, "a") as f:
+        f.write(json.dumps({"test": test, "what": what, "err": float(err), "tol": float(tol)}) + "\n")
+
+
+def check(err, tol, what):
+    """Record ``err`` and assert err <= tol."""
+    record(what, err, tol)
+    assert err <= tol, f"{what}: error {err:.3e} > {tol:.1e}"
 
 
 def normwise(got, ref):
@@ -34,4 +57,5 @@ def assert_fields_close(got, ref, tol, what="", joint=False):
             err = float(np.max(np.abs(gh - r))) / (joint_scale if joint_scale > 0 else 1.0)
         else:
             err = normwise(gh, r)
+        record(f"{what} component {c + 1}", err, tol)
         assert err <= tol, f"{what} component {c + 1}: norm-wise error {err:.3e} > {tol:.1e}"

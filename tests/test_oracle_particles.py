@@ -243,6 +243,66 @@ def test_deposit_continuity(ndim):
     assert np.max(np.abs(res)) < 1e-12 * np.max(np.abs(rho1 - rho0) / dt)
 
 
+def _hat_path_average(X0, dX, Y0, dY, a, b):
+    """int_0^1 S(X0 + s dX - a) S(Y0 + s dY - b) ds for the linear hat
+    S(t) = max(0, 1 - |t|), by three-point Gauss-Legendre on [0, 1] (exact:
+    for a path that stays inside one cell the integrand is a quadratic)."""
+    xg, wg = np.polynomial.legendre.leggauss(3)
+    s = (xg + 1) / 2
+    S = lambda t: np.maximum(0.0, 1.0 - np.abs(t))
+    return float(np.sum(wg * S(X0 + s * dX - a) * S(Y0 + s * dY - b)) / 2)
+
+
+def test_deposit_2d_out_of_plane_current():
+    """Sec. 3.3 in 2D3V: the out-of-plane current of a particle is q w v3,
+    v3 = u3/gamma^{n+1/2} (u3 alone would be wrong wherever gamma > 1), spread
+    over the nodes by a weight that moves with the particle:
+      * its sum is 1 (sum J3 = q w v3);
+      * by the linear shape's reproduction of linear functions, its first
+        moments are the midpoint of the path, X0 + dX/2 and Y0 + dY/2, and its
+        mixed moment sum a b W is the path average of X Y,
+        X0 Y0 + (X0 dY + Y0 dX)/2 + dX dY/3;
+      * for a move inside one cell it equals the time average of the shape
+        product along the straight path (checked per node by quadrature).
+    Moves cross faces and the periodic seam; gamma is far from 1."""
+    n = (8, 6, 1)
+    shape = (1, n[1], n[0])
+    L = [n[d] * DX[d] for d in range(2)]
+    g = np.random.default_rng(5)
+    q, w, dt = -1.0, 0.37, wl.DT
+    inside = 0
+    for trial in range(24):
+        x0 = np.array([[g.random() * L[0]], [g.random() * L[1]], [0.0]])
+        d = (2 * g.random(2) - 1) * (0.9 if trial % 2 else 0.2) * np.array(DX[:2])
+        if trial == 0:
+            x0[0, 0], d[0] = 0.02 * DX[0], -0.5 * DX[0]   # backwards across the seam
+        x1 = x0.copy()
+        x1[:2, 0] = np.mod(x0[:2, 0] + d, L)
+        u = np.array([[4.0 * g.standard_normal()], [g.standard_normal()], [3.0 * g.standard_normal()]])
+        J = pt.deposit(x0, x1, q, w, DX, dt, shape, 2, u=u)
+        v3 = u[2, 0] / np.sqrt(1 + float(u[:, 0] @ u[:, 0]))
+        qv = q * w * v3
+        X0, Y0 = x0[0, 0] / DX[0], x0[1, 0] / DX[1]
+        dX, dY = d[0] / DX[0], d[1] / DX[1]
+        # node coordinates as the periodic image nearest to the path start
+        ia, jb = np.arange(n[0]), np.arange(n[1])
+        a = ia + n[0] * np.round((X0 - ia) / n[0])
+        b = jb + n[1] * np.round((Y0 - jb) / n[1])
+        W = J[2][0] / qv  # [jb, ia]
+        assert abs(W.sum() - 1) < 1e-14
+        assert abs(np.sum(W * a[None, :]) - (X0 + dX / 2)) < 1e-13
+        assert abs(np.sum(W * b[:, None]) - (Y0 + dY / 2)) < 1e-13
+        mixed = X0 * Y0 + (X0 * dY + Y0 * dX) / 2 + dX * dY / 3
+        assert abs(np.sum(W * b[:, None] * a[None, :]) - mixed) < 1e-12
+        if np.floor(X0) == np.floor(X0 + dX) and np.floor(Y0) == np.floor(Y0 + dY):
+            inside += 1
+            for j_ in range(n[1]):
+                for i_ in range(n[0]):
+                    ref = _hat_path_average(X0, dX, Y0, dY, a[i_], b[j_])
+                    assert abs(W[j_, i_] - ref) < 1e-14, (trial, i_, j_)
+    assert inside >= 3
+
+
 def test_deposit_total_current_and_rest():
     """Sum of J_d over the grid is q w (displacement_d)/dt per particle; a
     particle that does not move deposits exactly zero."""

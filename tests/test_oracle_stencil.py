@@ -142,6 +142,60 @@ def test_F_factor_proposed_vs_yee_and_xu(fits):
     assert np.max(np.abs(Fx - 1)) > 1e-2
 
 
+@pytest.mark.parametrize("r", [0.5, 0.25])
+def test_xu_fitted_pair_keeps_c_and_gives_F_cos(r):
+    """Sec. 4 (Xu solver): [k]_E1 = [k]_B1 = [k]_{1,t}.  With both operators
+    equal to the fitted Xu stencil, Eq. (dispersion) gives sin(omega dt/2) =
+    sin(k1 dt/2), so v_phi = 1, and the factor of Eq. (f2_q) reduces to
+    F = cos(k1 dt/2).  Both hold over kappa <= 0.3 to the fit residual
+    (measured 2.3e-8 in v_phi, 5e-9 in F), and F departs from 1 there."""
+    cx = np.array([float(c) for c in st.fit_coeffs(16, mp.mpf(r), "xu")])
+    dx = 0.2
+    dt = r * dx
+    k = np.linspace(1e-4, 0.3, 3001) * 2 * np.pi / dx
+    vp = st.phase_velocity(cx, cx, k, dx, dt)
+    F = st.f_factor(cx, cx, k, dx, dt)
+    assert np.max(np.abs(vp - 1)) < 1e-7
+    assert np.max(np.abs(F - np.cos(k * dt / 2))) < 1e-7
+    assert np.max(np.abs(F - 1)) > 1e-3
+
+
+def test_cfl_exact_yee_closed_form_and_discrete_growth():
+    """Sec. 3.2 exact condition.  For Yee (C = 1) the x1 product peaks at the
+    Nyquist mode, [k]^2 = 4/dx1^2, so the bound is
+    (dt/2) sqrt(4/dx1^2 + 4/dx2^2 [+ 4/dx3^2]) = dt sqrt(sum 1/dx_d^2) (the
+    magic step is where it equals 1).  The discrete sweep's one-step
+    amplification of the Nyquist mode has spectral radius 1 just below the
+    limit and grows just above it.  For the fitted M = 16 pair the 3D value
+    exceeds the 2D one by the x3 term alone; its C^E alternates in sign, so
+    at the Nyquist mode [k]_E1 = (2/dx1) sum|C^E| and the sufficient bound is
+    attained (exact value 1 there)."""
+    dx1, dx2, dx3 = 2 * np.pi / 32, 2 * np.pi / 8, 2 * np.pi / 6
+    for dx in ([dx1, dx2], [dx1, dx2, dx3]):
+        dtm = 1.0 / np.sqrt(sum(1.0 / d ** 2 for d in dx))
+        for f in (0.7, 1.0, 1.3):
+            assert abs(st.cfl_exact_max([1.0], [1.0], dx, f * dtm) - f) < 1e-14
+        assert st.cfl_exact_max([1.0], [1.0], dx, dtm * (1 - 1e-3)) < 1
+        assert st.cfl_exact_max([1.0], [1.0], dx, dtm * (1 + 1e-3)) > 1
+    from oracle import fdtd
+    dx = [dx1, dx2, dx3]
+    dtm = 1.0 / np.sqrt(sum(1.0 / d ** 2 for d in dx))
+    k = (np.pi / dx1, np.pi / dx2, np.pi / dx3)
+    rad = {}
+    for f in (0.99, 1.01):
+        G = fdtd.amplification_matrix(k, [1.0], [1.0], dx, f * dtm, n=(2, 2, 2))
+        rad[f] = float(np.max(np.abs(np.linalg.eigvals(G))))
+    assert abs(rad[0.99] - 1) < 1e-9
+    assert rad[1.01] > 1 + 1e-2
+    ce, cb = st.fit_pair(16, 0.5)
+    dt = dx1 / 2
+    v2 = st.cfl_exact_max(ce, cb, [dx1, dx2], dt)
+    v3 = st.cfl_exact_max(ce, cb, [dx1, dx2, dx3], dt)
+    assert abs((v3 ** 2 - v2 ** 2) - (dt / 2) ** 2 * 4 / dx3 ** 2) < 1e-14
+    assert np.all(ce[:-1] * ce[1:] < 0)
+    assert abs(st.cfl_exact_max(ce, cb, [dx1, dx2, dx3], st.cfl_sufficient_dt(ce, cb, [dx1, dx2, dx3])) - 1) < 1e-14
+
+
 def test_oblique_waves(fits):
     """Sec. 3.1.1: leading term of Eq. (vphi_ob) is exactly 1 for the proposed
     solver (eta = 1) and below 1 for Yee; the symbol-based v_phi matches the
