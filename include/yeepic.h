@@ -292,6 +292,26 @@ int pic_window(const pic_grid *g, int64_t *origin, int64_t *moved);
 int pic_adjoint_step(pic_grid *g, const pic_adjoint *adj, const pic_particles *const *species,
                      pic_particles *const *lambda, int nspecies, int pusher);
 
+/* ---- the adjoint step without allocation ------------------------------------
+ * For callers that cannot allocate device memory during a step (code under
+ * HIP graph capture, tight loops of an optimiser, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as pic_adjoint_step, and
+ * the same kernels, but the per-block partial sums of the coefficient
+ * gradients live in a fixed device array of the library (1 MiB: 2^17
+ * doubles, i.e. 8192 reduction blocks of 1024 x1 cells by 8 x1 rows, about
+ * 67M cells) instead of grid scratch allocated at the first call; the call
+ * makes no hipMalloc, hipFree or other allocating call.  The array's device
+ * address is looked up once per device at pic_init_grid.  A mesh needing
+ * more partial sums is refused with PIC_EUNSUPPORTED (use pic_adjoint_step).
+ * Every grid on one device shares that array and nothing in it needs to
+ * start at zero (each call writes the partial sums before it reads them);
+ * calls that overlap in time on one device (other streams, other threads)
+ * race on it and must be serialised by the caller.  Without adj->En, Bn the
+ * step recomputes the forward sweep in the grid's second field set, which
+ * pic_init_grid allocated. */
+int pic_adjoint_step_noalloc(pic_grid *g, const pic_adjoint *adj, const pic_particles *const *species,
+                             pic_particles *const *lambda, int nspecies, int pusher);
+
 /* ---- diagnostics ------------------------------------------------------------
  * Waits for the grid's stream and reports a pending HIP error. */
 int pic_sync(pic_grid *g);

@@ -53,7 +53,8 @@ class _Adjoint(ctypes.Structure):
 EXPORTS = ["pic_design_coeffs", "pic_init_grid", "pic_set_fields", "pic_advance_B_half", "pic_advance_E",
            "pic_field_sweep", "pic_gather_push", "pic_deposit_J", "pic_step_n", "pic_sync", "pic_check",
            "pic_grid_widths", "pic_destroy", "pic_last_error", "pic_set_sort_interval", "pic_adjoint_step", "pic_step_to",
-           "pic_current_correction", "pic_set_shape", "pic_move_window", "pic_window"]
+           "pic_current_correction", "pic_set_shape", "pic_move_window", "pic_window",
+           "pic_adjoint_step_noalloc"]
 
 
 def lib():
@@ -81,6 +82,7 @@ def lib():
         L.pic_move_window.argtypes = [vp, ctypes.c_int64, PP, i]
         L.pic_window.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.pic_adjoint_step.argtypes = [vp, ctypes.POINTER(_Adjoint), PP, PP, i, i]
+        L.pic_adjoint_step_noalloc.argtypes = [vp, ctypes.POINTER(_Adjoint), PP, PP, i, i]
         L.pic_step_to.argtypes = [vp, PP, i, i, ctypes.c_void_p * 3, ctypes.c_void_p * 3, ctypes.c_void_p]
         L.pic_sync.argtypes = [vp]
         L.pic_check.argtypes = [vp, ctypes.POINTER(_Particles)]
@@ -199,13 +201,14 @@ class Grid:
         _check(lib().pic_set_fields(self._h, _ptr3(E), _ptr3(B), _ptr3(J)))
 
     def adjoint_step(self, lE, lB, gCE, gCB, species=(), lambdas=(), pusher="boris", next_E=None, next_B=None,
-                     half_B=None):
+                     half_B=None, noalloc=False):
         """Reverse of one vacuum step from the grid's current state (see
         pic_adjoint_step): lE, lB (FP64, field layout) and the particle
         cotangents in ``lambdas`` are mapped from t^{n+1} to t^n in place;
         gCE, gCB (16 doubles on the device) are accumulated.  next_E, next_B:
         the forward state at t^{n+1}, if the caller has it; half_B (with
-        them): the step's B^{n+1/2}, as step_to writes it."""
+        them): the step's B^{n+1/2}, as step_to writes it.  noalloc: call
+        pic_adjoint_step_noalloc (library-held scratch, no allocation)."""
         adj = _Adjoint()
         adj.lE, adj.lB = _ptr3(lE), _ptr3(lB)
         adj.gCE, adj.gCB = gCE.data_ptr(), gCB.data_ptr()
@@ -217,7 +220,8 @@ class Grid:
         for s_, (p, lam) in enumerate(zip(species, lambdas)):
             a[s_] = ctypes.pointer(p._s)
             b[s_] = ctypes.pointer(lam._s)
-        _check(lib().pic_adjoint_step(self._h, ctypes.byref(adj), a, b, ns, PUSHERS[pusher]))
+        fn = lib().pic_adjoint_step_noalloc if noalloc else lib().pic_adjoint_step
+        _check(fn(self._h, ctypes.byref(adj), a, b, ns, PUSHERS[pusher]))
 
     def widths(self):
         a, b = ctypes.c_int(), ctypes.c_int()

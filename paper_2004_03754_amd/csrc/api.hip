@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -50,6 +51,7 @@ struct pic_grid {
   std::vector<SortState> vsort_a, vsort_b;
   double* partial = nullptr;  // per-block partial sums of the coefficient gradients
   int64_t partial_cap = 0;
+  double* noalloc = nullptr;  // device address of the static adjoint scratch on the grid's device
   // x1 current correction for a non-Yee C^B (Sec. 3.3): taps of the periodic
   // kernel, zero-padded to corr_kw + 1, and the corrected x1 current
   int corr_status = 0;     // PIC_OK, or why no kernel could be built
@@ -71,6 +73,40 @@ struct pic_grid {
 namespace yeepic {
 
 static thread_local char g_err[512] = "no error";
+
+// Device scratch of the allocation-free adjoint step: the per-block partial
+// sums of the coefficient gradients (PIC_MAX_M doubles per reduction block).
+// Each device holds its own copy until the process ends.  Host code never
+// passes ``scratch`` itself to a kernel: it uses the device address that
+// hipGetSymbolAddress returns for the current device (scratch_on_device).
+constexpr int64_t kNoAllocDoubles = (int64_t)1 << 17;  // 1 MiB
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// The address of ``scratch`` on the current device, looked up once per
+// device; nullptr with the error recorded when the lookup fails.
+static double* scratch_on_device() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    set_error(PIC_EHIP, "no usable current device for the adjoint scratch");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    double* ptr = nullptr;
+    e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error(PIC_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
 
 // vacuum step loop: species of at least kVacSortMin particles are pushed as a
 // tile-ordered copy, re-sorted every kVacSortEvery steps (|v| < c moves a
@@ -348,6 +384,12 @@ int pic_init_grid(const pic_grid_desc* d, pic_grid** out) {
   if (hipMalloc((void**)&g->d_flag, sizeof(int)) != hipSuccess) {
     pic_destroy(g);
     return set_error(PIC_ENOMEM, "cannot allocate the flag word");
+  }
+  g->noalloc = scratch_on_device();
+  if (!g->noalloc) {
+    const int rc = PIC_EHIP;
+    pic_destroy(g);
+    return rc;
   }
   if (!ampere_is_yee(g)) {
     g->corr_status = build_correction(g);
@@ -642,8 +684,9 @@ int pic_step_to(pic_grid* g, pic_particles* const* species, int nspecies, int pu
   return sweep_once(g, g->E, g->B, Eout, Bout, 0, Bhalf);
 }
 
-int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* const* species,
-                     pic_particles* const* lambda, int nspecies, int pusher) {
+// Argument checks shared by the two adjoint entry points.
+static int adjoint_args(pic_grid* g, const pic_adjoint* adj, const pic_particles* const* species,
+                        pic_particles* const* lambda, int nspecies, int pusher) {
   if (!g || !adj) return set_error(PIC_EINVAL, "pic_adjoint_step: NULL argument");
   if (g->prec != PIC_FP64) return set_error(PIC_EUNSUPPORTED, "the adjoint is built for FP64 grids only");
   if (pusher == PIC_PUSH_HC) return set_error(PIC_EUNSUPPORTED, "the adjoint covers the Boris and exact pushers");
@@ -667,17 +710,14 @@ int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* c
         if (!l->u[d] || (d < g->ndim && !l->x[d]))
           return set_error(PIC_EINVAL, "lambda[%d] has a NULL array", s);
   }
+  return PIC_OK;
+}
+
+// The adjoint step with ``partial`` (coef_partial_blocks * PIC_MAX_M
+// doubles of device memory) for the coefficient reductions; allocates nothing.
+static int adjoint_body(pic_grid* g, const pic_adjoint* adj, const pic_particles* const* species,
+                        pic_particles* const* lambda, int nspecies, int pusher, double* partial) {
   const Mesh& m = g->mesh;
-  const int64_t need = (int64_t)coef_partial_blocks(m) * PIC_MAX_M;
-  if (need > g->partial_cap) {
-    (void)hipStreamSynchronize(g->stream);
-    if (g->partial) (void)hipFree(g->partial);
-    g->partial = nullptr;
-    g->partial_cap = 0;
-    if (hipMalloc((void**)&g->partial, (size_t)need * sizeof(double)) != hipSuccess)
-      return set_error(PIC_ENOMEM, "cannot allocate the coefficient-gradient scratch");
-    g->partial_cap = need;
-  }
   const double dt = g->dt;
   void* none[3] = {nullptr, nullptr, nullptr};
   auto d = [](const void* p) { return (const double*)p; };
@@ -713,21 +753,52 @@ int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* c
   void* const* aE = nE;
   if (!rc && !half) rc = launch_advance_b(g->prec, m, nE, nB, g->alt + 3, g->CE, g->ME, -0.5 * dt, g->stream);
   // third stage B'' = B' - dt/2 curl_E[C^E] E': dC^E from (lB, E')
-  if (!rc) rc = launch_coef_grad(m, 0, d(lB[1]), d(aE[2]), d(lB[2]), d(aE[1]), 0.5 * dt / m.dx1, g->M, g->partial,
+  if (!rc) rc = launch_coef_grad(m, 0, d(lB[1]), d(aE[2]), d(lB[2]), d(aE[1]), 0.5 * dt / m.dx1, g->M, partial,
                                  adj->gCE, g->stream);
   if (!rc) rc = launch_advance_e(g->prec, m, lE, lB, none, g->CE, g->ME, -0.5 * dt, g->stream);
   // second stage E' = E + dt curl_B[C^B] B': dC^B from (lE', B')
-  if (!rc) rc = launch_coef_grad(m, 1, d(lE[2]), d(aB[1]), d(lE[1]), d(aB[2]), dt / m.dx1, g->M, g->partial,
+  if (!rc) rc = launch_coef_grad(m, 1, d(lE[2]), d(aB[1]), d(lE[1]), d(aB[2]), dt / m.dx1, g->M, partial,
                                  adj->gCB, g->stream);
   if (!rc) rc = launch_advance_b(g->prec, m, lE, lB, lB, g->CB, g->MB, -dt, g->stream);
   // first stage B' = B - dt/2 curl_E[C^E] E: dC^E from (lB', E^n)
   if (!rc) rc = launch_coef_grad(m, 0, d(lB[1]), d(g->E[2]), d(lB[2]), d(g->E[1]), 0.5 * dt / m.dx1, g->M,
-                                 g->partial, adj->gCE, g->stream);
+                                 partial, adj->gCE, g->stream);
   if (!rc) rc = launch_advance_e(g->prec, m, lE, lB, none, g->CE, g->ME, -0.5 * dt, g->stream);
   // particles: reverse of position update, push and gather at t^n
   for (int s = 0; s < nspecies && !rc; ++s)
     rc = launch_adjoint_push(m, g->E, g->B, lE, lB, *species[s], *lambda[s], pusher, dt, g->stream);
   return rc;
+}
+
+int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* const* species,
+                     pic_particles* const* lambda, int nspecies, int pusher) {
+  int rc = adjoint_args(g, adj, species, lambda, nspecies, pusher);
+  if (rc) return rc;
+  const int64_t need = (int64_t)coef_partial_blocks(g->mesh) * PIC_MAX_M;
+  if (need > g->partial_cap) {
+    (void)hipStreamSynchronize(g->stream);
+    if (g->partial) (void)hipFree(g->partial);
+    g->partial = nullptr;
+    g->partial_cap = 0;
+    if (hipMalloc((void**)&g->partial, (size_t)need * sizeof(double)) != hipSuccess)
+      return set_error(PIC_ENOMEM, "cannot allocate the coefficient-gradient scratch");
+    g->partial_cap = need;
+  }
+  return adjoint_body(g, adj, species, lambda, nspecies, pusher, g->partial);
+}
+
+int pic_adjoint_step_noalloc(pic_grid* g, const pic_adjoint* adj, const pic_particles* const* species,
+                             pic_particles* const* lambda, int nspecies, int pusher) {
+  int rc = adjoint_args(g, adj, species, lambda, nspecies, pusher);
+  if (rc) return rc;
+  const int64_t need = (int64_t)coef_partial_blocks(g->mesh) * PIC_MAX_M;
+  if (need > kNoAllocDoubles)
+    return set_error(PIC_EUNSUPPORTED,
+                     "the allocation-free adjoint step needs %lld doubles of scratch for this mesh; it holds %lld "
+                     "(%lld reduction blocks of %d x1 rows)",
+                     (long long)need, (long long)kNoAllocDoubles, (long long)(kNoAllocDoubles / PIC_MAX_M), 8);
+  if (!g->noalloc) return set_error(PIC_EHIP, "the adjoint scratch has no device address");
+  return adjoint_body(g, adj, species, lambda, nspecies, pusher, g->noalloc);
 }
 
 int pic_set_shape(pic_grid* g, int order) {
