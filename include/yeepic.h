@@ -51,10 +51,17 @@ typedef enum {
   PIC_ESHAPE = -4,        /* mesh shape or alignment not supported */
   PIC_ENOMEM = -5,        /* device allocation failed */
   PIC_EUNSUPPORTED = -6,  /* valid request outside what is implemented */
-  PIC_ENONFINITE = -7     /* a non-finite value was found */
+  PIC_ENONFINITE = -7,    /* a non-finite value was found */
+  PIC_ENOCONV = -8        /* an exact push's proper-time solve hit its iteration cap */
 } pic_status;
 
 typedef enum { PIC_FP64 = 0, PIC_FP32_FIELDS = 1 } pic_precision;
+/* How the on-chip tile currents of a 3D deposit reach J (Sec. 3.3 current):
+ * added with atomics in whatever order the tiles finish (the default), or
+ * stored per tile and summed per node in a fixed order, so that the current,
+ * and every field and particle state computed from it, is the same bit for
+ * bit from run to run. */
+typedef enum { PIC_DEPOSIT_ATOMIC = 0, PIC_DEPOSIT_DETERMINISTIC = 1 } pic_deposit_mode;
 /* Pushers (Sec. 1, Sec. 4.1): Boris; the exact constant-field (analytic)
  * pusher; Higuera-Cary (the published method the paper cites and uses in its
  * single-particle runs: the Boris splitting with the rotation at the Lorentz
@@ -199,13 +206,33 @@ int pic_gather_push(pic_grid *g, pic_particles *p, int pusher, double *const x_o
 int pic_set_shape(pic_grid *g, int order);
 
 /* ---- current (Sec. 3.3) ----------------------------------------------------
- * Adds the charge-conserving (Esirkepov, linear shape) current J^{n+1/2} of
- * particles that moved from x_old to p->x (less than one cell per step; the
- * periodic wrap is undone by minimum image) to the grid's J.  If zero_first
- * is non-zero J is cleared first.  J keeps the deposited current for every
- * C^B: the x1 correction of Eq. (correction) is applied where Ampere's law
- * reads J (see pic_advance_E and pic_current_correction). */
+ * Adds the charge-conserving (Esirkepov) current J^{n+1/2} of particles that
+ * moved from x_old to p->x (less than one cell per step; the periodic wrap is
+ * undone by minimum image) to the grid's J, with the grid's particle shape.
+ * If zero_first is non-zero J is cleared first.  J keeps the deposited
+ * current for every C^B: the x1 correction of Eq. (correction) is applied
+ * where Ampere's law reads J (see pic_advance_E and pic_current_correction).
+ * On a 3D grid the (x_old, x) pairs are counting-sorted by the 8^3-cell tile
+ * of x_old into library scratch (grow-only, 52 bytes per particle) and each
+ * tile's current is summed on chip in 64-bit fixed point whose quantum is
+ * set per tile from its particle count, so that no sum can overflow; FP64
+ * grids keep two words per node, making each tile's sum exact before one
+ * final rounding (see pic_step_n).  The caller's arrays are not reordered.
+ * 2D grids deposit each particle with global atomics.  PIC_EUNSUPPORTED for
+ * a species of 2^31 or more particles on a 3D grid, and for a 2D grid in the
+ * deterministic mode. */
 int pic_deposit_J(pic_grid *g, const pic_particles *p, double *const x_old[3], int zero_first);
+
+/* Deposit mode of every later 3D deposit (pic_deposit_J, pic_step_n):
+ * PIC_DEPOSIT_ATOMIC (default) or PIC_DEPOSIT_DETERMINISTIC (pic_deposit_mode).
+ * The deterministic mode keeps a staging array of 3 (8 + 2m + 3)^3 doubles
+ * per tile (m the drift margin of the sort interval; about 103 bytes per
+ * cell at the default interval), grow-only; each tile's current is
+ * deterministic already (integer sums), and the node sums over the tiles
+ * covering a node are taken in a fixed order.  Particles that move faster
+ * than c (invalid input) still add through atomics.  PIC_EINVAL for another
+ * value. */
+int pic_set_deposit_mode(pic_grid *g, int mode);
 
 /* ---- the step loop ----------------------------------------------------------
  * nsteps times: [clear J], for each species gather + push + position update
@@ -225,6 +252,17 @@ int pic_deposit_J(pic_grid *g, const pic_particles *p, double *const x_old[3], i
  * order at the end: the results equal those of pushing in place, bit for bit. */
 int pic_step_n(pic_grid *g, pic_particles *const *species, int nspecies, int nsteps,
                int pusher, int deposit);
+/* The on-chip tile current of a 3D deposit (pic_step_n, pic_deposit_J):
+ * every Esirkepov contribution is at most |q w| (the particle moves less than
+ * c dt), and a node receives at most one per particle of the tile, so with
+ * the quantum 2^(e - 61), e = floor(log2(count |q w|)), count the tile's
+ * particles, no node sum can exceed 2^62: the 64-bit accumulator cannot
+ * overflow for any load; a denser tile only has a coarser quantum.  FP32
+ * grids keep one word per node (quantum below 1e-15 |q w| at 8 particles per
+ * cell); FP64 grids add a second word holding each contribution's rounding
+ * residual, so the tile sum is exact to 2^-(63 - bitlength(count)) of the
+ * quantum.  Tile sorts index particles with 32-bit offsets: PIC_EUNSUPPORTED
+ * for a species of 2^31 or more particles. */
 /* One vacuum step (no deposit) out of place: gather + push + position update
  * of each species at the grid's fields (particles advanced in place), then
  * the fused sweep (Eq. maxwell, App. B operators) from the grid's fields
@@ -316,8 +354,16 @@ int pic_adjoint_step_noalloc(pic_grid *g, const pic_adjoint *adj, const pic_part
  * Waits for the grid's stream and reports a pending HIP error. */
 int pic_sync(pic_grid *g);
 /* Scans fields and the given particles for non-finite values and positions
- * outside the periodic box; returns PIC_ENONFINITE if any (synchronous). */
+ * outside the periodic box; returns PIC_ENONFINITE if any (synchronous).
+ * Then reports, and clears, the grid's count of exact pushes (any call, any
+ * species) whose proper-time solve t(tau) = dt ended at the iteration cap
+ * instead of converging since the last check: PIC_ENOCONV if non-zero (the
+ * pushed momentum of such a particle is not the exact map's). */
 int pic_check(pic_grid *g, const pic_particles *p);
+/* Iteration cap of the exact pusher's proper-time solve (1..1000, default
+ * 100; it converges in 3-12 iterations for fields up to 1e4 at dt = dx1/2).
+ * PIC_EINVAL outside the range. */
+int pic_set_exact_iterations(pic_grid *g, int max_iter);
 /* Effective coefficient widths after trimming (for tests and reports). */
 int pic_grid_widths(const pic_grid *g, int *ME, int *MB);
 void pic_destroy(pic_grid *g);

@@ -20,8 +20,9 @@ PIC_MAX_M = 16
 PIC_PUSH_BORIS, PIC_PUSH_ANALYTIC, PIC_PUSH_HC = 0, 1, 2
 PIC_TARGET_E, PIC_TARGET_B, PIC_TARGET_XU, PIC_TARGET_YEET_E, PIC_TARGET_YEET_B = 0, 1, 2, 3, 4
 STATUS = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ECFL", -3: "PIC_EHIP", -4: "PIC_ESHAPE",
-          -5: "PIC_ENOMEM", -6: "PIC_EUNSUPPORTED", -7: "PIC_ENONFINITE"}
+          -5: "PIC_ENOMEM", -6: "PIC_EUNSUPPORTED", -7: "PIC_ENONFINITE", -8: "PIC_ENOCONV"}
 PUSHERS = {"boris": PIC_PUSH_BORIS, "analytic": PIC_PUSH_ANALYTIC, "hc": PIC_PUSH_HC}
+PIC_DEPOSIT_ATOMIC, PIC_DEPOSIT_DETERMINISTIC = 0, 1
 
 
 class YeePICError(RuntimeError):
@@ -54,7 +55,7 @@ EXPORTS = ["pic_design_coeffs", "pic_init_grid", "pic_set_fields", "pic_advance_
            "pic_field_sweep", "pic_gather_push", "pic_deposit_J", "pic_step_n", "pic_sync", "pic_check",
            "pic_grid_widths", "pic_destroy", "pic_last_error", "pic_set_sort_interval", "pic_adjoint_step", "pic_step_to",
            "pic_current_correction", "pic_set_shape", "pic_move_window", "pic_window",
-           "pic_adjoint_step_noalloc"]
+           "pic_adjoint_step_noalloc", "pic_set_deposit_mode", "pic_set_exact_iterations"]
 
 
 def lib():
@@ -78,6 +79,8 @@ def lib():
         L.pic_step_n.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(_Particles)), i, i, i, i]
         L.pic_set_sort_interval.argtypes = [vp, i]
         L.pic_set_shape.argtypes = [vp, i]
+        L.pic_set_deposit_mode.argtypes = [vp, i]
+        L.pic_set_exact_iterations.argtypes = [vp, i]
         PP = ctypes.POINTER(ctypes.POINTER(_Particles))
         L.pic_move_window.argtypes = [vp, ctypes.c_int64, PP, i]
         L.pic_window.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -296,6 +299,14 @@ class Grid:
         o, m = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().pic_window(self._h, ctypes.byref(o), ctypes.byref(m)))
         return o.value, m.value
+
+    def set_deposit_mode(self, deterministic):
+        """pic_set_deposit_mode: fixed-order (deterministic) or atomic tile flush."""
+        _check(lib().pic_set_deposit_mode(self._h, PIC_DEPOSIT_DETERMINISTIC if deterministic else PIC_DEPOSIT_ATOMIC))
+
+    def set_exact_iterations(self, max_iter):
+        """pic_set_exact_iterations: the exact pusher's iteration cap."""
+        _check(lib().pic_set_exact_iterations(self._h, int(max_iter)))
 
     def set_sort_interval(self, steps):
         _check(lib().pic_set_sort_interval(self._h, int(steps)))

@@ -282,9 +282,10 @@ __device__ __forceinline__ void apply_F_dual(const Dual E[3], const Dual B[3], d
 // Reverse of analytic(): u is the input momentum, lun the cotangent of the
 // output momentum; returns the cotangents of u, E and B.
 __device__ void analytic_vjp(const double u[3], const double E[3], const double B[3], double qm, double dt,
-                             const double lun[3], double lu[3], double lE[3], double lB[3]) {
+                             const double lun[3], double lu[3], double lE[3], double lB[3], int max_iter) {
   ExactState st;
-  const double tau_s = analytic_solve(u, E, B, qm, dt, st);
+  bool conv;  // the forward recompute of the same push counts a failed solve
+  const double tau_s = analytic_solve(u, E, B, qm, dt, st, max_iter, conv);
   for (int dir = 0; dir < 9; ++dir) {
     Dual ud[3], Ed[3], Bd[3];
     for (int c = 0; c < 3; ++c) {
@@ -412,7 +413,7 @@ __global__ __launch_bounds__(256) void adjoint_push_kernel(AdjFields F, Mesh m, 
   if (PUSH == PIC_PUSH_BORIS)
     boris(un, E, B, qm, dt);
   else
-    analytic(un, E, B, qm, dt);
+    analytic(un, E, B, qm, dt, m);
   const double gn = sqrt(1.0 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
   double lx[3] = {lx1[p], lx2[p], NDIM == 3 ? lx3[p] : 0.0};
   // x_d' = x_d + dt u'_d/gamma' for d < NDIM (the wrap is a constant shift)
@@ -425,7 +426,7 @@ __global__ __launch_bounds__(256) void adjoint_push_kernel(AdjFields F, Mesh m, 
   if (PUSH == PIC_PUSH_BORIS)
     boris_vjp(u, E, B, qm, dt, lun, lu, lE, lB);
   else
-    analytic_vjp(u, E, B, qm, dt, lun, lu, lE, lB);
+    analytic_vjp(u, E, B, qm, dt, lun, lu, lE, lB, m.exact_iters);
   // reverse of the gather
   const Axis a0 = axis(x[0], m.idx1, 0.0, m.n1), ah = axis(x[0], m.idx1, 0.5, m.n1);
   const Axis b0 = axis(x[1], m.idx2, 0.0, m.n2), bh = axis(x[1], m.idx2, 0.5, m.n2);

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <climits>
 #include <cstring>
 #include <mutex>
 #include <utility>
@@ -43,6 +44,11 @@ struct pic_grid {
   void* alt[6] = {};  // second field set for the out-of-place sweep
   hipStream_t stream = nullptr;
   int* d_flag = nullptr;
+  int* d_noconv = nullptr;  // exact pushes whose proper-time solve hit the iteration cap
+  int deposit_mode = PIC_DEPOSIT_ATOMIC;
+  double* stage = nullptr;  // deterministic mode: the tiles' staged currents (grow-only)
+  size_t stage_cap = 0;
+  SortState dsort;  // tile sort of (x_old, x_new) for pic_deposit_J on a 3D grid
   double* xo[3] = {nullptr, nullptr, nullptr};  // x^n scratch of the unsorted deposit path (grow-only)
   int64_t xo_cap = 0;
   int sort_every = 3;  // 3: the 64-bit tile current then fits three workgroups per CU
@@ -297,6 +303,37 @@ static int ensure_sort(pic_grid* g, SortState& st, int64_t np, int ntiles, bool 
   return PIC_OK;
 }
 
+// Deterministic deposit mode: staging for every tile's current, and the
+// limits of the fixed-order node reduction (tiles and periodic images per
+// direction that may cover one node).
+static int ensure_stage(pic_grid* g, const TileGeom& tg) {
+  const int n[3] = {(int)g->n[0], (int)g->n[1], (int)g->n[2]};
+  for (int d = 0; d < 3; ++d) {
+    const int reach = (tg.m[d] + 2 + tg.t[d] - 1) / tg.t[d] + 1;
+    const int cand = std::min(tg.nt[d], 2 * reach + 1);
+    if (cand > 16 || cand * (tg.r[d] / n[d] + 1) > 64)
+      return set_error(PIC_EUNSUPPORTED, "deterministic deposit: tile window too wide for the mesh along x%d", d + 1);
+  }
+  const size_t need = stage_doubles(tg);
+  if (need <= g->stage_cap) return PIC_OK;
+  (void)hipStreamSynchronize(g->stream);
+  if (g->stage) (void)hipFree(g->stage);
+  g->stage = nullptr;
+  g->stage_cap = 0;
+  if (hipMalloc((void**)&g->stage, need * sizeof(double)) != hipSuccess)
+    return set_error(PIC_ENOMEM, "cannot allocate %zu bytes of current staging", need * sizeof(double));
+  g->stage_cap = need;
+  return PIC_OK;
+}
+
+// Tile sorts index particles with 32-bit offsets.
+static int check_sortable(const pic_particles* p) {
+  if (p->np > (int64_t)INT32_MAX)
+    return set_error(PIC_EUNSUPPORTED, "a tile-sorted species holds at most 2^31 - 1 particles (got %lld)",
+                     (long long)p->np);
+  return PIC_OK;
+}
+
 }  // namespace yeepic
 
 using namespace yeepic;
@@ -374,6 +411,8 @@ int pic_init_grid(const pic_grid_desc* d, pic_grid** out) {
   m.L1 = m.n1 * m.dx1;
   m.L2 = m.n2 * m.dx2;
   m.L3 = m.n3 * m.dx3;
+  m.exact_iters = 100;
+  m.noconv = nullptr;
   const size_t bytes = (size_t)cells * g->elem;
   for (int c = 0; c < 6; ++c) {
     if (hipMalloc(&g->alt[c], bytes) != hipSuccess) {
@@ -385,6 +424,12 @@ int pic_init_grid(const pic_grid_desc* d, pic_grid** out) {
     pic_destroy(g);
     return set_error(PIC_ENOMEM, "cannot allocate the flag word");
   }
+  if (hipMalloc((void**)&g->d_noconv, sizeof(int)) != hipSuccess ||
+      hipMemset(g->d_noconv, 0, sizeof(int)) != hipSuccess) {
+    pic_destroy(g);
+    return set_error(PIC_ENOMEM, "cannot allocate the pusher convergence counter");
+  }
+  m.noconv = g->d_noconv;
   g->noalloc = scratch_on_device();
   if (!g->noalloc) {
     const int rc = PIC_EHIP;
@@ -494,6 +539,13 @@ int pic_deposit_J(pic_grid* g, const pic_particles* p, double* const x_old[3], i
   if (!x_old) return set_error(PIC_EINVAL, "x_old is NULL");
   for (int d = 0; d < g->ndim; ++d)
     if (!x_old[d]) return set_error(PIC_EINVAL, "x_old[%d] is NULL", d);
+  if (g->ndim != 3) {
+    if (g->deposit_mode == PIC_DEPOSIT_DETERMINISTIC)
+      return set_error(PIC_EUNSUPPORTED, "the deterministic deposit covers 3D grids");
+  } else {
+    rc = check_sortable(p);
+    if (rc) return rc;
+  }
   if (zero_first) {
     const size_t bytes = (size_t)g->n[0] * g->n[1] * g->n[2] * g->elem;
     for (int c = 0; c < 3; ++c) {
@@ -501,7 +553,33 @@ int pic_deposit_J(pic_grid* g, const pic_particles* p, double* const x_old[3], i
       if (e != hipSuccess) return hip_fail(e, "clear J");
     }
   }
-  return launch_deposit(g->prec, g->mesh, g->J, *p, x_old, g->dt, g->stream);
+  if (g->ndim != 3 || p->np == 0) return launch_deposit(g->prec, g->mesh, g->J, *p, x_old, g->dt, g->stream);
+  // 3D: counting sort of (x_old, x) by the tile of x_old, then the tile
+  // kernel accumulates each tile's current on chip (moves below one cell, so
+  // the window needs no drift margin)
+  const TileGeom tg = make_tile_geom(g->mesh, g->dt, 1);
+  rc = ensure_sort(g, g->dsort, p->np, tg.ntiles, false);
+  double* stage = nullptr;
+  if (rc == PIC_OK && g->deposit_mode == PIC_DEPOSIT_DETERMINISTIC) {
+    rc = ensure_stage(g, tg);
+    stage = g->stage;
+  }
+  if (rc) return rc;
+  pic_particles pairs = *p;  // keys from x_old; x_new travels as the payload
+  pic_particles sorted = *p;
+  for (int d = 0; d < 3; ++d) {
+    pairs.x[d] = x_old[d];
+    pairs.u[d] = p->x[d];
+    sorted.x[d] = g->dsort.xs[d];
+    sorted.u[d] = g->dsort.us[d];
+  }
+  pairs.id = nullptr;
+  sorted.id = nullptr;
+  SortState& st = g->dsort;
+  rc = launch_tile_sort(g->mesh, tg, pairs, sorted, st.keys, st.counts, st.offsets, st.cursors, st.segsum,
+                        g->stream);
+  if (rc) return rc;
+  return launch_tile_deposit(g->prec, g->mesh, tg, g->J, st.offsets, sorted, g->dt, stage, g->stream);
 }
 
 int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nsteps, int pusher, int deposit) {
@@ -517,6 +595,8 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
   if (deposit) {
     if (!(g->J[0] && g->J[1] && g->J[2])) return set_error(PIC_EINVAL, "deposit requested without J");
     if (!ampere_is_yee(g) && g->corr_status) return correction_error(g);
+    if (g->ndim != 3 && g->deposit_mode == PIC_DEPOSIT_DETERMINISTIC)
+      return set_error(PIC_EUNSUPPORTED, "the deterministic deposit covers 3D grids");
   }
   // scratch for x^n of the largest species (kept across calls)
   int64_t npmax = 0;
@@ -544,11 +624,17 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
   // 3D plasma: particles sorted by tile, current accumulated on chip
   const bool tiled = deposit && g->ndim == 3;
   TileGeom tg = {};
+  double* stage = nullptr;
   if (tiled) {
     tg = make_tile_geom(g->mesh, g->dt, g->sort_every);
+    for (int s = 0; s < nspecies && rc == PIC_OK; ++s) rc = check_sortable(species[s]);
     if ((int)g->sorts.size() < nspecies) g->sorts.resize(nspecies);
     for (int s = 0; s < nspecies && rc == PIC_OK; ++s)
       rc = ensure_sort(g, g->sorts[s], species[s]->np, tg.ntiles, species[s]->id != nullptr);
+    if (rc == PIC_OK && g->deposit_mode == PIC_DEPOSIT_DETERMINISTIC) {
+      rc = ensure_stage(g, tg);
+      stage = g->stage;
+    }
     if (rc) return rc;
   }
   // 3D vacuum: each large species is pushed as a tile-ordered copy, so that
@@ -569,6 +655,8 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
     vuse.assign(nspecies, 0);
     for (int s = 0; s < nspecies && rc == PIC_OK; ++s) {
       if (species[s]->np < kVacSortMin) continue;
+      rc = check_sortable(species[s]);
+      if (rc) break;
       SortState& A = g->vsort_a[s];
       SortState& B = g->vsort_b[s];
       rc = ensure_sort(g, A, species[s]->np, tg.ntiles, true);
@@ -615,7 +703,7 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
         }
         if (rc == PIC_OK)
           rc = launch_tile_push(g->prec, g->mesh, tg, cur, cur + 3, g->J, st.offsets, src, *species[s], pusher,
-                                g->dt, g->stream);
+                                g->dt, stage, g->stream);
         continue;
       }
       if (vac && vuse[s]) {
@@ -839,8 +927,32 @@ int pic_check(pic_grid* g, const pic_particles* p) {
   if (e != hipSuccess) return hip_fail(e, "check: read flag");
   e = hipStreamSynchronize(g->stream);
   if (e != hipSuccess) return hip_fail(e, "check: synchronize");
+  int noconv = 0;
+  e = hipMemcpyAsync(&noconv, g->d_noconv, sizeof(int), hipMemcpyDeviceToHost, g->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(g->d_noconv, 0, sizeof(int), g->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+  if (e != hipSuccess) return hip_fail(e, "check: read the convergence counter");
   if (flag & 1) return set_error(PIC_ENONFINITE, "non-finite field value");
   if (flag & 2) return set_error(PIC_ENONFINITE, "particle outside the box or non-finite momentum");
+  if (noconv > 0)
+    return set_error(PIC_ENOCONV,
+                     "%d exact pushes since the last check ended their proper-time solve at the iteration cap (%d)",
+                     noconv, g->mesh.exact_iters);
+  return PIC_OK;
+}
+
+int pic_set_exact_iterations(pic_grid* g, int max_iter) {
+  if (!g) return set_error(PIC_EINVAL, "grid is NULL");
+  if (max_iter < 1 || max_iter > 1000) return set_error(PIC_EINVAL, "iteration cap must be in 1..1000");
+  g->mesh.exact_iters = max_iter;
+  return PIC_OK;
+}
+
+int pic_set_deposit_mode(pic_grid* g, int mode) {
+  if (!g) return set_error(PIC_EINVAL, "grid is NULL");
+  if (mode != PIC_DEPOSIT_ATOMIC && mode != PIC_DEPOSIT_DETERMINISTIC)
+    return set_error(PIC_EINVAL, "bad deposit mode");
+  g->deposit_mode = mode;
   return PIC_OK;
 }
 
@@ -947,6 +1059,9 @@ void pic_destroy(pic_grid* g) {
   for (SortState& st : g->vsort_a) free_sort(st);
   for (SortState& st : g->vsort_b) free_sort(st);
   if (g->d_flag) (void)hipFree(g->d_flag);
+  if (g->d_noconv) (void)hipFree(g->d_noconv);
+  if (g->stage) (void)hipFree(g->stage);
+  free_sort(g->dsort);
   if (g->partial) (void)hipFree(g->partial);
   if (g->corr_taps) (void)hipFree(g->corr_taps);
   if (g->Jc) (void)hipFree(g->Jc);

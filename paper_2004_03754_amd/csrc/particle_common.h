@@ -232,9 +232,11 @@ struct ExactState {
 };
 
 // Solves t(tau) = dt for the exact push of u in (E, B); returns tau and the
-// state the exponential is applied to.
+// state the exponential is applied to.  ``conv`` is set false when the solve
+// ends by exhausting ``max_iter`` iterations instead of by one of its
+// stopping tests.
 __device__ __forceinline__ double analytic_solve(const double u[3], const double E[3], const double B[3], double qm,
-                                                 double dt, ExactState& st) {
+                                                 double dt, ExactState& st, int max_iter, bool& conv) {
   const double E2 = E[0] * E[0] + E[1] * E[1] + E[2] * E[2];
   const double B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
   const double EB = E[0] * B[0] + E[1] * B[1] + E[2] * B[2];
@@ -281,13 +283,17 @@ __device__ __forceinline__ double analytic_solve(const double u[3], const double
     }
   }
   if (kw * fabs(tau) > 50.0) tau = copysign(50.0 / kw, dt);
-  for (int it = 0; it < 100; ++it) {
+  conv = false;
+  for (int it = 0; it < max_iter; ++it) {
     const ExpCoef e = exp_coef(k2, w2, tau);
     const double t = e.a1 * U0[0] + e.A1 * V1[0] + e.a3 * V2[0] + e.A3 * V3[0];
     const double g = e.a0 * U0[0] + e.a1 * V1[0] + e.a2 * V2[0] + e.a3 * V3[0];
     const bool fin = isfinite(t) && isfinite(g) && g > 0.0;
     const double f = t - dt;
-    if (fin && fabs(f) <= 1e-16 * fabs(dt)) break;
+    if (fin && fabs(f) <= 1e-16 * fabs(dt)) {
+      conv = true;
+      break;
+    }
     // keep the root bracketed; a non-finite value lies beyond it, away from 0
     if (fin ? f > 0.0 : dt > 0.0) hi = tau; else lo = tau;
     // Far from the root (t/dt outside (1/2, 2)) the step is Newton on
@@ -304,7 +310,10 @@ __device__ __forceinline__ double analytic_solve(const double u[3], const double
       // a Newton correction below the rounding of tau ends the solve: t is
       // then at its rounding floor, which can stay above 1e-16 dt
       const double step = f / g;
-      if (fabs(step) <= 1e-15 * fabs(tau)) break;
+      if (fabs(step) <= 1e-15 * fabs(tau)) {
+        conv = true;
+        break;
+      }
       nx = tau - step;
     } else {
       nx = tau - log(ratio) * (t / g);
@@ -312,15 +321,26 @@ __device__ __forceinline__ double analytic_solve(const double u[3], const double
     if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
     const bool small = fabs(nx - tau) <= 1e-15 * fabs(tau);
     tau = nx;
-    if (small) break;
+    if (small) {
+      conv = true;
+      break;
+    }
   }
   return tau;
 }
 
-__device__ __forceinline__ void analytic(double u[3], const double E[3], const double B[3], double qm,
-                                         double dt) {
+// Counts an exact push whose proper-time solve did not converge (read and
+// cleared by pic_check).
+__device__ __forceinline__ void note_noconv(const Mesh& m) {
+  if (m.noconv) atomicAdd(m.noconv, 1);
+}
+
+__device__ __forceinline__ void analytic(double u[3], const double E[3], const double B[3], double qm, double dt,
+                                         const Mesh& m) {
   ExactState st;
-  const double tau = analytic_solve(u, E, B, qm, dt, st);
+  bool conv;
+  const double tau = analytic_solve(u, E, B, qm, dt, st, m.exact_iters, conv);
+  if (!conv) note_noconv(m);
   const ExpCoef e = exp_coef(st.k2, st.w2, tau);
   for (int d = 0; d < 3; ++d)
     u[d] = e.a0 * st.U0[d + 1] + e.a1 * st.V1[d + 1] + e.a2 * st.V2[d + 1] + e.a3 * st.V3[d + 1];

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void gather_push_kernel(const T* __restrict__ 
   else if (PUSH == PIC_PUSH_HC)
     higuera_cary(u, E, B, qm, dt);
   else
-    analytic(u, E, B, qm, dt);
+    analytic(u, E, B, qm, dt, m);
   const double ig = dt / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   if (o1) {
     o1[p] = x[0];

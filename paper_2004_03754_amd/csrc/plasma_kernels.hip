@@ -6,6 +6,9 @@
 //   tile_scatter counting-sort scatter of x, u (and ids) into scratch
 //   tile_push    per tile: gather + push + position update of its particles,
 //                Esirkepov current into an LDS tile, one atomic flush per node
+//   tile_deposit the same current for given old and new positions
+//   reduce_stage deterministic mode: the tiles' currents are stored, not
+//                added, and summed per node in a fixed order
 //
 // A tile is tx x ty x tz cells.  Particles stay sorted for S steps; since
 // |v| < c a particle drifts at most ceil((S-1) dt/dx_d) cells (the margin m_d)
@@ -159,39 +162,170 @@ __global__ __launch_bounds__(256) void tile_scatter_kernel(const double* __restr
   if (id) sid[q] = id[p];
 }
 
-// The tile's current is accumulated in LDS as 64-bit fixed point: integer
-// LDS adds are an order of magnitude faster than float ones on this part,
-// and the sum is exact.  ``scale`` = 2^S maps the largest single contribution
-// |q w dx_d/dt| to 2^47, which leaves room for 2^15 such contributions per
-// node and rounds each one to 2^-47 of the largest.
-__device__ __forceinline__ void lds_add(unsigned long long* p, double v, double scale) {
-  atomicAdd(p, (unsigned long long)llrint(v * scale));
+// ---------------------------------------------------------------------------
+// The tile current: 64-bit fixed point in LDS.  Integer LDS adds are an order
+// of magnitude faster than float ones on this part, and integer sums do not
+// depend on the order of the adds.
+//
+// Scale.  Every Esirkepov contribution is at most |q w| in magnitude: it is
+// -q w (dx_d/dt) times a running sum of shape differences bounded by
+// |dx_d^{n+1} - dx_d^n|/dx_d <= dt |v_d|/dx_d < dt/dx_d (|v| < c), times a
+// transverse weight in [0, 1].  A node of a tile receives at most one
+// contribution per component from each of the tile's ``count`` particles, so
+// with the quantum q_t = 2^(e - 61), e = floor(log2(count |q w|)), no node
+// sum can exceed 2^62 in magnitude: the accumulator cannot overflow for any
+// particle load, and each contribution is rounded to q_t.
+//
+// FP64 grids keep two words per node: hi = round(v/q_t) and the rounding
+// residual in units of q_t 2^-L, lo = round((v/q_t - hi) 2^L), L = 63 -
+// bitlength(count) (again no overflow).  The node value (hi + lo 2^-L) q_t is
+// then the sum of the FP64 contributions to within 2^-L q_t per contribution:
+// the tile current equals the exact sum of its contributions rounded about
+// once, whatever the order of the adds.
+// ---------------------------------------------------------------------------
+struct TileScale {
+  double s, us;    // 1/q_t and q_t
+  double sl, usl;  // 2^L and q_t 2^-L (two-word accumulation)
+};
+
+__device__ __forceinline__ TileScale tile_scale(int count, double qw_abs) {
+  const double cq = (double)count * qw_abs;
+  const int e = cq > 0.0 ? ilogb(cq) : 0;
+  const int L = 63 - (32 - __clz(count > 0 ? count : 1));
+  TileScale t;
+  t.s = ldexp(1.0, 61 - e);
+  t.us = ldexp(1.0, e - 61);
+  t.sl = ldexp(1.0, L);
+  t.usl = ldexp(1.0, e - 61 - L);
+  return t;
 }
 
-template <typename T, int PUSH, int ORDER>
+template <bool TWO>
+__device__ __forceinline__ void acc_add(unsigned long long* hi, unsigned long long* lo, double v, const TileScale& ts) {
+  const double y = v * ts.s;  // exact: a power-of-two scaling, |y| < 2^62
+  const long long h = llrint(y);
+  atomicAdd(hi, (unsigned long long)h);
+  if (TWO) atomicAdd(lo, (unsigned long long)llrint((y - (double)h) * ts.sl));  // y - h is exact
+}
+
+template <bool TWO>
+__device__ __forceinline__ double acc_value(unsigned long long hi, unsigned long long lo, const TileScale& ts) {
+  double v = (double)(long long)hi * ts.us;
+  if (TWO) v += (double)(long long)lo * ts.usl;
+  return v;
+}
+
+// Geometry of one tile's LDS current: origin m + 1 nodes below the tile.
+struct TileWin {
+  int lo[3];
+  int r0, r1, R;
+};
+
+__device__ __forceinline__ TileWin tile_window(int tile, const TileGeom& tg) {
+  TileWin w;
+  const int tx = tile % tg.nt[0], ty = (tile / tg.nt[0]) % tg.nt[1], tz = tile / (tg.nt[0] * tg.nt[1]);
+  w.lo[0] = tx * tg.t[0];
+  w.lo[1] = ty * tg.t[1];
+  w.lo[2] = tz * tg.t[2];
+  w.r0 = tg.r[0];
+  w.r1 = tg.r[1];
+  w.R = tg.r[0] * tg.r[1] * tg.r[2];
+  return w;
+}
+
+// Esirkepov current of one particle moving from xo to xn (Sec. 3.3): into
+// the tile's LDS accumulator when its stencil lies inside the tile window,
+// else (only for input moving faster than c) through global atomics.
+template <typename T, int ORDER, bool TWO>
+__device__ __forceinline__ void deposit_one(const double xo[3], const double xn[3], const Mesh& m,
+                                            const TileGeom& tg, const TileWin& w, unsigned long long* jh,
+                                            unsigned long long* jl, const TileScale& ts, double c1, double c2,
+                                            double c3, T* const Jg[3]) {
+  constexpr int K = ORDER + 2;  // stencil nodes per direction
+  const int n[3] = {m.n1, m.n2, m.n3};
+  const ShapeK<K> sh[3] = {shape_o<ORDER>(xo[0], xn[0], m.idx1, m.L1), shape_o<ORDER>(xo[1], xn[1], m.idx2, m.L2),
+                           shape_o<ORDER>(xo[2], xn[2], m.idx3, m.L3)};
+  // stencil origin relative to the LDS current tile (periodic images folded in)
+  int rel[3];
+  bool inside = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int bb = sh[d].base - w.lo[d];
+    if (bb < -(n[d] / 2)) bb += n[d];
+    if (bb > n[d] / 2) bb -= n[d];
+    rel[d] = bb + tg.m[d] + 1;
+    inside = inside && rel[d] >= 0 && rel[d] + K - 1 < tg.r[d];
+  }
+  if (inside) {
+    const int o = (rel[2] * w.r1 + rel[1]) * w.r0 + rel[0];
+    esirkepov<K>(sh[0], sh[1], sh[2], c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
+      const int i = comp * w.R + o + (c * w.r1 + b) * w.r0 + a;
+      acc_add<TWO>(&jh[i], &jl[i], v, ts);
+    });
+  } else {
+    const size_t pl = (size_t)m.n1 * m.n2;
+    int gw[3][K];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int k = 0; k < K; ++k) gw[d][k] = wrapn(sh[d].base + k, n[d]);
+    esirkepov<K>(sh[0], sh[1], sh[2], c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
+      atomic_add(&Jg[comp][(size_t)gw[2][c] * pl + (size_t)gw[1][b] * m.n1 + gw[0][a]], v);
+    });
+  }
+}
+
+// Clears the tile's accumulator words (1 or 2 per node and component).
+__device__ __forceinline__ void acc_clear(unsigned long long* jh, int words) {
+  for (int i = threadIdx.x; i < words; i += blockDim.x) jh[i] = 0;
+}
+
+// Flush of a tile's current: one global atomic add per non-zero node, or,
+// with ``stage`` (the deterministic mode), a plain store of every node's
+// value into the tile's slot of the staging array, which reduce_stage_kernel
+// then sums in a fixed order.
+template <typename T, bool TWO>
+__device__ __forceinline__ void acc_flush(const unsigned long long* jh, const unsigned long long* jl,
+                                          const TileScale& ts, const TileWin& w, const TileGeom& tg, const Mesh& m,
+                                          int tile, T* const Jg[3], double* stage) {
+  const size_t pl = (size_t)m.n1 * m.n2;
+  for (int i = threadIdx.x; i < 3 * w.R; i += blockDim.x) {
+    const double v = acc_value<TWO>(jh[i], TWO ? jl[i] : 0ull, ts);
+    if (stage) {
+      stage[(size_t)tile * 3 * w.R + i] = v;
+      continue;
+    }
+    if (v == 0.0) continue;
+    const int comp = i / w.R;
+    const int q = i - comp * w.R;
+    const int a = q % w.r0, b = (q / w.r0) % w.r1, c = q / (w.r0 * w.r1);
+    const int gx = wrapn(w.lo[0] + a - tg.m[0] - 1, m.n1);
+    const int gy = wrapn(w.lo[1] + b - tg.m[1] - 1, m.n2);
+    const int gz = wrapn(w.lo[2] + c - tg.m[2] - 1, m.n3);
+    unsafeAtomicAdd(&Jg[comp][(size_t)gz * pl + (size_t)gy * m.n1 + gx], (T)v);
+  }
+}
+
+template <typename T, int PUSH, int ORDER, bool TWO>
 __global__ __launch_bounds__(256) void tile_push_kernel(
     const T* __restrict__ E1, const T* __restrict__ E2, const T* __restrict__ E3, const T* __restrict__ B1,
     const T* __restrict__ B2, const T* __restrict__ B3, T* __restrict__ J1, T* __restrict__ J2, T* __restrict__ J3,
     Mesh m, TileGeom tg, const int* __restrict__ offsets, const double* sx1, const double* sx2, const double* sx3,
     const double* su1, const double* su2, const double* su3, const int64_t* sid, double* dx1, double* dx2,
     double* dx3, double* du1, double* du2, double* du3, int64_t* did, double qm, double qw, double dt,
-    double scale, double unscale) {
+    double* stage) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  // current tile, 3 x r0 r1 r2, fixed point (see lds_add)
-  unsigned long long* jl = reinterpret_cast<unsigned long long*>(lds_raw);
-  const int r0 = tg.r[0], r1 = tg.r[1], r2 = tg.r[2];
-  const int R = r0 * r1 * r2;
+  const TileWin w = tile_window(blockIdx.x, tg);
+  unsigned long long* jh = reinterpret_cast<unsigned long long*>(lds_raw);
+  unsigned long long* jl = jh + 3 * w.R;
   const int tile = blockIdx.x;
   const int beg = offsets[tile], end = offsets[tile + 1];
-  if (end == beg) return;  // uniform: no particles, nothing to add
-  const int tx = tile % tg.nt[0], ty = (tile / tg.nt[0]) % tg.nt[1], tz = tile / (tg.nt[0] * tg.nt[1]);
-  const int lo[3] = {tx * tg.t[0], ty * tg.t[1], tz * tg.t[2]};
-  const int n[3] = {m.n1, m.n2, m.n3};
-  const size_t pl = (size_t)m.n1 * m.n2;
-  for (int i = threadIdx.x; i < 3 * R; i += blockDim.x) jl[i] = 0;
+  T* const Jg[3] = {J1, J2, J3};
+  if (end == beg && !stage) return;  // uniform: no particles, nothing to add
+  const TileScale ts = tile_scale(end - beg, fabs(qw));
+  acc_clear(jh, (TWO ? 6 : 3) * w.R);
   __syncthreads();
   const double c1 = -qw * m.dx1 / dt, c2 = -qw * m.dx2 / dt, c3 = -qw * m.dx3 / dt;
-  T* Jg[3] = {J1, J2, J3};
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
     const double x[3] = {sx1[i], sx2[i], sx3[i]};
     double u[3] = {su1[i], su2[i], su3[i]};
@@ -202,11 +336,10 @@ __global__ __launch_bounds__(256) void tile_push_kernel(
     else if (PUSH == PIC_PUSH_HC)
       higuera_cary(u, E, B, qm, dt);
     else
-      analytic(u, E, B, qm, dt);
+      analytic(u, E, B, qm, dt, m);
     const double ig = dt / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     const double xn[3] = {wrap_pos(x[0] + ig * u[0], m.L1), wrap_pos(x[1] + ig * u[1], m.L2),
                           wrap_pos(x[2] + ig * u[2], m.L3)};
-    constexpr int K = ORDER + 2;  // stencil nodes per direction
     dx1[i] = xn[0];
     dx2[i] = xn[1];
     dx3[i] = xn[2];
@@ -214,89 +347,173 @@ __global__ __launch_bounds__(256) void tile_push_kernel(
     du2[i] = u[1];
     du3[i] = u[2];
     if (sid && sid != did) did[i] = sid[i];
-    const ShapeK<K> sh[3] = {shape_o<ORDER>(x[0], xn[0], m.idx1, m.L1), shape_o<ORDER>(x[1], xn[1], m.idx2, m.L2),
-                             shape_o<ORDER>(x[2], xn[2], m.idx3, m.L3)};
-    // stencil origin relative to the LDS current tile (periodic images folded in)
-    int rel[3];
-    bool inside = true;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      int bb = sh[d].base - lo[d];
-      if (bb < -(n[d] / 2)) bb += n[d];
-      if (bb > n[d] / 2) bb -= n[d];
-      rel[d] = bb + tg.m[d] + 1;
-      inside = inside && rel[d] >= 0 && rel[d] + K - 1 < tg.r[d];
-    }
-    if (inside) {
-      const int o = (rel[2] * r1 + rel[1]) * r0 + rel[0];
-      esirkepov<K>(sh[0], sh[1], sh[2], c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
-        lds_add(&jl[comp * R + o + (c * r1 + b) * r0 + a], v, scale);
-      });
-    } else {  // outside the on-chip tile (rare): global atomics, stencil nodes wrapped once
-      int gw[3][K];
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-#pragma unroll
-        for (int k = 0; k < K; ++k) gw[d][k] = wrapn(sh[d].base + k, n[d]);
-      esirkepov<K>(sh[0], sh[1], sh[2], c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
-        const size_t gidx = (size_t)gw[2][c] * pl + (size_t)gw[1][b] * m.n1 + gw[0][a];
-        atomic_add(&Jg[comp][gidx], v);
-      });
-    }
+    deposit_one<T, ORDER, TWO>(x, xn, m, tg, w, jh, jl, ts, c1, c2, c3, Jg);
   }
   __syncthreads();
-  // flush: one global atomic per non-zero LDS node
-  for (int i = threadIdx.x; i < 3 * R; i += blockDim.x) {
-    const long long acc = (long long)jl[i];
-    if (acc == 0) continue;
-    const T v = (T)((double)acc * unscale);
-    const int comp = i / R;
-    const int q = i - comp * R;
-    const int a = q % r0, b = (q / r0) % r1, c = q / (r0 * r1);
-    const int gx = wrapn(lo[0] + a - tg.m[0] - 1, m.n1);
-    const int gy = wrapn(lo[1] + b - tg.m[1] - 1, m.n2);
-    const int gz = wrapn(lo[2] + c - tg.m[2] - 1, m.n3);
-    unsafeAtomicAdd(&Jg[comp][(size_t)gz * pl + (size_t)gy * m.n1 + gx], v);
+  acc_flush<T, TWO>(jh, jl, ts, w, tg, m, tile, Jg, stage);
+}
+
+// The deposit alone (pic_deposit_J): particles sorted by the tile of their
+// old position, old positions in xo, new ones in xn.
+template <typename T, int ORDER, bool TWO>
+__global__ __launch_bounds__(256) void tile_deposit_kernel(T* __restrict__ J1, T* __restrict__ J2,
+                                                           T* __restrict__ J3, Mesh m, TileGeom tg,
+                                                           const int* __restrict__ offsets, const double* xo1,
+                                                           const double* xo2, const double* xo3, const double* xn1,
+                                                           const double* xn2, const double* xn3, double qw, double dt,
+                                                           double* stage) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const TileWin w = tile_window(blockIdx.x, tg);
+  unsigned long long* jh = reinterpret_cast<unsigned long long*>(lds_raw);
+  unsigned long long* jl = jh + 3 * w.R;
+  const int tile = blockIdx.x;
+  const int beg = offsets[tile], end = offsets[tile + 1];
+  T* const Jg[3] = {J1, J2, J3};
+  if (end == beg && !stage) return;
+  const TileScale ts = tile_scale(end - beg, fabs(qw));
+  acc_clear(jh, (TWO ? 6 : 3) * w.R);
+  __syncthreads();
+  const double c1 = -qw * m.dx1 / dt, c2 = -qw * m.dx2 / dt, c3 = -qw * m.dx3 / dt;
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    const double xo[3] = {xo1[i], xo2[i], xo3[i]};
+    const double xn[3] = {xn1[i], xn2[i], xn3[i]};
+    deposit_one<T, ORDER, TWO>(xo, xn, m, tg, w, jh, jl, ts, c1, c2, c3, Jg);
   }
+  __syncthreads();
+  acc_flush<T, TWO>(jh, jl, ts, w, tg, m, tile, Jg, stage);
+}
+
+// Deterministic mode: J[node] += the staged tile values that land on the
+// node, summed in FP64 over the covering tiles in increasing tile index (per
+// direction) and, within a tile, over its periodic images in increasing
+// window index.  One thread per node and component.
+__device__ __forceinline__ int cover(int i, int d, const TileGeom& tg, int n, int* tl, int* ws, int& nw) {
+  // tiles along direction d whose window holds node i, and the window
+  // indices of every image of i in each; returns the number of tiles
+  const int t = tg.t[d], nt = tg.nt[d], r = tg.r[d], mg = tg.m[d];
+  const int reach = (mg + 2 + t - 1) / t + 1;
+  int ntl = 0;
+  nw = 0;
+  const int c = i / t;
+  const bool all = nt <= 2 * reach + 1;
+  const int first = all ? 0 : c - reach, last = all ? nt - 1 : c + reach;
+  for (int k = first; k <= last; ++k) {
+    const int tt = all ? k : ((k % nt) + nt) % nt;
+    const int base = tt * t - mg - 1;  // node of window index 0
+    int a = ((i - base) % n + n) % n;
+    int cnt = 0;
+    for (; a < r; a += n) {
+      ws[nw + cnt] = a;
+      ++cnt;
+    }
+    if (cnt) {
+      tl[2 * ntl] = tt;
+      tl[2 * ntl + 1] = cnt;
+      nw += cnt;
+      ++ntl;
+    }
+  }
+  return ntl;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void reduce_stage_kernel(T* __restrict__ J1, T* __restrict__ J2,
+                                                           T* __restrict__ J3, Mesh m, TileGeom tg,
+                                                           const double* __restrict__ stage) {
+  const int64_t cells = (int64_t)m.n1 * m.n2 * m.n3;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= 3 * cells) return;
+  const int comp = (int)(g / cells);
+  const int64_t cell = g - comp * cells;
+  const int i = (int)(cell % m.n1), j = (int)((cell / m.n1) % m.n2), k = (int)(cell / ((int64_t)m.n1 * m.n2));
+  constexpr int kMaxT = 16, kMaxW = 64;  // limits checked on the host (ensure_stage)
+  int tx[2 * kMaxT], ty[2 * kMaxT], tz[2 * kMaxT], wx[kMaxW], wy[kMaxW], wz[kMaxW];
+  int nwx, nwy, nwz;
+  const int ntx = cover(i, 0, tg, m.n1, tx, wx, nwx);
+  const int nty = cover(j, 1, tg, m.n2, ty, wy, nwy);
+  const int ntz = cover(k, 2, tg, m.n3, tz, wz, nwz);
+  const int r0 = tg.r[0], r1 = tg.r[1], R = r0 * r1 * tg.r[2];
+  double acc = 0.0;
+  int oz = 0;
+  for (int c = 0; c < ntz; ++c) {
+    int oy = 0;
+    for (int b = 0; b < nty; ++b) {
+      int ox = 0;
+      for (int a = 0; a < ntx; ++a) {
+        const int tile = (tz[2 * c] * tg.nt[1] + ty[2 * b]) * tg.nt[0] + tx[2 * a];
+        const double* s = stage + (size_t)tile * 3 * R + (size_t)comp * R;
+        for (int cz = 0; cz < tz[2 * c + 1]; ++cz)
+          for (int cy = 0; cy < ty[2 * b + 1]; ++cy)
+            for (int cx = 0; cx < tx[2 * a + 1]; ++cx)
+              acc += s[(wz[oz + cz] * r1 + wy[oy + cy]) * r0 + wx[ox + cx]];
+        ox += tx[2 * a + 1];
+      }
+      oy += ty[2 * b + 1];
+    }
+    oz += tz[2 * c + 1];
+  }
+  T* J = comp == 0 ? J1 : (comp == 1 ? J2 : J3);
+  J[cell] = (T)((double)J[cell] + acc);
+}
+
+size_t tile_lds(const TileGeom& tg, bool two) {
+  return sizeof(unsigned long long) * (two ? 6 : 3) * (size_t)tg.r[0] * tg.r[1] * tg.r[2];
 }
 
 template <typename T>
 int run_tile_push(const Mesh& m, const TileGeom& tg, void* const E[3], void* const B[3], void* const J[3],
                   const int* offsets, const pic_particles& src, const pic_particles& dst, int pusher, double dt,
-                  hipStream_t s) {
-  const size_t lds = sizeof(unsigned long long) * 3 * (size_t)tg.r[0] * tg.r[1] * tg.r[2];
+                  double* stage, hipStream_t s) {
+  constexpr bool TWO = sizeof(T) == sizeof(double);
+  const size_t lds = tile_lds(tg, TWO);
   if (lds > 160 * 1024) return set_error(PIC_EUNSUPPORTED, "plasma tile needs %zu bytes of LDS", lds);
   const bool q2 = m.order == 2;
-  auto k = pusher == PIC_PUSH_BORIS ? (q2 ? tile_push_kernel<T, PIC_PUSH_BORIS, 2> : tile_push_kernel<T, PIC_PUSH_BORIS, 1>)
-           : pusher == PIC_PUSH_HC  ? (q2 ? tile_push_kernel<T, PIC_PUSH_HC, 2> : tile_push_kernel<T, PIC_PUSH_HC, 1>)
-                                    : (q2 ? tile_push_kernel<T, PIC_PUSH_ANALYTIC, 2>
-                                          : tile_push_kernel<T, PIC_PUSH_ANALYTIC, 1>);
+  auto k = pusher == PIC_PUSH_BORIS ? (q2 ? tile_push_kernel<T, PIC_PUSH_BORIS, 2, TWO>
+                                          : tile_push_kernel<T, PIC_PUSH_BORIS, 1, TWO>)
+           : pusher == PIC_PUSH_HC  ? (q2 ? tile_push_kernel<T, PIC_PUSH_HC, 2, TWO>
+                                          : tile_push_kernel<T, PIC_PUSH_HC, 1, TWO>)
+                                    : (q2 ? tile_push_kernel<T, PIC_PUSH_ANALYTIC, 2, TWO>
+                                          : tile_push_kernel<T, PIC_PUSH_ANALYTIC, 1, TWO>);
   if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return set_error(PIC_EHIP, "tile push: cannot reserve %zu bytes of LDS", lds);
   const double qm = src.q / src.m, qw = src.q * src.w;
-  // fixed-point scale of the LDS current (see lds_add)
-  const double cmax = std::fabs(qw) * std::fmax(m.dx1, std::fmax(m.dx2, m.dx3)) / dt;
-  const int S = cmax > 0 ? 47 - (int)std::ceil(std::log2(cmax)) : 0;
-  const double scale = std::ldexp(1.0, S), unscale = std::ldexp(1.0, -S);
-#define YP_TP(PUSH)   \
-  do {                \
-    if (q2)           \
-      YP_TP1(PUSH, 2); \
-    else              \
-      YP_TP1(PUSH, 1); \
-  } while (0)
-#define YP_TP1(PUSH, ORD)                                                                                         \
-  hipLaunchKernelGGL((tile_push_kernel<T, PUSH, ORD>), dim3(tg.ntiles), dim3(256), lds, s, (const T*)E[0],     \
-                     (const T*)E[1], (const T*)E[2], (const T*)B[0], (const T*)B[1], (const T*)B[2], (T*)J[0],  \
-                     (T*)J[1], (T*)J[2], m, tg, offsets, src.x[0], src.x[1], src.x[2], src.u[0], src.u[1],     \
-                     src.u[2], src.id, dst.x[0], dst.x[1], dst.x[2], dst.u[0], dst.u[1], dst.u[2], dst.id, qm, qw, \
-                     dt, scale, unscale)
-  if (pusher == PIC_PUSH_BORIS) YP_TP(PIC_PUSH_BORIS);
-  else if (pusher == PIC_PUSH_HC) YP_TP(PIC_PUSH_HC);
-  else YP_TP(PIC_PUSH_ANALYTIC);
-#undef YP_TP
-#undef YP_TP1
-  return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "tile push launch failed");
+  hipLaunchKernelGGL(k, dim3(tg.ntiles), dim3(256), lds, s, (const T*)E[0], (const T*)E[1], (const T*)E[2],
+                     (const T*)B[0], (const T*)B[1], (const T*)B[2], (T*)J[0], (T*)J[1], (T*)J[2], m, tg, offsets,
+                     (const double*)src.x[0], (const double*)src.x[1], (const double*)src.x[2],
+                     (const double*)src.u[0], (const double*)src.u[1], (const double*)src.u[2],
+                     (const int64_t*)src.id, dst.x[0], dst.x[1], dst.x[2], dst.u[0], dst.u[1], dst.u[2], dst.id, qm,
+                     qw, dt, stage);
+  if (hipGetLastError() != hipSuccess) return set_error(PIC_EHIP, "tile push launch failed");
+  if (stage) {
+    const int64_t work = 3 * (int64_t)m.n1 * m.n2 * m.n3;
+    hipLaunchKernelGGL(reduce_stage_kernel<T>, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, (T*)J[0],
+                       (T*)J[1], (T*)J[2], m, tg, (const double*)stage);
+    if (hipGetLastError() != hipSuccess) return set_error(PIC_EHIP, "current reduction launch failed");
+  }
+  return PIC_OK;
+}
+
+template <typename T>
+int run_tile_deposit(const Mesh& m, const TileGeom& tg, void* const J[3], const int* offsets,
+                     const pic_particles& sorted, double dt, double* stage, hipStream_t s) {
+  constexpr bool TWO = sizeof(T) == sizeof(double);
+  const size_t lds = tile_lds(tg, TWO);
+  if (lds > 160 * 1024) return set_error(PIC_EUNSUPPORTED, "deposit tile needs %zu bytes of LDS", lds);
+  auto k = m.order == 2 ? tile_deposit_kernel<T, 2, TWO> : tile_deposit_kernel<T, 1, TWO>;
+  if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return set_error(PIC_EHIP, "tile deposit: cannot reserve %zu bytes of LDS", lds);
+  const double qw = sorted.q * sorted.w;
+  hipLaunchKernelGGL(k, dim3(tg.ntiles), dim3(256), lds, s, (T*)J[0], (T*)J[1], (T*)J[2], m, tg, offsets,
+                     (const double*)sorted.x[0], (const double*)sorted.x[1], (const double*)sorted.x[2],
+                     (const double*)sorted.u[0], (const double*)sorted.u[1], (const double*)sorted.u[2], qw, dt, stage);
+  if (hipGetLastError() != hipSuccess) return set_error(PIC_EHIP, "tile deposit launch failed");
+  if (stage) {
+    const int64_t work = 3 * (int64_t)m.n1 * m.n2 * m.n3;
+    hipLaunchKernelGGL(reduce_stage_kernel<T>, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, (T*)J[0],
+                       (T*)J[1], (T*)J[2], m, tg, (const double*)stage);
+    if (hipGetLastError() != hipSuccess) return set_error(PIC_EHIP, "current reduction launch failed");
+  }
+  return PIC_OK;
 }
 
 }  // namespace
@@ -384,11 +601,21 @@ int launch_unsort(const pic_particles& sorted, const int64_t* ids, const pic_par
 
 int launch_tile_push(int prec, const Mesh& m, const TileGeom& tg, void* const E[3], void* const B[3],
                      void* const J[3], const int* offsets, const pic_particles& src, const pic_particles& dst,
-                     int pusher, double dt, void* stream) {
+                     int pusher, double dt, double* stage, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   if (src.np == 0) return PIC_OK;
-  return prec == PIC_FP64 ? run_tile_push<double>(m, tg, E, B, J, offsets, src, dst, pusher, dt, s)
-                          : run_tile_push<float>(m, tg, E, B, J, offsets, src, dst, pusher, dt, s);
+  return prec == PIC_FP64 ? run_tile_push<double>(m, tg, E, B, J, offsets, src, dst, pusher, dt, stage, s)
+                          : run_tile_push<float>(m, tg, E, B, J, offsets, src, dst, pusher, dt, stage, s);
 }
+
+int launch_tile_deposit(int prec, const Mesh& m, const TileGeom& tg, void* const J[3], const int* offsets,
+                        const pic_particles& sorted, double dt, double* stage, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (sorted.np == 0) return PIC_OK;
+  return prec == PIC_FP64 ? run_tile_deposit<double>(m, tg, J, offsets, sorted, dt, stage, s)
+                          : run_tile_deposit<float>(m, tg, J, offsets, sorted, dt, stage, s);
+}
+
+size_t stage_doubles(const TileGeom& tg) { return (size_t)tg.ntiles * 3 * tg.r[0] * tg.r[1] * tg.r[2]; }
 
 }  // namespace yeepic

@@ -15,7 +15,7 @@ int set_error(int code, const char* fmt, ...);
 constexpr int kWidths[5] = {1, 2, 4, 8, 16};
 int round_width(int m);
 
-// Mesh geometry passed to every kernel.
+// Mesh geometry and the grid's kernel settings, passed to every kernel.
 struct Mesh {
   int n1, n2, n3;
   int ndim;
@@ -23,6 +23,8 @@ struct Mesh {
   double dx1, dx2, dx3;
   double idx1, idx2, idx3;  // 1/dx: positions become cell coordinates by a multiply
   double L1, L2, L3;
+  int exact_iters;  // iteration cap of the exact pusher's proper-time solve
+  int* noconv;      // device counter of exact pushes whose solve hit the cap
 };
 
 // Field kernels (field_kernels.hip).  ``h`` is the time over which Faraday's
@@ -71,9 +73,17 @@ int launch_tile_sort(const Mesh& m, const TileGeom& tg, const pic_particles& p, 
 // ids[i] = i; dst[ids[i]] = sorted[i] for x and u (3D)
 int launch_iota(int64_t* ids, int64_t np, void* stream);
 int launch_unsort(const pic_particles& sorted, const int64_t* ids, const pic_particles& dst, void* stream);
+// ``stage`` (deterministic mode, else nullptr) holds stage_doubles(tg) doubles:
+// the tiles' currents are then stored there and summed per node in a fixed
+// order instead of being added to J with atomics.
 int launch_tile_push(int prec, const Mesh& m, const TileGeom& tg, void* const E[3], void* const B[3],
                      void* const J[3], const int* offsets, const pic_particles& src, const pic_particles& dst,
-                     int pusher, double dt, void* stream);
+                     int pusher, double dt, double* stage, void* stream);
+// Esirkepov current of particles sorted by the tile of their old position:
+// sorted.x holds the old positions, sorted.u the new ones.
+int launch_tile_deposit(int prec, const Mesh& m, const TileGeom& tg, void* const J[3], const int* offsets,
+                        const pic_particles& sorted, double dt, double* stage, void* stream);
+size_t stage_doubles(const TileGeom& tg);
 
 // Adjoint kernels (adjoint_kernels.hip).  launch_coef_grad adds
 // scale * sum_i (la_i D_j fa_i - lb_i D_j fb_i) to g[j], j < M, where D_j is

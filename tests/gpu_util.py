@@ -48,13 +48,18 @@ def normwise(got, ref):
 
 def assert_fields_close(got, ref, tol, what="", joint=False):
     """Per component max|got - ref| <= tol * scale, with scale = max|ref| of
-    that component, or (joint) of the largest component of the same field:
-    FP32 rounding follows the field's magnitude, not each component's."""
+    that component, or (joint) of the largest component of the same field.
+    Joint is for fields whose components differ by orders of magnitude (a
+    laser with the plasma's response): every component then carries the
+    rounding of the strong ones (ulps of max|E| through the curl), in FP64 as
+    in FP32, so a per-component bound would measure the float format; the
+    per-component errors are still recorded (tolerance inf)."""
     joint_scale = max(float(np.max(np.abs(r))) for r in ref) if joint else None
     for c, (g, r) in enumerate(zip(got, ref)):
         gh = host(g) if isinstance(g, torch.Tensor) else g
         if joint:
             err = float(np.max(np.abs(gh - r))) / (joint_scale if joint_scale > 0 else 1.0)
+            record(f"{what} component {c + 1} (own scale)", normwise(gh, r), float("inf"))
         else:
             err = normwise(gh, r)
         record(f"{what} component {c + 1}", err, tol)

@@ -86,7 +86,7 @@ def _by_id(t, ids):
 def test_step_n_plasma_wide_ampere(pusher, nsteps, prec, coeffs16_quarter):
     """The config-3 style plasma step at dt = dx1/4: tile-sorted push and
     on-chip deposit, the x1 current correction, the general fused sweep.
-    FP64 to 1e-11; FP32 fields to 1e-5 with FP64 particles (1e-6)."""
+    FP64 to 1e-12; FP32 fields to 1e-5 with FP64 particles (1e-6)."""
     CE, CB = coeffs16_quarter
     n = (128, 16, 12)
     L = [n[d] * DX[d] for d in range(3)]
@@ -107,7 +107,7 @@ def test_step_n_plasma_wide_ampere(pusher, nsteps, prec, coeffs16_quarter):
         B = [v.astype(np.float32).astype(np.float64) for v in B]
     sp = {"x": x.copy(), "u": u.copy(), "q": -1.0, "m": 1.0, "w": w}
     Er, Br = pic.run(E, B, [sp], CE, CB, DX, DT4, nsteps, pusher=pusher, deposit=True)
-    ftol, ptol = (1e-11, 1e-11) if prec == "fp64" else (1e-5, 1e-6)
+    ftol, ptol = (1e-12, 1e-12) if prec == "fp64" else (1e-5, 1e-6)
     assert_fields_close(grid.E, Er, ftol, "wide-Ampere step E", joint=prec == "fp32")
     assert_fields_close(grid.B, Br, ftol, "wide-Ampere step B", joint=prec == "fp32")
     ug, xg = _by_id(ud, ids), _by_id(xd, ids)
@@ -133,9 +133,9 @@ def test_step_n_2d_plasma_wide_ampere(coeffs16_quarter):
     grid.sync()
     sp = {"x": x.copy(), "u": u.copy(), "q": -1.0, "m": 1.0, "w": 0.01}
     Er, Br = pic.run(E, B, [sp], CE, CB, DX, DT4, 6, pusher="boris", deposit=True, ndim=2)
-    assert_fields_close(grid.E, Er, 1e-11, "2D wide-Ampere step E")
-    assert_fields_close(grid.B, Br, 1e-11, "2D wide-Ampere step B")
-    assert np.max(np.abs(host(ud) - sp["u"])) < 1e-11
+    assert_fields_close(grid.E, Er, 1e-12, "2D wide-Ampere step E")
+    assert_fields_close(grid.B, Br, 1e-12, "2D wide-Ampere step B")
+    assert np.max(np.abs(host(ud) - sp["u"])) < 1e-12
     grid.close()
 
 

@@ -106,9 +106,8 @@ def test_fused_sweep(ndim, prec, kind, coeffs16):
         grid.sweep(use_J=True)
         E, B = fdtd.sweep(E, B, Ja, CE, CB, DX, wl.DT)
     grid.sync()
-    tol = TOL[prec] * (4 if prec == "fp32" else 1)
-    assert_fields_close(grid.E, E, tol, "sweep E")
-    assert_fields_close(grid.B, B, tol, "sweep B")
+    assert_fields_close(grid.E, E, TOL[prec], "sweep E")
+    assert_fields_close(grid.B, B, TOL[prec], "sweep B")
     grid.close()
 
 
@@ -132,12 +131,14 @@ def test_fused_sweep_small_and_ragged_meshes(n, coeffs16):
 
 
 @pytest.mark.parametrize("kind", ["custom", "m8"])
-def test_fp32_sweep_two_workgroups_per_cu(kind, coeffs16):
+def test_fp32_sweep_one_workgroup_per_cu(kind, coeffs16):
     """FP32 meshes with at least two 128 x 8 tiles per compute unit run the
-    sweep at two workgroups per CU: 1024 x 512 x 2 cells (512 tiles), with a
-    current, against the oracle."""
+    Yee-Ampere sweep at one workgroup per CU, each marching its column along
+    x3: 1024 x 512 x 16 cells (512 tiles, 16 planes of x3-varying random
+    fields and a random current), two steps, against the oracle at 1e-5 (the
+    FP32 field bound; the oracle sees the same float32 inputs)."""
     CE, CB = _coeffs(kind, coeffs16)
-    n = (1024, 512, 2)
+    n = (1024, 512, 16)
     E, B = wl.random_fields(n, seed=41)
     J, _ = wl.random_fields(n, seed=42, scale=0.3)
     E, B, J = ([a.astype(np.float32).astype(np.float64) for a in f] for f in (E, B, J))
@@ -147,8 +148,8 @@ def test_fp32_sweep_two_workgroups_per_cu(kind, coeffs16):
         grid.sweep(use_J=True)
         E, B = fdtd.sweep(E, B, J, CE, CB, DX, wl.DT)
     grid.sync()
-    assert_fields_close(grid.E, E, 4 * TOL["fp32"], "sweep E")
-    assert_fields_close(grid.B, B, 4 * TOL["fp32"], "sweep B")
+    assert_fields_close(grid.E, E, TOL["fp32"], "sweep E")
+    assert_fields_close(grid.B, B, TOL["fp32"], "sweep B")
     grid.close()
 
 

@@ -21,7 +21,7 @@ from oracle import pic  # noqa: E402
 from paper_2004_03754_amd import binding as b, workloads as wl  # noqa: E402
 
 torch = pytest.importorskip("torch")
-from gpu_util import host  # noqa: E402
+from gpu_util import check, host  # noqa: E402
 
 DX = (wl.DX1, wl.DX2, wl.DX3)
 L0 = wl.LAMBDA0
@@ -145,4 +145,96 @@ def test_mixed_precision_plane_wave_full_size():
     # as the FP32-field oracle shows.  The GPU must not add error beyond that.
     assert np.median(rel) <= 10 * np.median(rel32) + 1e-12
     assert rel.max() <= 10 * rel32.max() + 1e-12
+    grid.close()
+
+
+def test_fp64_plane_wave_full_size_and_closed_form():
+    """The 2048 x 512 x 512 plane wave at a0 = 1e4 with FP64 fields (the
+    mixed-precision workload's FP64 run), 20 steps, 4M electrons from rest
+    with the exact pusher.  The fields do not depend on x2 and x3, so a
+    periodic 2048 x 4 x 4 window is exactly the full run: fields to 1e-12 per
+    component, and a sample of electrons per particle (|u - u_ref| /
+    max(1, |u_ref|)) against the oracle's own change under one-ulp changes of
+    the initial x1 and field (the map is ill-conditioned at this field
+    strength): median below 1e-12, the maximum within ten times the largest
+    sensitivity (measured: median 2.4e-13, maximum 2.4e-10 against 2.1e-10).  Every sampled
+    electron also follows the closed-form plane-wave motion (Sec. 4.1,
+    canonical momentum) from rest at t = -dt/2 within 0.25 of max(gamma - 1):
+    at a0 = 1e4 the linear gather's interpolation error, up to
+    (k0 dx1)^2/8 ~ 5e-3 of the field and different for E2 and B3, breaks the
+    null structure of the wave and grows over the step (the oracle shows a
+    median of 0.10 and a maximum of 0.18), which bounds the agreement."""
+    from oracle import trajectory as tj
+    CE = b.design_coeffs(16, 0.5, "E")
+    CB = b.design_coeffs(16, 0.5, "B")
+    n = (2048, 512, 512)
+    steps = 20
+    a0 = 1.0e4
+    L = [n[d] * DX[d] for d in range(3)]
+    pw = wl.PlaneWave(a0)
+    e2, b3, _ = wl.laser_profiles((n[0], 4, 4), DX, pw)
+    d = "cuda:0"
+    shape = (n[2], n[1], n[0])
+    E2 = torch.as_tensor(e2, device=d, dtype=torch.float64).expand(shape).contiguous()
+    B3 = torch.as_tensor(b3, device=d, dtype=torch.float64).expand(shape).contiguous()
+    z = [torch.zeros(shape, device=d, dtype=torch.float64) for _ in range(4)]
+    E = [z[0], E2, z[1]]
+    B = [z[2], z[3], B3]
+    x, u = wl.uniform_particles(1 << 22, [0, 0, 0], L, seed=5)
+    xd = torch.as_tensor(x, device=d).contiguous()
+    ud = torch.as_tensor(u, device=d).contiguous()
+    grid = b.Grid(E, B, DX, wl.DT, CE, CB)
+    p = b.Particles(xd, ud, q=-1.0, m=1.0)
+    print("plane-wave full size: 2048x512x512 FP64 fields, 4194304 electrons, 20 steps", flush=True)
+    grid.step_n([p], steps, pusher="analytic")
+    grid.sync()
+    nw = (n[0], 4, 4)
+    Ew, Bw = wl.laser_fields(nw, DX, pw)
+    idx = np.arange(0, x.shape[1], 2048)
+    xs = x[:, idx].copy()
+    xs[1] = np.mod(xs[1], 4 * DX[1])
+    xs[2] = np.mod(xs[2], 4 * DX[2])
+    sp = {"x": xs, "u": u[:, idx].copy(), "q": -1.0, "m": 1.0, "w": 1.0}
+    Er, Br = pic.run(Ew, Bw, [sp], CE, CB, DX, wl.DT, steps, pusher="analytic")
+    for c, (g, r) in enumerate(zip(E + B, list(Er) + list(Br))):
+        gw = host(g[200:204, 40:44, :])  # any window: the full run is uniform in x2, x3
+        scale = max(float(np.max(np.abs(r))), 1e-300)
+        check(float(np.max(np.abs(gw - r))) / scale if np.max(np.abs(r)) > 0 else float(np.max(np.abs(gw))),
+              1e-12, f"FP64 plane wave field {c}")
+    ug = host(ud)
+    nrm = np.maximum(1.0, np.linalg.norm(sp["u"], axis=0))
+    err = np.linalg.norm(ug[:, idx] - sp["u"], axis=0) / nrm
+    # The 20-step map at a0 = 1e4 is ill-conditioned: the oracle's own result
+    # moves by up to ~2e-10 when an electron's initial x1, or the initial
+    # field, changes by one ulp (median ~1e-13).  The GPU's errors must
+    # follow that distribution: median below 1e-12 and maximum within ten
+    # times the largest one-ulp sensitivity.  (Per electron the sensitivity
+    # to two perturbation directions underestimates the rest: 96% of the
+    # electrons lie within ten times their own.)
+    sens = np.zeros_like(err)
+    for kind, sgn in (("x", 1.0), ("x", -1.0), ("f", 1.0), ("f", -1.0)):
+        xp = xs.copy()
+        Ep, Bp = Ew, Bw
+        if kind == "x":
+            xp[0] = xp[0] * (1 + sgn * 2.0 ** -52)
+        else:
+            Ep = [e * (1 + sgn * 2.0 ** -52) for e in Ew]
+            Bp = [v * (1 + sgn * 2.0 ** -52) for v in Bw]
+        spp = {"x": xp, "u": u[:, idx].copy(), "q": -1.0, "m": 1.0, "w": 1.0}
+        pic.run(Ep, Bp, [spp], CE, CB, DX, wl.DT, steps, pusher="analytic")
+        sens = np.maximum(sens, np.linalg.norm(spp["u"] - sp["u"], axis=0) / nrm)
+    frac = float(np.mean(err <= np.maximum(1e-12, 10 * sens)))
+    print(f"FP64 plane-wave electrons: error median {np.median(err):.1e} max {err.max():.1e}; "
+          f"one-ulp sensitivity median {np.median(sens):.1e} max {sens.max():.1e}; "
+          f"{100 * frac:.2f}% within max(1e-12, 10 x own sensitivity)", flush=True)
+    check(float(np.median(err)), 1e-12, "FP64 plane wave electrons u (median)")
+    check(float(err.max()), 10 * float(sens.max()), "FP64 plane wave electrons u (max) vs 10 x largest sensitivity")
+    # closed form for every 256th electron (16384)
+    cf = np.arange(0, x.shape[1], 256)
+    g_gpu = np.sqrt(1 + np.sum(ug[:, cf] ** 2, axis=0))
+    tt = (steps - 0.5) * wl.DT
+    _, _, gcf = tj.state_at(pw.a, -1.0, -0.5 * wl.DT, x[:, cf], tt)
+    dev_cf = np.abs(g_gpu - gcf) / np.max(gcf - 1)
+    print(f"closed form over {cf.size} electrons: max {dev_cf.max():.3f}, median {np.median(dev_cf):.3f}", flush=True)
+    check(float(dev_cf.max()), 0.25, "FP64 plane wave gamma vs closed form")
     grid.close()

@@ -115,7 +115,7 @@ def test_quadratic_plasma_step(pusher, nsteps, prec, coeffs16):
         B = [v.astype(np.float32).astype(np.float64) for v in B]
     sp = {"x": x.copy(), "u": u.copy(), "q": -1.0, "m": 1.0, "w": w}
     Er, Br = pic.run(E, B, [sp], CE, CB, DX, wl.DT, nsteps, pusher=pusher, deposit=True, order=2)
-    ftol, ptol = (1e-11, 1e-11) if prec == "fp64" else (1e-5, 1e-6)
+    ftol, ptol = (1e-12, 1e-12) if prec == "fp64" else (1e-5, 1e-6)
     assert_fields_close(grid.E, Er, ftol, "quadratic step E", joint=prec == "fp32")
     assert_fields_close(grid.B, Br, ftol, "quadratic step B", joint=prec == "fp32")
     ug, xg = _by_id(ud, ids), _by_id(xd, ids)
@@ -147,8 +147,8 @@ def test_quadratic_2d_step_and_gauss_law(coeffs16_quarter):
     grid.sync()
     sp = {"x": x.copy(), "u": u.copy(), "q": -1.0, "m": 1.0, "w": 0.01}
     Er, Br = pic.run(E, B, [sp], CE, CB, DX, dt, 6, pusher="boris", deposit=True, ndim=2, order=2)
-    assert_fields_close(grid.E, Er, 1e-11, "2D quadratic step E")
-    assert_fields_close(grid.B, Br, 1e-11, "2D quadratic step B")
+    assert_fields_close(grid.E, Er, 1e-12, "2D quadratic step E")
+    assert_fields_close(grid.B, Br, 1e-12, "2D quadratic step B")
     Eg = [host(e) for e in Ed]
     g = fdtd.div_ampere(Eg, CB, DX) - pt.charge_density(host(xd), -1.0, 0.01, DX, shape, ndim=2, order=2)
     assert np.max(np.abs(g - g0)) < 1e-11 * np.max(np.abs(fdtd.div_ampere(Eg, CB, DX)))
