@@ -26,6 +26,8 @@ pic         the per-step driver: push, deposit, current correction, fused
 trajectory  closed-form electron trajectory in a plane wave, from rest or
             drifting (Sec. 4.1, canonical momentum conservation)
 window      moving window along x1 (Sec. 4.1 single-particle runs)
+absorb      graded damping layers at the two x1 ends of the window
+precise     the three pushers evaluated at 50 digits (strong-field checks)
 adjoint     FP64 adjoint of the field sweep, gather and pushers
 
 Every function names the passage of the paper it follows.  Readings of

@@ -10,12 +10,14 @@ Per step (Eq. pusher time levels; Sec. 3.3 for the source):
      is the identity when [k]_B1 equals the Yee symbol (the proposed solver
      at dt = dx1/2) and is skipped there.
   4. field sweep (E^n, B^n) -> (E^{n+1}, B^{n+1}) with J^{n+1/2}.
+  5. optionally, the absorbing layers at the two x1 ends of the window
+     (``absorb``; off by default).
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import current, fdtd, particles
+from . import absorb as absorb_mod, current, fdtd, particles
 
 
 def _ampere_is_yee(CB):
@@ -25,10 +27,12 @@ def _ampere_is_yee(CB):
     return abs(CB[0] - 1.0) <= 1e-20 and bool(np.all(np.abs(CB[1:]) <= 1e-20))
 
 
-def step(E, B, species, CE, CB, dx, dt, *, pusher="boris", deposit=False, ndim=3, order=1):
+def step(E, B, species, CE, CB, dx, dt, *, pusher="boris", deposit=False, ndim=3, order=1, absorb=None):
     """Advance fields and every species by one step; species entries are
     dicts with keys x, u, q, m, w (x and u are replaced).  ``order``: shape
-    function of gather and deposit, 1 linear, 2 quadratic."""
+    function of gather and deposit, 1 linear, 2 quadratic.  ``absorb``:
+    (W, sigma) or (W, sigma, origin) of the x1 absorbing layers, applied
+    after the field sweep."""
     shape = E[0].shape
     n3, n2, n1 = shape
     L = [n1 * dx[0], n2 * dx[1], n3 * dx[2]][:ndim]
@@ -54,7 +58,10 @@ def step(E, B, species, CE, CB, dx, dt, *, pusher="boris", deposit=False, ndim=3
         sp["x"], sp["u"] = x_new, u
     if deposit and not _ampere_is_yee(CB):
         J[0] = current.correct_x1(J[0], CB, dx[0])
-    return fdtd.sweep(E, B, J, CE, CB, dx, dt)
+    E, B = fdtd.sweep(E, B, J, CE, CB, dx, dt)
+    if absorb is not None:
+        E, B = absorb_mod.damp(E, B, *absorb)
+    return E, B
 
 
 def run(E, B, species, CE, CB, dx, dt, nsteps, **kw):
