@@ -300,6 +300,21 @@ int pic_move_window(pic_grid *g, int64_t cells, pic_particles *const *species, i
 /* The window's ring origin (0 <= origin < n1) and the cells moved so far. */
 int pic_window(const pic_grid *g, int64_t *origin, int64_t *moved);
 
+/* ---- absorbing layers at the x1 ends of the window -------------------------
+ * The moving-window runs of Sec. 4.1 and 4.2 let light leave through the
+ * window's x1 ends; on the ring (periodic) x1 axis it would otherwise
+ * re-enter at the other end.  With width W > 0, after every field step
+ * (pic_step_n, pic_field_sweep, pic_step_to) the fields in window cells
+ * [0, W) and [n1 - W, n1) are multiplied by the graded damping factor of
+ * Cerjan et al. (1985), exp(-sigma (d/W)^2), d the depth of each component's
+ * own staggered x1 position into the nearest strip (window coordinates, so
+ * the strips follow pic_move_window).  J is not damped.  At W = 32 cells of
+ * lambda0/32 and sigma = 1 a laser pulse entering a strip leaves less than
+ * 1e-9 of its energy reflected.  W = 0 (the default) turns the layers off.
+ * PIC_EINVAL unless 0 <= 2W <= n1 and sigma >= 0 is finite; the adjoint
+ * step refuses a grid with layers (PIC_EUNSUPPORTED). */
+int pic_set_absorber(pic_grid *g, int width, double sigma);
+
 /* ---- adjoint of one vacuum step ---------------------------------------------
  * Reverse mode of one step of pic_step_n without deposit, with the Boris or
  * the exact pusher: gather (App. A) + push (Sec. 1) + position update (Sec. 4.1) of

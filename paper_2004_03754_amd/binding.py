@@ -55,7 +55,7 @@ EXPORTS = ["pic_design_coeffs", "pic_init_grid", "pic_set_fields", "pic_advance_
            "pic_field_sweep", "pic_gather_push", "pic_deposit_J", "pic_step_n", "pic_sync", "pic_check",
            "pic_grid_widths", "pic_destroy", "pic_last_error", "pic_set_sort_interval", "pic_adjoint_step", "pic_step_to",
            "pic_current_correction", "pic_set_shape", "pic_move_window", "pic_window",
-           "pic_adjoint_step_noalloc", "pic_set_deposit_mode", "pic_set_exact_iterations"]
+           "pic_adjoint_step_noalloc", "pic_set_deposit_mode", "pic_set_exact_iterations", "pic_set_absorber"]
 
 
 def lib():
@@ -80,6 +80,7 @@ def lib():
         L.pic_set_sort_interval.argtypes = [vp, i]
         L.pic_set_shape.argtypes = [vp, i]
         L.pic_set_deposit_mode.argtypes = [vp, i]
+        L.pic_set_absorber.argtypes = [vp, i, d]
         L.pic_set_exact_iterations.argtypes = [vp, i]
         PP = ctypes.POINTER(ctypes.POINTER(_Particles))
         L.pic_move_window.argtypes = [vp, ctypes.c_int64, PP, i]
@@ -299,6 +300,11 @@ class Grid:
         o, m = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().pic_window(self._h, ctypes.byref(o), ctypes.byref(m)))
         return o.value, m.value
+
+    def set_absorber(self, width, sigma=1.0):
+        """pic_set_absorber: graded damping layers of ``width`` cells at the
+        two x1 ends of the window (0 turns them off)."""
+        _check(lib().pic_set_absorber(self._h, int(width), float(sigma)))
 
     def set_deposit_mode(self, deterministic):
         """pic_set_deposit_mode: fixed-order (deterministic) or atomic tile flush."""

@@ -68,6 +68,8 @@ struct pic_grid {
   // moving window: array column of window cell 0, cells moved so far, and
   // the compaction scratch (grow-only)
   int64_t win_origin = 0, win_moved = 0;
+  int absorb_w = 0;  // absorbing layers at the x1 ends: width in cells (0: none) and strength
+  double absorb_sigma = 0.0;
   int* win_counts = nullptr;
   int64_t* win_offs = nullptr;
   int64_t win_nb_cap = 0;
@@ -511,12 +513,27 @@ int pic_current_correction(pic_grid* g, void* J1_out) {
   return launch_correct_j1(g->prec, g->mesh, g->J[0], J1_out, g->corr_taps, g->corr_kw, g->stream);
 }
 
+// The absorbing layers (if set) on the fields of a finished step.
+static int absorb_after_step(pic_grid* g, void* const E[3], void* const B[3]) {
+  return launch_damp_columns(g->prec, g->mesh, E, B, g->win_origin, g->absorb_w, g->absorb_sigma, g->stream);
+}
+
 int pic_field_sweep(pic_grid* g, int use_J) {
   if (!g) return set_error(PIC_EINVAL, "grid is NULL");
   if (use_J && !(g->J[0] && g->J[1] && g->J[2])) return set_error(PIC_EINVAL, "use_J set but J is not");
   int rc = sweep_once(g, g->E, g->B, g->alt, g->alt + 3, use_J);
+  if (rc == PIC_OK) rc = absorb_after_step(g, g->alt, g->alt + 3);
   if (rc) return rc;
   return swap_into_caller(g);
+}
+
+int pic_set_absorber(pic_grid* g, int width, double sigma) {
+  if (!g) return set_error(PIC_EINVAL, "grid is NULL");
+  if (width < 0 || 2 * (int64_t)width > g->n[0]) return set_error(PIC_EINVAL, "absorber width must be in 0..n1/2");
+  if (!(sigma >= 0.0) || !std::isfinite(sigma)) return set_error(PIC_EINVAL, "absorber strength must be >= 0");
+  g->absorb_w = width;
+  g->absorb_sigma = sigma;
+  return PIC_OK;
 }
 
 int pic_gather_push(pic_grid* g, pic_particles* p, int pusher, double* const x_old[3]) {
@@ -722,6 +739,7 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
       if (rc == PIC_OK && deposit) rc = launch_deposit(g->prec, g->mesh, g->J, *species[s], xo, g->dt, g->stream);
     }
     if (rc == PIC_OK) rc = sweep_once(g, cur, cur + 3, nxt, nxt + 3, deposit);
+    if (rc == PIC_OK) rc = absorb_after_step(g, nxt, nxt + 3);
     for (int c = 0; c < 6; ++c) std::swap(cur[c], nxt[c]);
   }
   if (vac)
@@ -769,7 +787,9 @@ int pic_step_to(pic_grid* g, pic_particles* const* species, int nspecies, int pu
     int rc = launch_gather_push(g->prec, g->mesh, g->E, g->B, *species[s], pusher, g->dt, nullptr, g->stream);
     if (rc) return rc;
   }
-  return sweep_once(g, g->E, g->B, Eout, Bout, 0, Bhalf);
+  int rc = sweep_once(g, g->E, g->B, Eout, Bout, 0, Bhalf);
+  if (rc) return rc;
+  return absorb_after_step(g, Eout, Bout);
 }
 
 // Argument checks shared by the two adjoint entry points.
@@ -779,6 +799,7 @@ static int adjoint_args(pic_grid* g, const pic_adjoint* adj, const pic_particles
   if (g->prec != PIC_FP64) return set_error(PIC_EUNSUPPORTED, "the adjoint is built for FP64 grids only");
   if (pusher == PIC_PUSH_HC) return set_error(PIC_EUNSUPPORTED, "the adjoint covers the Boris and exact pushers");
   if (g->mesh.order != 1) return set_error(PIC_EUNSUPPORTED, "the adjoint covers the linear particle shape");
+  if (g->absorb_w > 0) return set_error(PIC_EUNSUPPORTED, "the adjoint does not cover the absorbing layers");
   if (pusher != PIC_PUSH_BORIS && pusher != PIC_PUSH_ANALYTIC) return set_error(PIC_EINVAL, "bad pusher");
   if (nspecies < 0) return set_error(PIC_EINVAL, "negative count");
   if (nspecies > 0 && (!species || !lambda)) return set_error(PIC_EINVAL, "species or lambda is NULL");

@@ -36,6 +36,40 @@ __global__ void __launch_bounds__(kColBlock) zero_columns_kernel(Columns z, int6
   static_cast<T*>(z.f[blockIdx.y])[row * n1 + c] = T(0);
 }
 
+// Graded damping layers at the two x1 ends of the window (the absorber of
+// Cerjan, Kosloff, Kosloff and Reshef, 1985): in window cells [0, W) and
+// [n1 - W, n1) every component is multiplied by exp(-sigma (d/W)^2), d the
+// depth of its own staggered x1 position (window cell + 0 or 1/2) into the
+// nearest strip.  Window cell s lives in array column (origin + s) mod n1.
+struct Fields6 {
+  void* f[6];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kColBlock) damp_columns_kernel(Fields6 z, int64_t n1, int64_t rows, int64_t origin,
+                                                                 int W, double sigma) {
+  const int64_t ncol = 2 * (int64_t)W;
+  const int64_t i = (int64_t)blockIdx.x * kColBlock + threadIdx.x;
+  if (i >= rows * ncol) return;
+  const int64_t row = i / ncol;
+  const int64_t k = i - row * ncol;
+  const int64_t s = k < W ? k : n1 - ncol + k;  // window cell
+  int64_t c = origin + s;
+  if (c >= n1) c -= n1;
+  const int comp = blockIdx.y;                 // E1 E2 E3 B1 B2 B3
+  const double off = (comp == 0 || comp == 4 || comp == 5) ? 0.5 : 0.0;
+  const double pos = (double)s + off;
+  double d = 0.0;
+  if (pos < (double)W)
+    d = (double)W - pos;
+  else if (pos > (double)(n1 - W))
+    d = pos - (double)(n1 - W);
+  if (!(d > 0.0)) return;
+  const double r = d / (double)W;
+  T* f = static_cast<T*>(z.f[comp]) + row * n1 + c;
+  *f = (T)((double)*f * exp(-sigma * (r * r)));
+}
+
 struct Leave {
   double inv_dx1;
   int64_t n1, origin, s;
@@ -164,6 +198,27 @@ int launch_zero_columns(int prec, const Mesh& m, void* const* arrays, int narray
     hipLaunchKernelGGL(zero_columns_kernel<float>, grid, dim3(kColBlock), 0, (hipStream_t)stream, z,
                        (int64_t)m.n1, rows, c0, s);
   return hip_status("zero_columns_kernel");
+}
+
+int launch_damp_columns(int prec, const Mesh& m, void* const E[3], void* const B[3], int64_t origin, int W,
+                        double sigma, void* stream) {
+  if (W <= 0) return PIC_OK;
+  Fields6 z;
+  for (int c = 0; c < 3; ++c) {
+    z.f[c] = E[c];
+    z.f[3 + c] = B[c];
+  }
+  const int64_t rows = (int64_t)m.n2 * m.n3;
+  const int64_t work = rows * 2 * W;
+  const dim3 grid((unsigned)((work + kColBlock - 1) / kColBlock), 6);
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == PIC_FP64)
+    hipLaunchKernelGGL(damp_columns_kernel<double>, grid, dim3(kColBlock), 0, s, z, (int64_t)m.n1, rows, origin, W,
+                       sigma);
+  else
+    hipLaunchKernelGGL(damp_columns_kernel<float>, grid, dim3(kColBlock), 0, s, z, (int64_t)m.n1, rows, origin, W,
+                       sigma);
+  return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "absorber launch failed");
 }
 
 int64_t window_blocks(int64_t np) { return (np + kWinChunk - 1) / kWinChunk; }

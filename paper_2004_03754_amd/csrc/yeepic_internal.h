@@ -104,6 +104,10 @@ int launch_adjoint_push(const Mesh& m, void* const E[3], void* const B[3], void*
 int launch_zero_columns(int prec, const Mesh& m, void* const* arrays, int narrays, int64_t c0, int64_t s,
                         void* stream);
 int64_t window_blocks(int64_t np);
+// Absorbing layers: damps E and B in the 2W window columns at the two x1
+// ends (window cell s in array column (origin + s) mod n1); W = 0 does nothing.
+int launch_damp_columns(int prec, const Mesh& m, void* const E[3], void* const B[3], int64_t origin, int W,
+                        double sigma, void* stream);
 int launch_window_count(const Mesh& m, const pic_particles& p, int64_t origin, int64_t s, int* counts,
                         int64_t* offs, void* stream);
 int launch_window_scatter(const Mesh& m, const pic_particles& src, const pic_particles& dst, int64_t origin,
