@@ -35,6 +35,17 @@ if ROOT not in sys.path:
 
 METRIC = "cell-updates/s + particle-pushes/s (FP64 vs FP32-field); fwd+adjoint step ms"
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6  # MI355X vector FP64 (FMA counted as two flops)
+# Algorithmic FP64 work per particle of the plasma step (Boris, linear shape):
+# staggered gather 126 (six trilinear interpolations of 21 flops), Boris 60,
+# position update 14, Esirkepov deposit about 300 (shape differences, 27
+# weights of 7 flops, running sums and scaling), an FMA counted as two.
+PLASMA_FLOPS_PER_PARTICLE = 500
+# The exact pusher per particle: gather 126, invariants and three applications
+# of the field tensor about 100, about five Newton iterations of the
+# Cayley-Hamilton coefficients and t(tau) (about 150 each), the final
+# exponential and position update about 30.
+EXACT_FLOPS_PER_PARTICLE = 1000
 
 
 def _device_fields(n, dx, pulse, x_head, w0, dtype, torch):
@@ -145,6 +156,7 @@ def run_plane_wave(torch, b, wl, CE, CB, steps):
     n = (2048, 512, 512)
     L = [n[d] * dx[d] for d in range(3)]
     out = {}
+    keep = {}
     for prec in ("fp32", "fp64"):
         dtype = torch.float32 if prec == "fp32" else torch.float64
         E, B = _device_plane_wave(n, dx, 1.0e4, dtype, torch)
@@ -167,12 +179,27 @@ def run_plane_wave(torch, b, wl, CE, CB, steps):
         ms_sweep = s0.elapsed_time(s1) / 4
         cells = n[0] * n[1] * n[2]
         elem = 4 if prec == "fp32" else 8
+        gbps = 12 * elem * cells / (ms_sweep * 1e-3) / 1e9
         out[prec] = {"ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3),
                      "particle_pushes_per_s": (1 << 22) / (ms * 1e-3), "sweep_ms": ms_sweep,
-                     "sweep_GBps": 12 * elem * cells / (ms_sweep * 1e-3) / 1e9}
+                     "sweep_GBps": gbps, "sweep_hbm_frac": gbps / HBM_PEAK_GBS}
+        # state for the mixed-path error: every electron's gamma and one x2-x3
+        # column of the fields (the plane wave is uniform across it)
+        keep[prec] = (torch.sqrt(1.0 + torch.sum(ud * ud, 0)),
+                      [f[0, 0, :].to(torch.float64).clone() for f in E + B])
         grid.close()
         del E, B, xd, ud, grid, p
         torch.cuda.empty_cache()
+    g32, f32 = keep["fp32"]
+    g64, f64 = keep["fp64"]
+    rel = (torch.abs(g32 - g64) / g64).cpu()
+    fscale = max(float(torch.max(torch.abs(f))) for f in f64)
+    ferr = max(float(torch.max(torch.abs(a - c))) for a, c in zip(f32, f64)) / fscale
+    out["mixed_path_error_vs_fp64_path"] = {
+        "steps": steps + 2, "field_joint_norm": ferr,
+        "gamma_rel_median": float(torch.median(rel)), "gamma_rel_p99": float(torch.quantile(rel[::16], 0.99)),
+        "gamma_rel_max": float(torch.max(rel)),
+        "note": "FP32-field run against the FP64-field run of the same GPU from the same state, all 4M electrons"}
     out["fp32_speedup_step"] = out["fp64"]["ms_per_step"] / out["fp32"]["ms_per_step"]
     out["fp32_speedup_sweep"] = out["fp64"]["sweep_ms"] / out["fp32"]["sweep_ms"]
     return out
@@ -218,9 +245,16 @@ def run_plasma(torch, b, wl, CE, CB, steps, dt=None, order=1):
     d1.record()
     torch.cuda.synchronize()
     grid.check(p)
+    cells = n[0] * n[1] * n[2]
+    step_bytes = 96 * npart + 60 * cells
     out = {"ms_per_step": ms, "particles": npart, "particle_pushes_per_s": npart / (ms * 1e-3),
-           "cell_updates_per_s": n[0] * n[1] * n[2] / (ms * 1e-3),
-           "gather_push_ms": q0.elapsed_time(q1), "deposit_ms": d0.elapsed_time(d1)}
+           "cell_updates_per_s": cells / (ms * 1e-3),
+           "gather_push_ms": q0.elapsed_time(q1), "deposit_ms": d0.elapsed_time(d1),
+           "step_roofline": {
+               "hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               "fp64_valu_frac": PLASMA_FLOPS_PER_PARTICLE * npart / (ms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS,
+               "note": "whole step (sort every 3 steps included) against 96 B/particle + 60 B/cell of HBM "
+                       "and about 500 FP64 flops/particle"}}
     if abs(dt - wl.DT) > 1e-15:
         jc = torch.empty_like(J[0])
         grid.current_correction(jc)
@@ -418,7 +452,17 @@ def cpu_baseline():
     if r.returncode != 0:
         return {"error": r.stderr[-400:]}
     d = json.loads(r.stdout.strip().splitlines()[-1])
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": d["value"], "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "os_cpu_count": os.cpu_count(),
             "sample": f"oracle step (exact pusher) on a 1024x32x32 column with {d['npart']} electrons, "
                       f"{d['steps']} steps after 1 warm-up, {d['seconds']:.1f} s, NumPy FP64 single thread"}
 
@@ -529,6 +573,11 @@ def main():
                    "cells": cells, "electrons": main_run["npart"], "dt_over_dx1": r},
         "particle_pushes_per_s": main_run["npart"] / (main_run["ms_step"] * 1e-3),
         "kernels_ms": {"fused_sweep": main_run["ms_sweep"], "gather_push_analytic": main_run["ms_push"]},
+        "gather_push_analytic_roofline": {
+            "hbm_frac": main_run["push_bytes"] / (main_run["ms_push"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "fp64_valu_frac": EXACT_FLOPS_PER_PARTICLE * main_run["npart"] / (main_run["ms_push"] * 1e-3) / 1e12
+            / FP64_VALU_PEAK_TFLOPS,
+            "note": "96 B and about 1000 FP64 flops per exact push (estimate of the algorithm's work)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "fused B-half/E/B-half sweep, 96 B/cell FP64"},

@@ -119,6 +119,9 @@ typedef struct pic_adjoint {
   const void *Bn[3];   /* ... and B, read only; when given the step recomputes no sweep */
   const void *Bh[3];   /* optional (with En, Bn; all three or none): B^{n+1/2} of the step,
                           read only; when given the step rebuilds nothing */
+  void *lEo[3];        /* optional (all six or none), device, layout of E: receive dL/dE at t^n
+                          (out of place); lE and lB are then only read */
+  void *lBo[3];        /* ... and dL/dB at t^n */
 } pic_adjoint;
 
 /* ---- coefficient design (host only; App. B) ------------------------------
@@ -340,8 +343,16 @@ int pic_set_absorber(pic_grid *g, int width, double sigma);
  * PIC_EUNSUPPORTED for FP32-field grids and for the Higuera-Cary pusher;
  * PIC_EINVAL for an unknown pusher; the
  * coefficient reduction allocates a scratch of 16 doubles per 1024 cells of
- * 8 x1 rows at the first call (PIC_ENOMEM if that fails).  Scatter into lE, lB
- * uses atomics, so the field cotangents vary in the last bits between runs. */
+ * 8 x1 rows (32 per 1024 cells of the fused 2D kernel) at the first call
+ * (PIC_ENOMEM if that fails).  Scatter into lE, lB uses atomics, so the field
+ * cotangents vary in the last bits between runs.
+ * With adj->lEo, lBo given (no aliasing of any other array), dL/d(E,B) at t^n
+ * go there and lE, lB are left unchanged; on a 2D grid whose C^B has one
+ * coefficient (the proposed solver at dt = dx1/2) with En, Bn and Bh given,
+ * the three field stages and their dL/dC products then run as one fused pass
+ * over the mesh (about a third of the memory traffic of the three in-place
+ * stages and their products);
+ * in every other case the in-place stages run and their result is copied. */
 int pic_adjoint_step(pic_grid *g, const pic_adjoint *adj, const pic_particles *const *species,
                      pic_particles *const *lambda, int nspecies, int pusher);
 
@@ -351,11 +362,13 @@ int pic_adjoint_step(pic_grid *g, const pic_adjoint *adj, const pic_particles *c
  * hipMalloc).  Same arguments, results and errors as pic_adjoint_step, and
  * the same kernels, but the per-block partial sums of the coefficient
  * gradients live in a fixed device array of the library (1 MiB: 2^17
- * doubles, i.e. 8192 reduction blocks of 1024 x1 cells by 8 x1 rows, about
- * 67M cells) instead of grid scratch allocated at the first call; the call
- * makes no hipMalloc, hipFree or other allocating call.  The array's device
- * address is looked up once per device at pic_init_grid.  A mesh needing
- * more partial sums is refused with PIC_EUNSUPPORTED (use pic_adjoint_step).
+ * doubles; enough for 8192 reduction blocks of 1024 x1 cells by 8 x1 rows
+ * on the in-place path, about 67M cells, and for any mesh on the fused 2D
+ * path, whose 256 persistent workgroups need 8192 doubles) instead of grid scratch
+ * allocated at the first call; the call makes no hipMalloc, hipFree or other
+ * allocating call.  The array's device address is looked up once per device
+ * at pic_init_grid.  A mesh needing more partial sums is refused with
+ * PIC_EUNSUPPORTED (use pic_adjoint_step).
  * Every grid on one device shares that array and nothing in it needs to
  * start at zero (each call writes the partial sums before it reads them);
  * calls that overlap in time on one device (other streams, other threads)

@@ -87,6 +87,10 @@ class PICRun(torch.autograd.Function):
         halves = [[torch.empty_like(v) for v in B0] for _ in range(K)]  # B^{n+1/2} of each step
         grid = b.Grid(slots[0][0], slots[0][1], cfg.dx, cfg.dt, ce, cb, ndim=cfg.ndim)
         lam = b.Particles(lx, lu, q=cfg.q, m=cfg.m, w=cfg.w)
+        # the field cotangents alternate between two sets: each reverse step
+        # reads one and writes the other (out of place, fused where possible)
+        lE2 = [torch.empty_like(v) for v in lE]
+        lB2 = [torch.empty_like(v) for v in lB]
         nseg = len(ctx.checkpoints)
         for seg in reversed(range(nseg)):
             s0 = seg * cfg.K
@@ -111,11 +115,11 @@ class PICRun(torch.autograd.Function):
                 st, nx = slots[i], slots[i + 1]
                 grid.set_fields(st[0], st[1])
                 p = b.Particles(st[2], st[3], q=cfg.q, m=cfg.m, w=cfg.w)
-                if p.np:
-                    grid.adjoint_step(lE, lB, gCE, gCB, [p], [lam], pusher=cfg.pusher, next_E=nx[0], next_B=nx[1],
-                                      half_B=halves[i])
-                else:
-                    grid.adjoint_step(lE, lB, gCE, gCB, next_E=nx[0], next_B=nx[1], half_B=halves[i])
+                sp, lp = ([p], [lam]) if p.np else ((), ())
+                grid.adjoint_step(lE, lB, gCE, gCB, sp, lp, pusher=cfg.pusher, next_E=nx[0], next_B=nx[1],
+                                  half_B=halves[i], out_E=lE2, out_B=lB2)
+                lE, lE2 = lE2, lE
+                lB, lB2 = lB2, lB
         grid.sync()
         grid.close()
         dtype, device, M = ctx.coef_meta

@@ -48,7 +48,7 @@ class _Particles(ctypes.Structure):
 class _Adjoint(ctypes.Structure):
     _fields_ = [("lE", ctypes.c_void_p * 3), ("lB", ctypes.c_void_p * 3), ("gCE", ctypes.c_void_p),
                 ("gCB", ctypes.c_void_p), ("En", ctypes.c_void_p * 3), ("Bn", ctypes.c_void_p * 3),
-                ("Bh", ctypes.c_void_p * 3)]
+                ("Bh", ctypes.c_void_p * 3), ("lEo", ctypes.c_void_p * 3), ("lBo", ctypes.c_void_p * 3)]
 
 
 EXPORTS = ["pic_design_coeffs", "pic_init_grid", "pic_set_fields", "pic_advance_B_half", "pic_advance_E",
@@ -205,18 +205,23 @@ class Grid:
         _check(lib().pic_set_fields(self._h, _ptr3(E), _ptr3(B), _ptr3(J)))
 
     def adjoint_step(self, lE, lB, gCE, gCB, species=(), lambdas=(), pusher="boris", next_E=None, next_B=None,
-                     half_B=None, noalloc=False):
+                     half_B=None, noalloc=False, out_E=None, out_B=None):
         """Reverse of one vacuum step from the grid's current state (see
         pic_adjoint_step): lE, lB (FP64, field layout) and the particle
-        cotangents in ``lambdas`` are mapped from t^{n+1} to t^n in place;
+        cotangents in ``lambdas`` are mapped from t^{n+1} to t^n (in place
+        unless out_E, out_B are given);
         gCE, gCB (16 doubles on the device) are accumulated.  next_E, next_B:
         the forward state at t^{n+1}, if the caller has it; half_B (with
         them): the step's B^{n+1/2}, as step_to writes it.  noalloc: call
-        pic_adjoint_step_noalloc (library-held scratch, no allocation)."""
+        pic_adjoint_step_noalloc (library-held scratch, no allocation).
+        out_E, out_B: receive the field cotangents at t^n (out of place; lE
+        and lB are then only read; with the forward state and half_B given,
+        a 2D grid and C^B = c e1 this takes the fused reverse sweep)."""
         adj = _Adjoint()
         adj.lE, adj.lB = _ptr3(lE), _ptr3(lB)
         adj.gCE, adj.gCB = gCE.data_ptr(), gCB.data_ptr()
         adj.En, adj.Bn, adj.Bh = _ptr3(next_E), _ptr3(next_B), _ptr3(half_B)
+        adj.lEo, adj.lBo = _ptr3(out_E), _ptr3(out_B)
         ns = len(species)
         assert len(lambdas) == ns
         a = (ctypes.POINTER(_Particles) * max(1, ns))()

@@ -24,6 +24,9 @@
 //   position cotangent.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdint>
+
 #include "particle_common.h"
 
 namespace yeepic {
@@ -132,6 +135,361 @@ __global__ __launch_bounds__(256) void coef_finalize_kernel(const double* __rest
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) g[j] += scale * (((red[0] + red[1]) + red[2]) + red[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Fused reverse of one 2D vacuum sweep for a Yee-width Ampere stencil
+// (C^B = c e1: the proposed solver at dt = dx1/2), the stacked-plane batch of
+// the differentiated workload.  With h = dt/2 and the cotangents (lE, lB) of
+// (E^{n+1}, B^{n+1}):
+//   lE1 = lE - h curl_B[C^E] lB        (reverse of the second B half step)
+//   lB1 = lB + dt curl_E[C^B] lE1      (reverse of the E step)
+//   lE0 = lE1 - h curl_B[C^E] lB1      (reverse of the first B half step)
+// plus the three stages' lag products for dL/dC^E and dL/dC^B, in one pass.
+// The mesh is cut into tiles of TX x TY cells of one plane.  For a tile, lB
+// is staged with the halo the three stages need (2W - 1 .. 2W cells along
+// x1, two rows below and one above) and lE with half of it; both are updated
+// in LDS stage by stage, lE0 and lB1 are written out of place (neighbouring
+// tiles read the inputs' halos), and the rows of E^{n+1}, B^{n+1/2} and E^n
+// the products need are staged beside them.  The stencil arithmetic is that
+// of advance_e_kernel / advance_b_kernel and the products those of
+// coef_partial_kernel; only the order of the sums differs.
+//
+// The tiles take all of a CU's LDS, so one workgroup runs per CU; to keep
+// HBM busy, the launch is persistent: a fixed grid of kAdjBlocks workgroups
+// walks runs of consecutive tiles along x2 (work items), and a workgroup
+// issues the loads of its next tile into registers before it computes the
+// current one.  The lag products stay in registers over all of a
+// workgroup's tiles and are reduced once, so the partial sums (and their
+// order) depend on the mesh only.
+// ---------------------------------------------------------------------------
+constexpr int kAW = kLags;  // x1 reach of the wide (Faraday C^E) stencil
+constexpr int kATX = 128, kATY = 8, kANT = kATX * kATY / 4;
+constexpr int kARB = kATY + 3, kAXB = kATX + 4 * kAW;  // lB tile: rows j0-2 .., cols i0-2W ..
+constexpr int kARE = kATY + 2, kAXE = kATX + 2 * kAW;  // lE tile: rows j0-1 .., cols i0-W ..
+constexpr int kAXF = kATX + 2 * kAW;                   // forward-field rows: cols i0-W ..
+constexpr size_t kALdsB = (size_t)3 * kARB * kAXB, kALdsE = (size_t)3 * kARE * kAXE;
+constexpr size_t kALdsF = (size_t)6 * kATY * kAXF;
+constexpr size_t kALds = (kALdsB + kALdsE + kALdsF) * sizeof(double);
+constexpr int kAdjBlocks = 256;  // persistent workgroups: one per CU of an MI355X
+
+struct Coef16 {
+  double c[kAW];
+};
+
+struct AdjPlane {
+  const double* li[6];   // lE1 lE2 lE3 lB1 lB2 lB3 at t^{n+1} (read)
+  double* lo[6];         // the same at t^n (written)
+  const double* fw[6];   // E^{n+1}_2, E^{n+1}_3, B^{n+1/2}_2, B^{n+1/2}_3, E^n_2, E^n_3
+};
+
+// Work items: item w is strip w % strips (x1 cells strip*TX ..), chunk
+// (w / strips) % ysplit of the strip's nty tile rows (tpb tiles from
+// chunk*tpb, clipped to nty; never empty), plane w / (strips * ysplit).
+struct AdjWork {
+  int strips, ysplit, tpb, nty, nwork;
+};
+
+struct AdjTile {
+  int item, y, yend, i0, k;
+};
+
+__device__ __forceinline__ AdjTile adj_item(const AdjWork& W, int w) {
+  AdjTile c;
+  c.item = w;
+  const int strip = w % W.strips, rest = w / W.strips;
+  c.y = (rest % W.ysplit) * W.tpb;
+  c.yend = min(W.nty, c.y + W.tpb);
+  c.i0 = strip * kATX;
+  c.k = rest / W.ysplit;
+  return c;
+}
+
+// Periodic wrap of a tile row or column index that lies within [-n, 2n):
+// tiles start inside the mesh and their halos reach at most one period out
+// when n1 >= kAXB and n2 >= kATY + 3 (checked by the launcher, which falls
+// back to the full remainder otherwise).
+template <bool kNear>
+__device__ __forceinline__ int wrap_index(int i, int n) {
+  if (kNear) {
+    i += i < 0 ? n : 0;
+    return i - (i >= n ? n : 0);
+  }
+  i %= n;
+  return i + (i < 0 ? n : 0);
+}
+
+// Loads a rows x cols window of one plane of ``src`` (rows from j, cols
+// from i, periodic) into v[]: element q = t + it * kANT of the window, row
+// q / cols, col q % cols.  All loads of a call are issued before any is used.
+template <bool kNear, int kRows, int kCols>
+__device__ __forceinline__ void load_window(const double* __restrict__ src, const Mesh& m, int k, int j, int i,
+                                            int t, double* v) {
+  constexpr int kN = (kRows * kCols + kANT - 1) / kANT;
+  const double* __restrict__ plane = src + (size_t)k * m.n2 * m.n1;  // uniform; in-plane offsets fit 32 bits
+#pragma unroll
+  for (int it = 0; it < kN; ++it) {
+    const int q = t + it * kANT;
+    if (kRows * kCols % kANT == 0 || q < kRows * kCols) {
+      const int r = q / kCols, x = q % kCols;
+      const int jj = wrap_index<kNear>(j + r, m.n2), ii = wrap_index<kNear>(i + x, m.n1);
+      v[it] = plane[(unsigned)(jj * m.n1 + ii)];
+    }
+  }
+}
+
+// Lag products of four cells with one staged forward row: for j = 1..W,
+//   acc[j-1] += sum_u x[u] D_j f,  D_j f = f_{i+j} - f_{i-j+1} (Faraday,
+//   FORM 0) or f_{i+j-1} - f_{i-j} (Ampere, FORM 1), cell i = first + u,
+// w0 the row from W cells left of the first cell (2W + 4 values).
+template <int FORM>
+__device__ __forceinline__ void lag_products(const double* __restrict__ w0, const double x[4], double acc[kAW]) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  double w[2 * kAW + 4];
+  const v2* src = reinterpret_cast<const v2*>(w0);
+#pragma unroll
+  for (int k = 0; k < kAW + 2; ++k) {
+    const v2 v = src[k];
+    w[2 * k] = v[0];
+    w[2 * k + 1] = v[1];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+#pragma unroll
+    for (int j = 1; j <= kAW; ++j)
+      acc[j - 1] += FORM == 0 ? x[u] * (w[kAW + u + j] - w[kAW + u - j + 1])
+                              : x[u] * (w[kAW + u + j - 1] - w[kAW + u - j]);
+  }
+}
+
+template <int kRows, int kCols>
+__device__ __forceinline__ void store_window(double* dst, int t, const double* v) {
+  constexpr int kN = (kRows * kCols + kANT - 1) / kANT;
+#pragma unroll
+  for (int it = 0; it < kN; ++it) {
+    const int q = t + it * kANT;
+    if (kRows * kCols % kANT == 0 || q < kRows * kCols) dst[q] = v[it];
+  }
+}
+
+// The wide x1 stage on four consecutive cells of one LDS row: for u < 4,
+//   out[u] = sum_q a_q (w[W + u + q - 1] - w[W + u - q]),
+// w the 2W + 3 values of the source row starting W cells left of the first.
+__device__ __forceinline__ void wide4(const double* __restrict__ w0, const Coef16& a, double out[4]) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  double w[2 * kAW + 4];
+  const v2* src = reinterpret_cast<const v2*>(w0);
+#pragma unroll
+  for (int k = 0; k < kAW + 2; ++k) {
+    const v2 v = src[k];
+    w[2 * k] = v[0];
+    w[2 * k + 1] = v[1];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 1; q <= kAW; ++q) s += a.c[q - 1] * (w[kAW + u + q - 1] - w[kAW + u - q]);
+    out[u] = s;
+  }
+}
+
+// Sum over a tile's 256 threads of acc[0..W) through LDS: each thread stores
+// its values (column t of the [W][kRS] table ``tab``), 16 threads sum each
+// row's values in strided groups of 16, and thread t < W returns the sum of
+// row t (others return 0).  Callers have synchronised before the table is
+// written; it is free again on return.
+constexpr int kTS = kANT / kAW;  // threads summing one row
+constexpr int kRS = kANT + 16;   // padded row: the two rows a half-wave reads fall in distinct banks
+static_assert(kTS * kAW == kANT && kANT % kTS == 0, "threads per accumulator row");
+static_assert((size_t)kAW * kRS <= kALdsB, "the tile-sum table fits over lB");
+__device__ __forceinline__ double tile_sum(const double acc[kAW], double* tab, double* grp, int t) {
+#pragma unroll
+  for (int j = 0; j < kAW; ++j) tab[j * kRS + t] = acc[j];
+  __syncthreads();
+  {
+    const int row = t / kTS, part = t % kTS;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < kANT / kTS; i += 2) {
+      s0 += tab[row * kRS + i * kTS + part];
+      s1 += tab[row * kRS + (i + 1) * kTS + part];
+    }
+    grp[row * kTS + part] = s0 + s1;
+  }
+  __syncthreads();
+  double s = 0.0;
+  if (t < kAW) {
+#pragma unroll
+    for (int w = 0; w < kTS; ++w) s += grp[t * kTS + w];
+  }
+  return s;
+}
+
+template <bool kNear>
+__global__ __launch_bounds__(kANT) void adjoint_sweep2d_kernel(AdjPlane P, Mesh m, AdjWork W, Coef16 a, double ty,
+                                                               double b1, double hy, double* __restrict__ partial) {
+  extern __shared__ __align__(16) double lds[];
+  double* sB = lds;                      // [3][kARB][kAXB]
+  double* sE = lds + kALdsB;             // [3][kARE][kAXE]
+  double* sF = lds + kALdsB + kALdsE;    // [6][kATY][kAXF]: rows j0 .., cols i0-W ..
+  const int t = threadIdx.x;
+  auto B = [&](int c, int r, int x) -> double& { return sB[((size_t)c * kARB + r) * kAXB + x]; };
+  auto Ev = [&](int c, int r, int x) -> double& { return sE[((size_t)c * kARE + r) * kAXE + x]; };
+  // a tile's loads: lB (rows j0-2 .., cols i0-2W ..), lE (rows j0-1 ..,
+  // cols i0-W ..) and the forward rows of the lag products (rows j0 ..,
+  // cols i0-W ..), into registers
+  constexpr int kPB = (kARB * kAXB + kANT - 1) / kANT, kPE = (kARE * kAXE + kANT - 1) / kANT;
+  constexpr int kPF = (kATY * kAXF + kANT - 1) / kANT;
+  double vB[3][kPB], vE[3][kPE], vF[6][kPF];
+  auto load_tile = [&](const AdjTile& c) {
+    const int j0 = c.y * kATY;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) load_window<kNear, kARB, kAXB>(P.li[3 + q], m, c.k, j0 - 2, c.i0 - 2 * kAW, t, vB[q]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) load_window<kNear, kARE, kAXE>(P.li[q], m, c.k, j0 - 1, c.i0 - kAW, t, vE[q]);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) load_window<kNear, kATY, kAXF>(P.fw[q], m, c.k, j0, c.i0 - kAW, t, vF[q]);
+  };
+  double* tab = sB;  // [W][kRS] tile-sum table, over lB once its products are taken
+  __shared__ double grp[kAW * kTS];
+  double totE = 0.0, totB = 0.0;  // thread t < W: the workgroup's sums of lag t + 1
+  const int tr = t / (kATX / 4), g = t % (kATX / 4);  // this thread's row and 4-cell group in a tile
+  AdjTile cur = adj_item(W, blockIdx.x);  // gridDim.x <= nwork
+  load_tile(cur);
+  for (;;) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) store_window<kARB, kAXB>(sB + (size_t)q * kARB * kAXB, t, vB[q]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) store_window<kARE, kAXE>(sE + (size_t)q * kARE * kAXE, t, vE[q]);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) store_window<kATY, kAXF>(sF + (size_t)q * kATY * kAXF, t, vF[q]);
+    __syncthreads();
+    // the next tile of this workgroup: the next along x2 in the item, else
+    // the first of its next item; its loads fly while this one is computed
+    AdjTile nxt = cur;
+    if (++nxt.y >= nxt.yend) nxt = adj_item(W, cur.item + gridDim.x);
+    const bool more = nxt.item < W.nwork;
+    if (more) load_tile(nxt);
+    const int i0 = cur.i0, j0 = cur.y * kATY, k = cur.k;
+    const int gi = i0 + 4 * g, gj = j0 + tr;
+    bool own[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) own[u] = gi + u < m.n1 && gj < m.n2;
+    double lb2[4], lb3[4];  // the input lB at the interior cells (stage-3 products)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      lb2[u] = own[u] ? B(1, tr + 2, 2 * kAW + 4 * g + u) : 0.0;
+      lb3[u] = own[u] ? B(2, tr + 2, 2 * kAW + 4 * g + u) : 0.0;
+    }
+    // lE1 = lE - h curl_B[C^E] lB on the whole lE tile, four cells at a time
+    for (int q = t; q < kARE * (kAXE / 4); q += kANT) {
+      const int re = q / (kAXE / 4), ce = 4 * (q % (kAXE / 4));
+      const int rb = re + 1, cb = ce + kAW;
+      double d3[4], d2[4];
+      wide4(&B(2, rb, ce), a, d3);
+      wide4(&B(1, rb, ce), a, d2);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        Ev(0, re, ce + u) += ty * (B(2, rb, cb + u) - B(2, rb - 1, cb + u));
+        Ev(1, re, ce + u) -= d3[u];
+        Ev(2, re, ce + u) += d2[u] - ty * (B(0, rb, cb + u) - B(0, rb - 1, cb + u));
+      }
+    }
+    __syncthreads();
+    // lB1 = lB + dt curl_E[c e1] lE1 on rows j0-1 .. j0+TY-1, cols i0-W .. i0+TX+W-2
+    constexpr int kNB = kATX + 2 * kAW - 1;
+    for (int q = t; q < (kATY + 1) * kNB; q += kANT) {
+      const int rb = 1 + q / kNB, cb = kAW + q % kNB;
+      const int re = rb - 1, ce = cb - kAW;
+      B(0, rb, cb) -= hy * (Ev(2, re + 1, ce) - Ev(2, re, ce));
+      B(1, rb, cb) += b1 * (Ev(2, re, ce + 1) - Ev(2, re, ce));
+      B(2, rb, cb) -= b1 * (Ev(1, re, ce + 1) - Ev(1, re, ce)) - hy * (Ev(0, re + 1, ce) - Ev(0, re, ce));
+    }
+    __syncthreads();
+    // lE0 = lE1 - h curl_B[C^E] lB1 on the interior; write lE0 and lB1
+    {
+      const int re = tr + 1, ce = kAW + 4 * g, rb = re + 1, cb = ce + kAW;
+      double d3[4], d2[4];
+      wide4(&B(2, rb, ce), a, d3);
+      wide4(&B(1, rb, ce), a, d2);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (!own[u]) continue;
+        const size_t o = ((size_t)k * m.n2 + gj) * m.n1 + gi + u;
+        P.lo[0][o] = Ev(0, re, ce + u) + ty * (B(2, rb, cb + u) - B(2, rb - 1, cb + u));
+        P.lo[1][o] = Ev(1, re, ce + u) - d3[u];
+        P.lo[2][o] = Ev(2, re, ce + u) + d2[u] - ty * (B(0, rb, cb + u) - B(0, rb - 1, cb + u));
+        P.lo[3][o] = B(0, rb, cb + u);
+        P.lo[4][o] = B(1, rb, cb + u);
+        P.lo[5][o] = B(2, rb, cb + u);
+      }
+    }
+    // lag products of the interior cells, one form at a time: Faraday
+    // (dL/dC^E) from E'2, E'3 with the input lB (kept in registers) and
+    // E^n2, E^n3 with lB1 (in sB); Ampere (dL/dC^B) from B'2, B'3 with lE1
+    // (in sE).  Window of 4 cells at i: staged cols 4g .. 4g + 35 = x1
+    // i - W .. i + W + 3 of row tr.
+    auto frow = [&](int arr) { return &sF[((size_t)arr * kATY + tr) * kAXF + 4 * g]; };
+    {
+      double acc[kAW], xs[4];
+#pragma unroll
+      for (int j = 0; j < kAW; ++j) acc[j] = 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xs[u] = -lb3[u];
+      lag_products<0>(frow(0), xs, acc);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xs[u] = lb2[u];
+      lag_products<0>(frow(1), xs, acc);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xs[u] = own[u] ? -B(2, tr + 2, 2 * kAW + 4 * g + u) : 0.0;
+      lag_products<0>(frow(4), xs, acc);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xs[u] = own[u] ? B(1, tr + 2, 2 * kAW + 4 * g + u) : 0.0;
+      lag_products<0>(frow(5), xs, acc);
+      __syncthreads();  // sB is free: it holds the table
+      totE += tile_sum(acc, tab, grp, t);
+    }
+    {
+      double acc[kAW], xs[4];
+#pragma unroll
+      for (int j = 0; j < kAW; ++j) acc[j] = 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xs[u] = own[u] ? Ev(2, tr + 1, kAW + 4 * g + u) : 0.0;
+      lag_products<1>(frow(2), xs, acc);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xs[u] = own[u] ? -Ev(1, tr + 1, kAW + 4 * g + u) : 0.0;
+      lag_products<1>(frow(3), xs, acc);
+      totB += tile_sum(acc, tab, grp, t);
+    }
+    if (!more) break;
+    cur = nxt;
+  }
+  if (t < kAW) {
+    partial[(size_t)blockIdx.x * 2 * kAW + t] = totE;
+    partial[(size_t)blockIdx.x * 2 * kAW + kAW + t] = totB;
+  }
+}
+
+// gE[j] += sE * sum_b partial[b][j], gB[j] += sB * sum_b partial[b][W + j]
+__global__ __launch_bounds__(256) void coef_finalize2_kernel(const double* __restrict__ partial, int64_t nblocks,
+                                                             int M, double sE, double sBv, double* __restrict__ gE,
+                                                             double* __restrict__ gB) {
+  __shared__ double red[4];
+  const int j = blockIdx.x % M, which = blockIdx.x / M;
+  const int col = which * kAW + j;
+  double s = 0;
+  for (int64_t b = threadIdx.x; b < nblocks; b += 256) s += partial[b * 2 * kAW + col];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double v = ((red[0] + red[1]) + red[2]) + red[3];
+    if (which == 0)
+      gE[j] += sE * v;
+    else
+      gB[j] += sBv * v;
+  }
 }
 
 // Reverse of boris(): u is the input momentum, lun the cotangent of the
@@ -477,6 +835,71 @@ int launch_coef_grad(const Mesh& m, int form, const double* la, const double* fa
                        partial);
   hipLaunchKernelGGL(coef_finalize_kernel, dim3(M), dim3(256), 0, s, (const double*)partial, nblocks, scale, g);
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "coefficient-gradient launch failed");
+}
+
+// Work items for the fused reverse: enough chunks along x2 that every
+// persistent workgroup has at least one item, each chunk never empty.
+static AdjWork adj_work(const Mesh& m) {
+  AdjWork W;
+  W.strips = (m.n1 + kATX - 1) / kATX;
+  W.nty = (m.n2 + kATY - 1) / kATY;
+  const int64_t pairs = (int64_t)W.strips * m.n3;
+  const int64_t want = (kAdjBlocks + pairs - 1) / pairs;
+  const int ys = (int)std::min<int64_t>(W.nty, std::max<int64_t>(1, want));
+  W.tpb = (W.nty + ys - 1) / ys;
+  W.ysplit = (W.nty + W.tpb - 1) / W.tpb;
+  const int64_t total = pairs * W.ysplit;
+  W.nwork = total > INT32_MAX - kAdjBlocks ? -1 : (int)total;  // -1: too many items for int indices
+  return W;
+}
+
+bool adjoint_sweep2d_fits(const Mesh& m) {
+  return (int64_t)m.n1 * m.n2 <= INT32_MAX && adj_work(m).nwork > 0;
+}
+
+int64_t adjoint_sweep2d_blocks(const Mesh& m) {
+  const AdjWork W = adj_work(m);
+  return W.nwork < 0 ? kAdjBlocks : std::min<int64_t>(W.nwork, kAdjBlocks);
+}
+
+int launch_adjoint_sweep2d(const Mesh& m, void* const lE[3], void* const lB[3], void* const lEo[3],
+                           void* const lBo[3], const void* const Enext[3], const void* const Bhalf[3],
+                           void* const En[3], const double* CE, int ME, double cb1, double dt, int M,
+                           double* partial, double* gCE, double* gCB, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  AdjPlane P;
+  for (int c = 0; c < 3; ++c) {
+    P.li[c] = (const double*)lE[c];
+    P.li[3 + c] = (const double*)lB[c];
+    P.lo[c] = (double*)lEo[c];
+    P.lo[3 + c] = (double*)lBo[c];
+  }
+  P.fw[0] = (const double*)Enext[1];
+  P.fw[1] = (const double*)Enext[2];
+  P.fw[2] = (const double*)Bhalf[1];
+  P.fw[3] = (const double*)Bhalf[2];
+  P.fw[4] = (const double*)En[1];
+  P.fw[5] = (const double*)En[2];
+  Coef16 a;
+  const double h = -0.5 * dt;
+  for (int q = 0; q < kAW; ++q) a.c[q] = (q < ME ? CE[q] : 0.0) * h / m.dx1;
+  if (!adjoint_sweep2d_fits(m)) return set_error(PIC_EUNSUPPORTED, "adjoint sweep: mesh too large for the fused path");
+  const AdjWork W = adj_work(m);
+  const int64_t nb = adjoint_sweep2d_blocks(m);
+  const bool near = m.n1 >= kAXB && m.n2 >= kATY + 3;
+  const void* kern = near ? (const void*)adjoint_sweep2d_kernel<true> : (const void*)adjoint_sweep2d_kernel<false>;
+  if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kALds) != hipSuccess)
+    return set_error(PIC_EHIP, "adjoint sweep: cannot reserve %zu bytes of LDS", kALds);
+  const double ty = h / m.dx2, bx = cb1 * (-dt) / m.dx1, hy = -dt / m.dx2;
+  if (near)
+    hipLaunchKernelGGL(adjoint_sweep2d_kernel<true>, dim3((unsigned)nb), dim3(kANT), kALds, s, P, m, W, a, ty, bx, hy,
+                       partial);
+  else
+    hipLaunchKernelGGL(adjoint_sweep2d_kernel<false>, dim3((unsigned)nb), dim3(kANT), kALds, s, P, m, W, a, ty, bx,
+                       hy, partial);
+  hipLaunchKernelGGL(coef_finalize2_kernel, dim3(2 * M), dim3(256), 0, s, (const double*)partial, nb, M,
+                     0.5 * dt / m.dx1, dt / m.dx1, gCE, gCB);
+  return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "adjoint sweep launch failed");
 }
 
 int launch_adjoint_push(const Mesh& m, void* const E[3], void* const B[3], void* const lE[3], void* const lB[3],

@@ -809,6 +809,22 @@ static int adjoint_args(pic_grid* g, const pic_adjoint* adj, const pic_particles
       return set_error(PIC_ESHAPE, "adjoint fields must be 16-byte aligned");
   }
   if (!adj->gCE || !adj->gCB) return set_error(PIC_EINVAL, "coefficient-gradient pointer is NULL");
+  const bool outs = adj->lEo[0] || adj->lEo[1] || adj->lEo[2] || adj->lBo[0] || adj->lBo[1] || adj->lBo[2];
+  if (outs) {
+    const void* others[] = {adj->lE[0], adj->lE[1], adj->lE[2], adj->lB[0], adj->lB[1], adj->lB[2],
+                            adj->En[0], adj->En[1], adj->En[2], adj->Bn[0], adj->Bn[1], adj->Bn[2],
+                            adj->Bh[0], adj->Bh[1], adj->Bh[2], g->E[0], g->E[1], g->E[2],
+                            g->B[0], g->B[1], g->B[2]};
+    void* const o[6] = {adj->lEo[0], adj->lEo[1], adj->lEo[2], adj->lBo[0], adj->lBo[1], adj->lBo[2]};
+    for (int c = 0; c < 6; ++c) {
+      if (!o[c]) return set_error(PIC_EINVAL, "output cotangents: all six or none");
+      if ((uintptr_t)o[c] & 15) return set_error(PIC_ESHAPE, "adjoint fields must be 16-byte aligned");
+      for (const void* q : others)
+        if (q == o[c]) return set_error(PIC_EINVAL, "an output cotangent aliases another array");
+      for (int d = 0; d < c; ++d)
+        if (o[d] == o[c]) return set_error(PIC_EINVAL, "output cotangents alias each other");
+    }
+  }
   for (int s = 0; s < nspecies; ++s) {
     int rc = check_particles(g, species[s]);
     if (rc) return rc;
@@ -824,10 +840,33 @@ static int adjoint_args(pic_grid* g, const pic_adjoint* adj, const pic_particles
 
 // The adjoint step with ``partial`` (coef_partial_blocks * PIC_MAX_M
 // doubles of device memory) for the coefficient reductions; allocates nothing.
+// The fused 2D reverse applies: out-of-place outputs, the forward state and
+// B^{n+1/2} given, a 2D grid and a one-coefficient Ampere stencil.
+static bool adjoint_fused(const pic_grid* g, const pic_adjoint* adj) {
+  const bool outs = adj->lEo[0] != nullptr;
+  const bool next = adj->En[0] && adj->En[1] && adj->En[2] && adj->Bn[0] && adj->Bn[1] && adj->Bn[2];
+  const bool half = next && adj->Bh[0] && adj->Bh[1] && adj->Bh[2];
+  return outs && half && g->ndim == 2 && g->MB == 1 && adjoint_sweep2d_fits(g->mesh);
+}
+
+// Doubles of coefficient scratch the step needs.
+static int64_t adjoint_partial_need(const pic_grid* g, const pic_adjoint* adj) {
+  if (adjoint_fused(g, adj)) return adjoint_sweep2d_blocks(g->mesh) * 2 * PIC_MAX_M;
+  return (int64_t)coef_partial_blocks(g->mesh) * PIC_MAX_M;
+}
+
 static int adjoint_body(pic_grid* g, const pic_adjoint* adj, const pic_particles* const* species,
                         pic_particles* const* lambda, int nspecies, int pusher, double* partial) {
   const Mesh& m = g->mesh;
   const double dt = g->dt;
+  if (adjoint_fused(g, adj)) {
+    void* En[3] = {g->E[0], g->E[1], g->E[2]};
+    int rc = launch_adjoint_sweep2d(m, adj->lE, adj->lB, adj->lEo, adj->lBo, adj->En, adj->Bh, En, g->CE, g->ME,
+                                    g->CB[0], dt, g->M, partial, adj->gCE, adj->gCB, g->stream);
+    for (int s = 0; s < nspecies && !rc; ++s)
+      rc = launch_adjoint_push(m, g->E, g->B, adj->lEo, adj->lBo, *species[s], *lambda[s], pusher, dt, g->stream);
+    return rc;
+  }
   void* none[3] = {nullptr, nullptr, nullptr};
   auto d = [](const void* p) { return (const double*)p; };
   void* const* lE = adj->lE;
@@ -876,6 +915,13 @@ static int adjoint_body(pic_grid* g, const pic_adjoint* adj, const pic_particles
   // particles: reverse of position update, push and gather at t^n
   for (int s = 0; s < nspecies && !rc; ++s)
     rc = launch_adjoint_push(m, g->E, g->B, lE, lB, *species[s], *lambda[s], pusher, dt, g->stream);
+  if (!rc && adj->lEo[0]) {  // out of place requested on the in-place path: copy the result
+    const size_t bytes = (size_t)g->n[0] * g->n[1] * g->n[2] * sizeof(double);
+    for (int c = 0; c < 3 && !rc; ++c)
+      if (hipMemcpyAsync(adj->lEo[c], lE[c], bytes, hipMemcpyDeviceToDevice, g->stream) != hipSuccess ||
+          hipMemcpyAsync(adj->lBo[c], lB[c], bytes, hipMemcpyDeviceToDevice, g->stream) != hipSuccess)
+        rc = set_error(PIC_EHIP, "adjoint output copy");
+  }
   return rc;
 }
 
@@ -883,7 +929,7 @@ int pic_adjoint_step(pic_grid* g, const pic_adjoint* adj, const pic_particles* c
                      pic_particles* const* lambda, int nspecies, int pusher) {
   int rc = adjoint_args(g, adj, species, lambda, nspecies, pusher);
   if (rc) return rc;
-  const int64_t need = (int64_t)coef_partial_blocks(g->mesh) * PIC_MAX_M;
+  const int64_t need = adjoint_partial_need(g, adj);
   if (need > g->partial_cap) {
     (void)hipStreamSynchronize(g->stream);
     if (g->partial) (void)hipFree(g->partial);
@@ -900,12 +946,12 @@ int pic_adjoint_step_noalloc(pic_grid* g, const pic_adjoint* adj, const pic_part
                              pic_particles* const* lambda, int nspecies, int pusher) {
   int rc = adjoint_args(g, adj, species, lambda, nspecies, pusher);
   if (rc) return rc;
-  const int64_t need = (int64_t)coef_partial_blocks(g->mesh) * PIC_MAX_M;
+  const int64_t need = adjoint_partial_need(g, adj);
   if (need > kNoAllocDoubles)
     return set_error(PIC_EUNSUPPORTED,
                      "the allocation-free adjoint step needs %lld doubles of scratch for this mesh; it holds %lld "
-                     "(%lld reduction blocks of %d x1 rows)",
-                     (long long)need, (long long)kNoAllocDoubles, (long long)(kNoAllocDoubles / PIC_MAX_M), 8);
+                     "(use pic_adjoint_step)",
+                     (long long)need, (long long)kNoAllocDoubles);
   if (!g->noalloc) return set_error(PIC_EHIP, "the adjoint scratch has no device address");
   return adjoint_body(g, adj, species, lambda, nspecies, pusher, g->noalloc);
 }

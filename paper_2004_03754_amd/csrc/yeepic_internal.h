@@ -92,6 +92,18 @@ size_t stage_doubles(const TileGeom& tg);
 int coef_partial_blocks(const Mesh& m);
 int launch_coef_grad(const Mesh& m, int form, const double* la, const double* fa, const double* lb,
                      const double* fb, double scale, int M, double* partial, double* g, void* stream);
+// Fused reverse of one 2D vacuum sweep with a one-coefficient Ampere
+// stencil (C^B = cb1 e1): (lE, lB) at t^{n+1} -> (lEo, lBo) at t^n, out of
+// place, from E^{n+1}, B^{n+1/2} and E^n; adds dL/dC^E and dL/dC^B (M
+// entries).  ``partial`` holds adjoint_sweep2d_blocks(m) * 2 * PIC_MAX_M doubles
+// (at most 256 workgroups).  adjoint_sweep2d_fits: the mesh is within the
+// kernel's index range (a plane below 2^31 cells).
+bool adjoint_sweep2d_fits(const Mesh& m);
+int64_t adjoint_sweep2d_blocks(const Mesh& m);
+int launch_adjoint_sweep2d(const Mesh& m, void* const lE[3], void* const lB[3], void* const lEo[3],
+                           void* const lBo[3], const void* const Enext[3], const void* const Bhalf[3],
+                           void* const En[3], const double* CE, int ME, double cb1, double dt, int M,
+                           double* partial, double* gCE, double* gCB, void* stream);
 int launch_adjoint_push(const Mesh& m, void* const E[3], void* const B[3], void* const lE[3], void* const lB[3],
                         const pic_particles& p, const pic_particles& lam, int pusher, double dt, void* stream);
 

@@ -10,7 +10,7 @@ from oracle import adjoint as ad, pic  # noqa: E402
 from paper_2004_03754_amd import binding as b, workloads as wl  # noqa: E402
 
 torch = pytest.importorskip("torch")
-from gpu_util import dev, host  # noqa: E402
+from gpu_util import check, dev, host  # noqa: E402
 
 DX = (wl.DX1, wl.DX2, wl.DX3)
 QM = -1.0
@@ -365,3 +365,47 @@ def test_envelope_gradients_match_central_differences(coeffs16):
         fd = (vals[0] - vals[1]) / (2 * h)
         gr = {"CE": ce.grad, "CB": cb.grad, "a0": a0.grad}[name][j].item()
         assert abs(fd - gr) <= 1e-5 * abs(fd) + 1e-8 * max(1.0, abs(float(Lv))), (name, j, fd, gr)
+
+
+@pytest.mark.parametrize("n,npart,pusher", [((256, 10, 3), 300, "boris"), ((64, 5, 2), 100, "analytic"),
+                                            ((384, 17, 1), 200, "boris"), ((448, 21, 3), 300, "analytic"),
+                                            ((256, 24, 200), 400, "boris")])
+def test_fused_2d_reverse_matches_in_place_stages(n, npart, pusher, coeffs16):
+    """The fused 2D reverse sweep (out-of-place cotangents, forward state and
+    B^{n+1/2} given, C^B = e1) against the three in-place stages on the same
+    inputs: field, particle and coefficient cotangents to 1e-12 (norm-wise),
+    on stacks of planes with tiles overhanging the mesh in x1 and x2, meshes
+    narrower than a tile's halo (the general periodic wrap), and 400 work
+    items over the 256 persistent workgroups (several items per workgroup)."""
+    CE, CB = coeffs16
+    E, B, x, u = _case(n, 31, npart, 2, scale=2.0)
+    x[2] = np.floor(wl.rng(33).random(npart) * n[2]) + 0.5
+    lE, lB, lx, lu = _cotangents(n, npart, 32)
+    res = []
+    for oop in (False, True):
+        grid = b.Grid([dev(e) for e in E], [dev(v) for v in B], DX[:2], wl.DT, CE, CB, ndim=2)
+        pn = b.Particles(dev(x), dev(u), q=QM, m=1.0)
+        En = [torch.empty_like(a) for a in grid.E]
+        Bn = [torch.empty_like(a) for a in grid.B]
+        Bh = [torch.empty_like(a) for a in grid.B]
+        grid.step_to([pn], En, Bn, pusher=pusher, B_half=Bh)
+        p = b.Particles(dev(x), dev(u), q=QM, m=1.0)
+        lEd, lBd = [dev(a) for a in lE], [dev(a) for a in lB]
+        lxd, lud = dev(lx), dev(lu)
+        lam = b.Particles(lxd, lud, q=QM, m=1.0)
+        gCE = torch.zeros(16, dtype=torch.float64, device="cuda:0")
+        gCB = torch.zeros(16, dtype=torch.float64, device="cuda:0")
+        kw = dict(next_E=En, next_B=Bn, half_B=Bh)
+        if oop:
+            kw["out_E"] = [torch.empty_like(a) for a in lEd]
+            kw["out_B"] = [torch.empty_like(a) for a in lBd]
+        grid.adjoint_step(lEd, lBd, gCE, gCB, [p], [lam], pusher=pusher, **kw)
+        grid.sync()
+        f = (kw["out_E"] + kw["out_B"]) if oop else (lEd + lBd)
+        res.append([host(a) for a in f] + [host(lxd)[:2], host(lud), host(gCE), host(gCB)])
+        if oop:  # the inputs are left unchanged
+            assert all(np.array_equal(host(a), c) for a, c in zip(lEd + lBd, list(lE) + list(lB)))
+        grid.close()
+    names = ["lE1", "lE2", "lE3", "lB1", "lB2", "lB3", "lx", "lu", "gCE", "gCB"]
+    for name, g_, r in zip(names, res[1], res[0]):
+        check(_rel(g_, r), 1e-12, f"fused 2D reverse {n} {pusher} {name}")

@@ -15,7 +15,7 @@ from gpu_util import check, dev, host  # noqa: E402
 DX = (wl.DX1, wl.DX2, wl.DX3)
 
 
-def _run(n, ndim, npart, seed, pusher, noalloc, CE, CB, with_next):
+def _run(n, ndim, npart, seed, pusher, noalloc, CE, CB, with_next, out_of_place=False):
     E, B = wl.random_fields(n, seed=seed, scale=0.3)
     L = [n[d] * DX[d] for d in range(3)]
     x, u = wl.uniform_particles(npart, [0, 0, 0], L, seed=seed + 1, u_th=0.3)
@@ -39,9 +39,13 @@ def _run(n, ndim, npart, seed, pusher, noalloc, CE, CB, with_next):
         Bh = [torch.empty_like(a) for a in grid.B]
         grid.step_to([pn], En, Bn, pusher=pusher, B_half=Bh)
         nxt = {"next_E": En, "next_B": Bn, "half_B": Bh}
+    if out_of_place:
+        nxt["out_E"] = [torch.empty_like(a) for a in lE]
+        nxt["out_B"] = [torch.empty_like(a) for a in lB]
     grid.adjoint_step(lE, lB, gCE, gCB, [p], [lam], pusher=pusher, noalloc=noalloc, **nxt)
     grid.sync()
-    out = [host(a) for a in lE + lB] + [host(lx), host(lu), host(gCE), host(gCB)]
+    fo = (nxt["out_E"] + nxt["out_B"]) if out_of_place else (lE + lB)
+    out = [host(a) for a in fo] + [host(lx), host(lu), host(gCE), host(gCB)]
     grid.close()
     return out
 
@@ -49,15 +53,15 @@ def _run(n, ndim, npart, seed, pusher, noalloc, CE, CB, with_next):
 @pytest.mark.parametrize("pusher", ["boris", "analytic"])
 def test_noalloc_adjoint_matches_allocating_entry_point(pusher, coeffs16):
     """Two allocation-free calls in a row (a 2D stack of 16 planes of
-    2048 x 64, then a smaller 3D mesh), each against pic_adjoint_step on the
-    same inputs: field, particle and coefficient cotangents to 1e-12
-    (norm-wise; the particle scatter uses atomics, so the last bits of the
+    2048 x 64 on the fused out-of-place path, then a smaller 3D mesh in
+    place), each against pic_adjoint_step on the same inputs: field,
+    particle and coefficient cotangents to 1e-12 (norm-wise; the particle scatter uses atomics, so the last bits of the
     field cotangents may differ between any two runs)."""
     CE, CB = coeffs16
-    cases = [((2048, 64, 16), 2, 3000, 31, True), ((256, 8, 6), 3, 500, 41, False)]
-    for n, ndim, npart, seed, with_next in cases:
-        ref = _run(n, ndim, npart, seed, pusher, False, CE, CB, with_next)
-        got = _run(n, ndim, npart, seed, pusher, True, CE, CB, with_next)
+    cases = [((2048, 64, 16), 2, 3000, 31, True, True), ((256, 8, 6), 3, 500, 41, False, False)]
+    for n, ndim, npart, seed, with_next, oop in cases:
+        ref = _run(n, ndim, npart, seed, pusher, False, CE, CB, with_next, oop)
+        got = _run(n, ndim, npart, seed, pusher, True, CE, CB, with_next, oop)
         names = ["lE1", "lE2", "lE3", "lB1", "lB2", "lB3", "lx", "lu", "gCE", "gCB"]
         for name, g_, r in zip(names, got, ref):
             if name == "lx" and ndim == 2:
@@ -67,9 +71,10 @@ def test_noalloc_adjoint_matches_allocating_entry_point(pusher, coeffs16):
 
 
 def test_noalloc_adjoint_refuses_meshes_beyond_its_scratch(coeffs16):
-    """A mesh needing more than the fixed 2^17 doubles of partial sums
-    (8192 blocks of 1024 x 8 cells) is refused with PIC_EUNSUPPORTED before
-    any launch; the allocating entry point takes it."""
+    """A mesh needing more than the fixed 2^17 doubles of partial sums on
+    the in-place path (8192 blocks of 1024 x 8 cells) is refused with
+    PIC_EUNSUPPORTED before any launch; the allocating entry point takes
+    it."""
     CE, CB = coeffs16
     n = (1024, 256, 264)  # 8448 blocks of 1024 x 8 cells (69M cells)
     shape = (n[2], n[1], n[0])
