@@ -775,7 +775,7 @@ __device__ __forceinline__ T faraday_w(const T (&w)[NW], const T (&a)[ME], int u
   return acc;
 }
 
-template <typename T, int ME, int TX, int TY, int NT, int WPE, bool HAS_J>
+template <typename T, int ME, int TX, int TY, int NT, int WPE, bool HAS_J, bool FLAT>
 __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict__ iE1, const T* __restrict__ iE2,
                                                        const T* __restrict__ iE3, const T* __restrict__ iB1,
                                                        const T* __restrict__ iB2, const T* __restrict__ iB3,
@@ -895,13 +895,21 @@ __global__ __launch_bounds__(NT, WPE) void sweep_yee_kernel(const T* __restrict_
   };
 
   T bn[3][RW], nn[2][RW], cb[3][RW], jv[HAS_J ? 3 : 1][RW];
-  auto load_own = [&](size_t pk, size_t pk1) {  // B^n(k), E1/E2(k+1) at the stage-1 positions
+  // B^n(k), E1/E2(k+1) at the stage-1 positions.  A stack of 2D planes
+  // (FLAT) has no x3 derivative, so the next plane's E1/E2 are not read.
+  auto load_own = [&](size_t pk, size_t pk1) {
     const size_t o = pk + g1, on = pk1 + g1;
     ld_run<T, RW>(iB1 + o, bn[0]);
     ld_run<T, RW>(iB2 + o, bn[1]);
     ld_run<T, RW>(iB3 + o, bn[2]);
-    ld_run<T, RW>(iE1 + on, nn[0]);
-    ld_run<T, RW>(iE2 + on, nn[1]);
+    if constexpr (FLAT) {
+#pragma unroll
+      for (int u = 0; u < RW; ++u) nn[0][u] = nn[1][u] = 0;
+      (void)on;
+    } else {
+      ld_run<T, RW>(iE1 + on, nn[0]);
+      ld_run<T, RW>(iE2 + on, nn[1]);
+    }
   };
   auto load_J = [&](size_t pk) {
     if constexpr (HAS_J) {
@@ -1176,7 +1184,11 @@ int launch_sweep_yee(const Mesh& m, void* const Ein[3], void* const Bin[3], void
                      int wgs_per_cu, hipStream_t s) {
   using G = YeeGeom<T, ME, TX, TY>;
   const bool hasJ = J && J[0];
-  auto kern = hasJ ? sweep_yee_kernel<T, ME, TX, TY, NT, WPE, true> : sweep_yee_kernel<T, ME, TX, TY, NT, WPE, false>;
+  const bool flat = m.ndim == 2;
+  auto kern = hasJ ? (flat ? sweep_yee_kernel<T, ME, TX, TY, NT, WPE, true, true>
+                           : sweep_yee_kernel<T, ME, TX, TY, NT, WPE, true, false>)
+                   : (flat ? sweep_yee_kernel<T, ME, TX, TY, NT, WPE, false, true>
+                           : sweep_yee_kernel<T, ME, TX, TY, NT, WPE, false, false>);
   static_assert(G::lds_bytes <= 160 * 1024, "sweep tile exceeds LDS");
   if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G::lds_bytes) !=
       hipSuccess)

@@ -367,6 +367,70 @@ def test_envelope_gradients_match_central_differences(coeffs16):
         assert abs(fd - gr) <= 1e-5 * abs(fd) + 1e-8 * max(1.0, abs(float(Lv))), (name, j, fd, gr)
 
 
+def test_config4_length_run_matches_oracle(coeffs16):
+    """The differentiated workload's shape at its length: 2 planes, 256
+    steps, checkpoints every K = 64, Boris; each plane a sin^2 pulse
+    (L_p = 4 lambda0, head at 8 lambda0, a0 = 10^U(0,3), seed 4) with 32
+    electrons at rest spread over 2 lambda0 ahead of it on the middle x2
+    line; loss = mean final gamma + the vacuum phase error of E2 against the
+    initial pulse moved on by the elapsed time.  Gradients with respect to
+    C^E, C^B, the initial fields and the particles against the oracle's
+    autograd (each step checkpointed on the CPU side so that 256 steps fit
+    in memory), at the FP64 bound 1e-12 (norm-wise; about 1e-13 measured)."""
+    from torch.utils.checkpoint import checkpoint
+
+    from paper_2004_03754_amd import autograd as pa
+    CE, CB = coeffs16
+    n1, n2, nb, npb, nsteps, K = 512, 16, 2, 32, 256, 64
+    L0 = wl.LAMBDA0
+    a0 = 10.0 ** (3.0 * wl.rng(4).random(nb))
+    planes = [wl.laser_fields((n1, n2, 1), DX, wl.Sin2Pulse(a0=float(a), Lp=4 * L0), x_head=8 * L0) for a in a0]
+    refs = [wl.laser_fields((n1, n2, 1), DX, wl.Sin2Pulse(a0=float(a), Lp=4 * L0), x_head=8 * L0 + nsteps * wl.DT)
+            for a in a0]
+    E = [np.concatenate([pl[0][c] for pl in planes], 0) for c in range(3)]
+    B = [np.concatenate([pl[1][c] for pl in planes], 0) for c in range(3)]
+    Eref2 = np.concatenate([r[0][1] for r in refs], 0)
+    x = np.zeros((3, nb * npb))
+    x[0] = np.tile(8.5 * L0 + np.arange(npb) * (2 * L0 / npb), nb)
+    x[1] = 0.5 * n2 * DX[1]
+    x[2] = np.repeat(np.arange(nb) + 0.5, npb)
+    u = np.zeros_like(x)
+    leaves = [_t(CE).requires_grad_(), _t(CB).requires_grad_()] + \
+             [dev(a).requires_grad_() for a in E + B] + [dev(x).requires_grad_(), dev(u).requires_grad_()]
+    cfg = pa.RunConfig(DX, wl.DT, nsteps, K=K, ndim=2, q=QM)
+    Ef, Bf, xf, uf = pa.run(leaves[0], leaves[1], leaves[2:5], leaves[5:8], leaves[8], leaves[9], cfg)
+    den = float(np.sum(Eref2 ** 2))
+    L = torch.mean(torch.sqrt(1.0 + torch.sum(uf * uf, 0))) + torch.sum((Ef[1] - dev(Eref2)) ** 2) / den
+    L.backward()
+
+    def one(*s):
+        En, Bn, xn, un = ad.step(s[:3], s[3:6], s[6], s[7], s[8], s[9], DX, wl.DT, QM,
+                                 (n1 * DX[0], n2 * DX[1], DX[2]), 2)
+        return (*En, *Bn, xn, un)
+
+    gsum = {"CE": 0, "CB": 0}
+    for k in range(nb):
+        ol = [_t(CE).requires_grad_(), _t(CB).requires_grad_()] + \
+             [_t(a[k:k + 1]).requires_grad_() for a in E + B] + \
+             [_t(x[:, k * npb:(k + 1) * npb]).requires_grad_(), _t(u[:, k * npb:(k + 1) * npb]).requires_grad_()]
+        st = tuple(ol[2:])
+        for _ in range(nsteps):
+            st = checkpoint(one, *st, ol[0], ol[1], use_reentrant=False)
+        gam = torch.sqrt(1.0 + torch.sum(st[7] * st[7], 0))
+        Lk = torch.sum(gam) / (nb * npb) + torch.sum((st[1] - _t(Eref2[k:k + 1])) ** 2) / den
+        gr = torch.autograd.grad(Lk, ol)
+        gsum["CE"] = gsum["CE"] + gr[0].numpy()
+        gsum["CB"] = gsum["CB"] + gr[1].numpy()
+        for i in range(6):
+            check(_rel(host(leaves[2 + i].grad)[k:k + 1], gr[2 + i].numpy()), 1e-12,
+                  f"config-4 length field grad {i} plane {k}")
+        sl = slice(k * npb, (k + 1) * npb)
+        check(_rel(host(leaves[8].grad)[:2, sl], gr[8].numpy()[:2]), 1e-12, f"config-4 length x grad plane {k}")
+        check(_rel(host(leaves[9].grad)[:, sl], gr[9].numpy()), 1e-12, f"config-4 length u grad plane {k}")
+    check(_rel(leaves[0].grad.numpy(), gsum["CE"]), 1e-12, "config-4 length dL/dC^E")
+    check(_rel(leaves[1].grad.numpy(), gsum["CB"]), 1e-12, "config-4 length dL/dC^B")
+
+
 @pytest.mark.parametrize("n,npart,pusher", [((256, 10, 3), 300, "boris"), ((64, 5, 2), 100, "analytic"),
                                             ((384, 17, 1), 200, "boris"), ((448, 21, 3), 300, "analytic"),
                                             ((256, 24, 200), 400, "boris")])
