@@ -164,7 +164,9 @@ __global__ __launch_bounds__(256) void coef_finalize_kernel(const double* __rest
 // order) depend on the mesh only.
 // ---------------------------------------------------------------------------
 constexpr int kAW = kLags;  // x1 reach of the wide (Faraday C^E) stencil
-constexpr int kATX = 128, kATY = 8, kANT = kATX * kATY / 4;
+constexpr int kATX = 128, kATY = 8;
+constexpr int kAPOS = kATX * kATY / 4;  // four-cell positions of a tile
+constexpr int kANT = 2 * kAPOS;         // two threads per position: two waves per SIMD
 constexpr int kARB = kATY + 3, kAXB = kATX + 4 * kAW;  // lB tile: rows j0-2 .., cols i0-2W ..
 constexpr int kARE = kATY + 2, kAXE = kATX + 2 * kAW;  // lE tile: rows j0-1 .., cols i0-W ..
 constexpr int kAXF = kATX + 2 * kAW;                   // forward-field rows: cols i0-W ..
@@ -294,15 +296,15 @@ __device__ __forceinline__ void wide4(const double* __restrict__ w0, const Coef1
   }
 }
 
-// Sum over a tile's 256 threads of acc[0..W) through LDS: each thread stores
-// its values (column t of the [W][kRS] table ``tab``), 16 threads sum each
-// row's values in strided groups of 16, and thread t < W returns the sum of
-// row t (others return 0).  Callers have synchronised before the table is
+// Sum over a workgroup's threads of acc[0..W) through LDS: each thread
+// stores its values (column t of the [W][kRS] table ``tab``), kTS threads
+// sum each row's values in strided groups, and thread t < W returns the sum
+// of row t (others return 0).  Callers have synchronised before the table is
 // written; it is free again on return.
-constexpr int kTS = kANT / kAW;  // threads summing one row
-constexpr int kRS = kANT + 16;   // padded row: the two rows a half-wave reads fall in distinct banks
-static_assert(kTS * kAW == kANT && kANT % kTS == 0, "threads per accumulator row");
-static_assert((size_t)kAW * kRS <= kALdsB, "the tile-sum table fits over lB");
+constexpr int kTS = kANT / kAW;  // threads summing one row (a half-wave reads one row: no bank conflicts)
+constexpr int kRS = kANT + 16;   // padded row
+static_assert(kTS * kAW == kANT && kANT % kTS == 0 && (kANT / kTS) % 2 == 0, "threads per accumulator row");
+static_assert((size_t)kAW * kRS <= kALdsB + kALdsE, "the tile-sum table fits over the cotangent tiles");
 __device__ __forceinline__ double tile_sum(const double acc[kAW], double* tab, double* grp, int t) {
 #pragma unroll
   for (int j = 0; j < kAW; ++j) tab[j * kRS + t] = acc[j];
@@ -336,9 +338,10 @@ __global__ __launch_bounds__(kANT) void adjoint_sweep2d_kernel(AdjPlane P, Mesh 
   const int t = threadIdx.x;
   auto B = [&](int c, int r, int x) -> double& { return sB[((size_t)c * kARB + r) * kAXB + x]; };
   auto Ev = [&](int c, int r, int x) -> double& { return sE[((size_t)c * kARE + r) * kAXE + x]; };
-  // a tile's loads: lB (rows j0-2 .., cols i0-2W ..), lE (rows j0-1 ..,
-  // cols i0-W ..) and the forward rows of the lag products (rows j0 ..,
-  // cols i0-W ..), into registers
+  // a tile's loads into registers: the cotangents lB (rows j0-2 .., cols
+  // i0-2W ..) and lE (rows j0-1 .., cols i0-W ..), issued a tile ahead, and
+  // the forward rows of the lag products (rows j0 .., cols i0-W ..), issued
+  // at the start of the tile and stored once the three stages are done
   constexpr int kPB = (kARB * kAXB + kANT - 1) / kANT, kPE = (kARE * kAXE + kANT - 1) / kANT;
   constexpr int kPF = (kATY * kAXF + kANT - 1) / kANT;
   double vB[3][kPB], vE[3][kPE], vF[6][kPF];
@@ -348,13 +351,18 @@ __global__ __launch_bounds__(kANT) void adjoint_sweep2d_kernel(AdjPlane P, Mesh 
     for (int q = 0; q < 3; ++q) load_window<kNear, kARB, kAXB>(P.li[3 + q], m, c.k, j0 - 2, c.i0 - 2 * kAW, t, vB[q]);
 #pragma unroll
     for (int q = 0; q < 3; ++q) load_window<kNear, kARE, kAXE>(P.li[q], m, c.k, j0 - 1, c.i0 - kAW, t, vE[q]);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) load_window<kNear, kATY, kAXF>(P.fw[q], m, c.k, j0, c.i0 - kAW, t, vF[q]);
   };
-  double* tab = sB;  // [W][kRS] tile-sum table, over lB once its products are taken
+  auto load_rows = [&](const AdjTile& c) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) load_window<kNear, kATY, kAXF>(P.fw[q], m, c.k, c.y * kATY, c.i0 - kAW, t, vF[q]);
+  };
+  double* tab = sB;  // [W][kRS] tile-sum table, over the cotangent tiles once their products are taken
   __shared__ double grp[kAW * kTS];
   double totE = 0.0, totB = 0.0;  // thread t < W: the workgroup's sums of lag t + 1
-  const int tr = t / (kATX / 4), g = t % (kATX / 4);  // this thread's row and 4-cell group in a tile
+  // this thread's four-cell position (row tr, group g) and half of the work
+  // at that position
+  const int pos = t % kAPOS, half = t / kAPOS;
+  const int tr = pos / (kATX / 4), g = pos % (kATX / 4);
   AdjTile cur = adj_item(W, blockIdx.x);  // gridDim.x <= nwork
   load_tile(cur);
   for (;;) {
@@ -362,9 +370,8 @@ __global__ __launch_bounds__(kANT) void adjoint_sweep2d_kernel(AdjPlane P, Mesh 
     for (int q = 0; q < 3; ++q) store_window<kARB, kAXB>(sB + (size_t)q * kARB * kAXB, t, vB[q]);
 #pragma unroll
     for (int q = 0; q < 3; ++q) store_window<kARE, kAXE>(sE + (size_t)q * kARE * kAXE, t, vE[q]);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) store_window<kATY, kAXF>(sF + (size_t)q * kATY * kAXF, t, vF[q]);
     __syncthreads();
+    load_rows(cur);
     // the next tile of this workgroup: the next along x2 in the item, else
     // the first of its next item; its loads fly while this one is computed
     AdjTile nxt = cur;
@@ -376,24 +383,33 @@ __global__ __launch_bounds__(kANT) void adjoint_sweep2d_kernel(AdjPlane P, Mesh 
     bool own[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) own[u] = gi + u < m.n1 && gj < m.n2;
-    double lb2[4], lb3[4];  // the input lB at the interior cells (stage-3 products)
+    // the input lB at the interior cells (products with E'2 and E'3, taken
+    // by the first half)
+    double lb2[4], lb3[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       lb2[u] = own[u] ? B(1, tr + 2, 2 * kAW + 4 * g + u) : 0.0;
       lb3[u] = own[u] ? B(2, tr + 2, 2 * kAW + 4 * g + u) : 0.0;
     }
-    // lE1 = lE - h curl_B[C^E] lB on the whole lE tile, four cells at a time
-    for (int q = t; q < kARE * (kAXE / 4); q += kANT) {
-      const int re = q / (kAXE / 4), ce = 4 * (q % (kAXE / 4));
+    // lE1 = lE - h curl_B[C^E] lB on the whole lE tile, four cells at a
+    // time: item q < kNE updates lE_1 and lE_2 (wide stencil of lB_3), item
+    // q >= kNE lE_3 (wide stencil of lB_2) of the same four cells
+    constexpr int kNE = kARE * (kAXE / 4);
+    for (int q = t; q < 2 * kNE; q += kANT) {
+      const int q1 = q < kNE ? q : q - kNE;
+      const int re = q1 / (kAXE / 4), ce = 4 * (q1 % (kAXE / 4));
       const int rb = re + 1, cb = ce + kAW;
-      double d3[4], d2[4];
-      wide4(&B(2, rb, ce), a, d3);
-      wide4(&B(1, rb, ce), a, d2);
+      double d[4];
+      wide4(&B(q < kNE ? 2 : 1, rb, ce), a, d);
+      if (q < kNE) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        Ev(0, re, ce + u) += ty * (B(2, rb, cb + u) - B(2, rb - 1, cb + u));
-        Ev(1, re, ce + u) -= d3[u];
-        Ev(2, re, ce + u) += d2[u] - ty * (B(0, rb, cb + u) - B(0, rb - 1, cb + u));
+        for (int u = 0; u < 4; ++u) {
+          Ev(0, re, ce + u) += ty * (B(2, rb, cb + u) - B(2, rb - 1, cb + u));
+          Ev(1, re, ce + u) -= d[u];
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) Ev(2, re, ce + u) += d[u] - ty * (B(0, rb, cb + u) - B(0, rb - 1, cb + u));
       }
     }
     __syncthreads();
@@ -407,59 +423,60 @@ __global__ __launch_bounds__(kANT) void adjoint_sweep2d_kernel(AdjPlane P, Mesh 
       B(2, rb, cb) -= b1 * (Ev(1, re, ce + 1) - Ev(1, re, ce)) - hy * (Ev(0, re + 1, ce) - Ev(0, re, ce));
     }
     __syncthreads();
-    // lE0 = lE1 - h curl_B[C^E] lB1 on the interior; write lE0 and lB1
+    // lE0 = lE1 - h curl_B[C^E] lB1 on the interior; write lE0 and lB1.  The
+    // first half takes lE0_1, lE0_2 (wide stencil of lB1_3), lB1_1, lB1_3;
+    // the second lE0_3 (wide stencil of lB1_2) and lB1_2.
+    const int re = tr + 1, ce = kAW + 4 * g, rb = re + 1, cb = ce + kAW;
     {
-      const int re = tr + 1, ce = kAW + 4 * g, rb = re + 1, cb = ce + kAW;
-      double d3[4], d2[4];
-      wide4(&B(2, rb, ce), a, d3);
-      wide4(&B(1, rb, ce), a, d2);
+      double d[4];
+      wide4(&B(half == 0 ? 2 : 1, rb, ce), a, d);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         if (!own[u]) continue;
         const size_t o = ((size_t)k * m.n2 + gj) * m.n1 + gi + u;
-        P.lo[0][o] = Ev(0, re, ce + u) + ty * (B(2, rb, cb + u) - B(2, rb - 1, cb + u));
-        P.lo[1][o] = Ev(1, re, ce + u) - d3[u];
-        P.lo[2][o] = Ev(2, re, ce + u) + d2[u] - ty * (B(0, rb, cb + u) - B(0, rb - 1, cb + u));
-        P.lo[3][o] = B(0, rb, cb + u);
-        P.lo[4][o] = B(1, rb, cb + u);
-        P.lo[5][o] = B(2, rb, cb + u);
+        if (half == 0) {
+          P.lo[0][o] = Ev(0, re, ce + u) + ty * (B(2, rb, cb + u) - B(2, rb - 1, cb + u));
+          P.lo[1][o] = Ev(1, re, ce + u) - d[u];
+          P.lo[3][o] = B(0, rb, cb + u);
+          P.lo[5][o] = B(2, rb, cb + u);
+        } else {
+          P.lo[2][o] = Ev(2, re, ce + u) + d[u] - ty * (B(0, rb, cb + u) - B(0, rb - 1, cb + u));
+          P.lo[4][o] = B(1, rb, cb + u);
+        }
       }
     }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) store_window<kATY, kAXF>(sF + (size_t)q * kATY * kAXF, t, vF[q]);
+    __syncthreads();
     // lag products of the interior cells, one form at a time: Faraday
-    // (dL/dC^E) from E'2, E'3 with the input lB (kept in registers) and
-    // E^n2, E^n3 with lB1 (in sB); Ampere (dL/dC^B) from B'2, B'3 with lE1
-    // (in sE).  Window of 4 cells at i: staged cols 4g .. 4g + 35 = x1
-    // i - W .. i + W + 3 of row tr.
+    // (dL/dC^E) from E'2, E'3 with the input lB (first half) and E^n2, E^n3
+    // with lB1 (second half, from sB); Ampere (dL/dC^B) from B'2 (first
+    // half) and B'3 (second half) with lE1 (from sE, read before the
+    // Faraday table covers it).  Window of 4 cells at i: staged cols
+    // 4g .. 4g + 35 = x1 i - W .. i + W + 3 of row tr.
     auto frow = [&](int arr) { return &sF[((size_t)arr * kATY + tr) * kAXF + 4 * g]; };
+    double xa[4];  // lE1_3 (first half) or -lE1_2 (second half) at the interior cells
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xa[u] = own[u] ? (half == 0 ? Ev(2, re, ce + u) : -Ev(1, re, ce + u)) : 0.0;
     {
-      double acc[kAW], xs[4];
+      double acc[kAW], x0[4], x1[4];
 #pragma unroll
       for (int j = 0; j < kAW; ++j) acc[j] = 0.0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) xs[u] = -lb3[u];
-      lag_products<0>(frow(0), xs, acc);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) xs[u] = lb2[u];
-      lag_products<0>(frow(1), xs, acc);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) xs[u] = own[u] ? -B(2, tr + 2, 2 * kAW + 4 * g + u) : 0.0;
-      lag_products<0>(frow(4), xs, acc);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) xs[u] = own[u] ? B(1, tr + 2, 2 * kAW + 4 * g + u) : 0.0;
-      lag_products<0>(frow(5), xs, acc);
-      __syncthreads();  // sB is free: it holds the table
+      for (int u = 0; u < 4; ++u) {
+        x0[u] = half == 0 ? -lb3[u] : (own[u] ? -B(2, rb, cb + u) : 0.0);  // with E'2 / E^n2
+        x1[u] = half == 0 ? lb2[u] : (own[u] ? B(1, rb, cb + u) : 0.0);    // with E'3 / E^n3
+      }
+      lag_products<0>(frow(half == 0 ? 0 : 4), x0, acc);
+      lag_products<0>(frow(half == 0 ? 1 : 5), x1, acc);
+      __syncthreads();  // sB and sE are free: they hold the table
       totE += tile_sum(acc, tab, grp, t);
     }
     {
-      double acc[kAW], xs[4];
+      double acc[kAW];
 #pragma unroll
       for (int j = 0; j < kAW; ++j) acc[j] = 0.0;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) xs[u] = own[u] ? Ev(2, tr + 1, kAW + 4 * g + u) : 0.0;
-      lag_products<1>(frow(2), xs, acc);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) xs[u] = own[u] ? -Ev(1, tr + 1, kAW + 4 * g + u) : 0.0;
-      lag_products<1>(frow(3), xs, acc);
+      lag_products<1>(frow(half == 0 ? 2 : 3), xa, acc);
       totB += tile_sum(acc, tab, grp, t);
     }
     if (!more) break;
