@@ -167,14 +167,20 @@ __global__ __launch_bounds__(256) void tile_scatter_kernel(const double* __restr
 // of magnitude faster than float ones on this part, and integer sums do not
 // depend on the order of the adds.
 //
-// Scale.  Every Esirkepov contribution is at most |q w| in magnitude: it is
-// -q w (dx_d/dt) times a running sum of shape differences bounded by
-// |dx_d^{n+1} - dx_d^n|/dx_d <= dt |v_d|/dx_d < dt/dx_d (|v| < c), times a
-// transverse weight in [0, 1].  A node of a tile receives at most one
-// contribution per component from each of the tile's ``count`` particles, so
-// with the quantum q_t = 2^(e - 61), e = floor(log2(count |q w|)), no node
-// sum can exceed 2^62 in magnitude: the accumulator cannot overflow for any
-// particle load, and each contribution is rounded to q_t.
+// Scale.  Every Esirkepov contribution is at most c = max_d |q w| dx_d/dt in
+// magnitude: it is -q w (dx_d/dt) times a running sum of shape differences
+// (a difference of two partial sums of shape values, so at most 1 in
+// magnitude) times a transverse weight in [0, 1].  A node of a tile receives
+// at most one contribution per component from each of the tile's ``count``
+// particles, so with the quantum q_t = 2^(e - 61), e = floor(log2(count c)),
+// no node sum can exceed 2^62 in magnitude: the accumulator cannot overflow
+// for any particle load or move, and each contribution is rounded to q_t.
+//
+// FP32 grids take e = max(floor(log2(count c)), floor(log2 c) + 11), so that
+// every scaled contribution is below 2^51 in magnitude and converts to an
+// integer with one add of 1.5 2^52 (round to nearest even, as llrint, whose
+// 64-bit form takes six instructions); the quantum is then at most 2^-49 c,
+// far below FP32 resolution.
 //
 // FP64 grids keep two words per node: hi = round(v/q_t) and the rounding
 // residual in units of q_t 2^-L, lo = round((v/q_t - hi) 2^L), L = 63 -
@@ -188,9 +194,12 @@ struct TileScale {
   double sl, usl;  // 2^L and q_t 2^-L (two-word accumulation)
 };
 
-__device__ __forceinline__ TileScale tile_scale(int count, double qw_abs) {
-  const double cq = (double)count * qw_abs;
-  const int e = cq > 0.0 ? ilogb(cq) : 0;
+// cmax: the largest |c_d| = |q w| dx_d/dt.
+template <bool TWO>
+__device__ __forceinline__ TileScale tile_scale(int count, double cmax) {
+  const double cq = (double)count * cmax;
+  int e = cq > 0.0 ? ilogb(cq) : 0;
+  if (!TWO && cmax > 0.0) e = max(e, ilogb(cmax) + 11);
   const int L = 63 - (32 - __clz(count > 0 ? count : 1));
   TileScale t;
   t.s = ldexp(1.0, 61 - e);
@@ -200,12 +209,22 @@ __device__ __forceinline__ TileScale tile_scale(int count, double qw_abs) {
   return t;
 }
 
+// v: a contribution (FP64 grids), or the contribution already in units of
+// the quantum (FP32 grids, |v| < 2^51).
 template <bool TWO>
 __device__ __forceinline__ void acc_add(unsigned long long* hi, unsigned long long* lo, double v, const TileScale& ts) {
-  const double y = v * ts.s;  // exact: a power-of-two scaling, |y| < 2^62
-  const long long h = llrint(y);
-  atomicAdd(hi, (unsigned long long)h);
-  if (TWO) atomicAdd(lo, (unsigned long long)llrint((y - (double)h) * ts.sl));  // y - h is exact
+  if (TWO) {
+    // the product rounds first (v is itself rounded), so y - h below is
+    // exact, whether or not the compiler fuses it with the scaling
+    const double y = v * ts.s;  // exact: a power-of-two scaling, |y| < 2^62
+    const long long h = llrint(y);
+    atomicAdd(hi, (unsigned long long)h);
+    atomicAdd(lo, (unsigned long long)llrint((y - (double)h) * ts.sl));
+  } else {
+    const double y = v;
+    const double t = y + 6755399441055744.0;  // 1.5 2^52: the integer round(y) lands in the low bits
+    atomicAdd(hi, (unsigned long long)(__double_as_longlong(t) - 0x4338000000000000LL));
+  }
 }
 
 template <bool TWO>
@@ -258,7 +277,10 @@ __device__ __forceinline__ void deposit_one(const double xo[3], const double xn[
   }
   if (inside) {
     const int o = (rel[2] * w.r1 + rel[1]) * w.r0 + rel[0];
-    esirkepov<K>(sh[0], sh[1], sh[2], c1, c2, c3, [&](int comp, int a, int b, int c, double v) {
+    // FP32 grids: coefficients in units of the quantum (power-of-two
+    // scalings, exact), so that each contribution is one product
+    const double k = TWO ? 1.0 : ts.s;
+    esirkepov<K>(sh[0], sh[1], sh[2], c1 * k, c2 * k, c3 * k, [&](int comp, int a, int b, int c, double v) {
       const int i = comp * w.R + o + (c * w.r1 + b) * w.r0 + a;
       acc_add<TWO>(&jh[i], &jl[i], v, ts);
     });
@@ -322,10 +344,10 @@ __global__ __launch_bounds__(256) void tile_push_kernel(
   const int beg = offsets[tile], end = offsets[tile + 1];
   T* const Jg[3] = {J1, J2, J3};
   if (end == beg && !stage) return;  // uniform: no particles, nothing to add
-  const TileScale ts = tile_scale(end - beg, fabs(qw));
+  const double c1 = -qw * m.dx1 / dt, c2 = -qw * m.dx2 / dt, c3 = -qw * m.dx3 / dt;
+  const TileScale ts = tile_scale<TWO>(end - beg, fmax(fabs(c1), fmax(fabs(c2), fabs(c3))));
   acc_clear(jh, (TWO ? 6 : 3) * w.R);
   __syncthreads();
-  const double c1 = -qw * m.dx1 / dt, c2 = -qw * m.dx2 / dt, c3 = -qw * m.dx3 / dt;
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
     const double x[3] = {sx1[i], sx2[i], sx3[i]};
     double u[3] = {su1[i], su2[i], su3[i]};
@@ -370,10 +392,10 @@ __global__ __launch_bounds__(256) void tile_deposit_kernel(T* __restrict__ J1, T
   const int beg = offsets[tile], end = offsets[tile + 1];
   T* const Jg[3] = {J1, J2, J3};
   if (end == beg && !stage) return;
-  const TileScale ts = tile_scale(end - beg, fabs(qw));
+  const double c1 = -qw * m.dx1 / dt, c2 = -qw * m.dx2 / dt, c3 = -qw * m.dx3 / dt;
+  const TileScale ts = tile_scale<TWO>(end - beg, fmax(fabs(c1), fmax(fabs(c2), fabs(c3))));
   acc_clear(jh, (TWO ? 6 : 3) * w.R);
   __syncthreads();
-  const double c1 = -qw * m.dx1 / dt, c2 = -qw * m.dx2 / dt, c3 = -qw * m.dx3 / dt;
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
     const double xo[3] = {xo1[i], xo2[i], xo3[i]};
     const double xn[3] = {xn1[i], xn2[i], xn3[i]};
