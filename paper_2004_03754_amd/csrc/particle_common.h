@@ -36,17 +36,37 @@ __device__ __forceinline__ Axis axis(double x, double idx, double off, int n) {
   return a;
 }
 
-template <typename T>
+// The two x1 nodes of row ``r``.  PAIR (the caller has checked that no
+// lane's pair wraps around the periodic x1 edge): one load of two adjacent
+// elements, which needs only element alignment (global memory on this part
+// takes unaligned multi-dword loads).
+template <bool PAIR, typename T>
+__device__ __forceinline__ void row_pair(const T* __restrict__ r, const Axis& a, double& f0, double& f1) {
+  if (PAIR) {
+    struct P {
+      T v[2];
+    } p;
+    __builtin_memcpy(&p, r + a.i0, sizeof(P));
+    f0 = (double)p.v[0];
+    f1 = (double)p.v[1];
+  } else {
+    f0 = (double)r[a.i0];
+    f1 = (double)r[a.i1];
+  }
+}
+
+template <bool PAIR = false, typename T>
 __device__ __forceinline__ double interp3(const T* __restrict__ f, const Axis& a, const Axis& b, const Axis& c,
                                           int n1, size_t plane) {
   const size_t r00 = (size_t)c.i0 * plane + (size_t)b.i0 * n1;
   const size_t r01 = (size_t)c.i0 * plane + (size_t)b.i1 * n1;
   const size_t r10 = (size_t)c.i1 * plane + (size_t)b.i0 * n1;
   const size_t r11 = (size_t)c.i1 * plane + (size_t)b.i1 * n1;
-  const double f000 = f[r00 + a.i0], f001 = f[r00 + a.i1];
-  const double f010 = f[r01 + a.i0], f011 = f[r01 + a.i1];
-  const double f100 = f[r10 + a.i0], f101 = f[r10 + a.i1];
-  const double f110 = f[r11 + a.i0], f111 = f[r11 + a.i1];
+  double f000, f001, f010, f011, f100, f101, f110, f111;
+  row_pair<PAIR>(f + r00, a, f000, f001);
+  row_pair<PAIR>(f + r01, a, f010, f011);
+  row_pair<PAIR>(f + r10, a, f100, f101);
+  row_pair<PAIR>(f + r11, a, f110, f111);
   return c.w0 * (b.w0 * (a.w0 * f000 + a.w1 * f001) + b.w1 * (a.w0 * f010 + a.w1 * f011)) +
          c.w1 * (b.w0 * (a.w0 * f100 + a.w1 * f101) + b.w1 * (a.w0 * f110 + a.w1 * f111));
 }
@@ -454,12 +474,25 @@ __device__ __forceinline__ void gather6(const T* __restrict__ E1, const T* __res
   if (NDIM == 3) {
     const Axis c0 = axis(x[2], m.idx3, 0.0, m.n3), ch = axis(x[2], m.idx3, 0.5, m.n3);
     const size_t pl = (size_t)m.n1 * m.n2;
-    E[0] = interp3(E1, ah, b0, c0, m.n1, pl);
-    E[1] = interp3(E2, a0, bh, c0, m.n1, pl);
-    E[2] = interp3(E3, a0, b0, ch, m.n1, pl);
-    B[0] = interp3(B1, a0, bh, ch, m.n1, pl);
-    B[1] = interp3(B2, ah, b0, ch, m.n1, pl);
-    B[2] = interp3(B3, ah, bh, c0, m.n1, pl);
+    // FP64 fields: pairs of x1 nodes in one 16-byte load when no lane of the
+    // wave wraps in x1 (only waves at the last x1 cell column do).  FP32
+    // pairs would be unaligned 8-byte loads, measured slower than two loads
+    // in the plasma push.
+    if (sizeof(T) == 8 && __builtin_amdgcn_ballot_w64(a0.i1 == 0 || ah.i1 == 0) == 0) {
+      E[0] = interp3<true>(E1, ah, b0, c0, m.n1, pl);
+      E[1] = interp3<true>(E2, a0, bh, c0, m.n1, pl);
+      E[2] = interp3<true>(E3, a0, b0, ch, m.n1, pl);
+      B[0] = interp3<true>(B1, a0, bh, ch, m.n1, pl);
+      B[1] = interp3<true>(B2, ah, b0, ch, m.n1, pl);
+      B[2] = interp3<true>(B3, ah, bh, c0, m.n1, pl);
+    } else {
+      E[0] = interp3(E1, ah, b0, c0, m.n1, pl);
+      E[1] = interp3(E2, a0, bh, c0, m.n1, pl);
+      E[2] = interp3(E3, a0, b0, ch, m.n1, pl);
+      B[0] = interp3(B1, a0, bh, ch, m.n1, pl);
+      B[1] = interp3(B2, ah, b0, ch, m.n1, pl);
+      B[2] = interp3(B3, ah, bh, c0, m.n1, pl);
+    }
   } else {
     const size_t o = plane_offset(m, x[2]);
     E[0] = interp2(E1 + o, ah, b0, m.n1);
@@ -575,12 +608,23 @@ __device__ __forceinline__ ShapeK<ORDER + 2> shape_o(double xo, double xn, doubl
 template <int K, typename Add>
 __device__ __forceinline__ void esirkepov(const ShapeK<K>& sx, const ShapeK<K>& sy, const ShapeK<K>& sz, double c1,
                                           double c2, double c3, Add add) {
+  // The transverse weight of W_d at nodes (p, q) of the two other directions,
+  //   S0_p S0_q + (dS_p S0_q + S0_p dS_q)/2 + dS_p dS_q/3,
+  // taken as S0_p h_q + dS_p k_q with h = S0 + dS/2, k = S0/2 + dS/3 (the
+  // same quantity, two operations per node)
+  double hy[K], ky[K], hz[K], kz[K];
+#pragma unroll
+  for (int n = 0; n < K; ++n) {
+    hy[n] = sy.s0[n] + 0.5 * sy.ds[n];
+    ky[n] = 0.5 * sy.s0[n] + (1.0 / 3.0) * sy.ds[n];
+    hz[n] = sz.s0[n] + 0.5 * sz.ds[n];
+    kz[n] = 0.5 * sz.s0[n] + (1.0 / 3.0) * sz.ds[n];
+  }
 #pragma unroll
   for (int b = 0; b < K; ++b)
 #pragma unroll
     for (int c = 0; c < K; ++c) {
-      const double w = sy.s0[b] * sz.s0[c] + 0.5 * sy.ds[b] * sz.s0[c] + 0.5 * sy.s0[b] * sz.ds[c] +
-                       sy.ds[b] * sz.ds[c] * (1.0 / 3.0);
+      const double w = sy.s0[b] * hz[c] + sy.ds[b] * kz[c];
       double run = 0;
 #pragma unroll
       for (int a = 0; a < K - 1; ++a) {
@@ -592,8 +636,7 @@ __device__ __forceinline__ void esirkepov(const ShapeK<K>& sx, const ShapeK<K>& 
   for (int a = 0; a < K; ++a)
 #pragma unroll
     for (int c = 0; c < K; ++c) {
-      const double w = sx.s0[a] * sz.s0[c] + 0.5 * sx.ds[a] * sz.s0[c] + 0.5 * sx.s0[a] * sz.ds[c] +
-                       sx.ds[a] * sz.ds[c] * (1.0 / 3.0);
+      const double w = sx.s0[a] * hz[c] + sx.ds[a] * kz[c];
       double run = 0;
 #pragma unroll
       for (int b = 0; b < K - 1; ++b) {
@@ -605,8 +648,7 @@ __device__ __forceinline__ void esirkepov(const ShapeK<K>& sx, const ShapeK<K>& 
   for (int a = 0; a < K; ++a)
 #pragma unroll
     for (int b = 0; b < K; ++b) {
-      const double w = sx.s0[a] * sy.s0[b] + 0.5 * sx.ds[a] * sy.s0[b] + 0.5 * sx.s0[a] * sy.ds[b] +
-                       sx.ds[a] * sy.ds[b] * (1.0 / 3.0);
+      const double w = sx.s0[a] * hy[b] + sx.ds[a] * ky[b];
       double run = 0;
 #pragma unroll
       for (int c = 0; c < K - 1; ++c) {
