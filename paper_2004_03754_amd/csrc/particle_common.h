@@ -604,55 +604,71 @@ __device__ __forceinline__ ShapeK<ORDER + 2> shape_o(double xo, double xn, doubl
 // Esirkepov 3D decomposition (Sec. 3.3, cited method): for each node
 // (a, b, c) of the K x K x K local stencil, add the current contributions
 // J_d = -q w (dx_d/dt) * (running sum of W_d along d).  ``add(comp, a, b, c, v)``
-// receives stencil-local node indices.
-template <int K, typename Add>
+// receives stencil-local node indices.  N < K: only the first N nodes per
+// direction, for particles known not to change cell (nearest node, at the
+// quadratic shape) in any direction, whose last node carries no weight.
+template <int K, int N = K, typename Add>
 __device__ __forceinline__ void esirkepov(const ShapeK<K>& sx, const ShapeK<K>& sy, const ShapeK<K>& sz, double c1,
                                           double c2, double c3, Add add) {
+  static_assert(N == K || N == K - 1, "node count");
+  // The running sum of W_d along d is (prefix sum of the shape differences
+  // up to the node) times the transverse weight.  A particle that stays in
+  // its cell along d has an empty last node there, so the prefix sum up to
+  // the node before it is exactly zero; it is set so (the differences'
+  // rounding would leave a residue), which makes the full loop give the same
+  // contributions as the N = K - 1 loop for such a particle.
+  auto prefix = [](const ShapeK<K>& sh, double cs[N > 1 ? N - 1 : 1]) {
+    cs[0] = sh.ds[0];
+#pragma unroll
+    for (int n = 1; n < N - 1; ++n) cs[n] = cs[n - 1] + sh.ds[n];
+    if (N == K && sh.s0[K - 1] == 0.0 && sh.ds[K - 1] == 0.0) cs[N - 2] = 0.0;
+  };
+  double cx[N - 1], cy[N - 1], cz[N - 1];
+  prefix(sx, cx);
+  prefix(sy, cy);
+  prefix(sz, cz);
   // The transverse weight of W_d at nodes (p, q) of the two other directions,
   //   S0_p S0_q + (dS_p S0_q + S0_p dS_q)/2 + dS_p dS_q/3,
   // taken as S0_p h_q + dS_p k_q with h = S0 + dS/2, k = S0/2 + dS/3 (the
   // same quantity, two operations per node)
-  double hy[K], ky[K], hz[K], kz[K];
+  double hy[N], ky[N], hz[N], kz[N];
 #pragma unroll
-  for (int n = 0; n < K; ++n) {
+  for (int n = 0; n < N; ++n) {
     hy[n] = sy.s0[n] + 0.5 * sy.ds[n];
     ky[n] = 0.5 * sy.s0[n] + (1.0 / 3.0) * sy.ds[n];
     hz[n] = sz.s0[n] + 0.5 * sz.ds[n];
     kz[n] = 0.5 * sz.s0[n] + (1.0 / 3.0) * sz.ds[n];
   }
 #pragma unroll
-  for (int b = 0; b < K; ++b)
+  for (int b = 0; b < N; ++b)
 #pragma unroll
-    for (int c = 0; c < K; ++c) {
+    for (int c = 0; c < N; ++c) {
       const double w = sy.s0[b] * hz[c] + sy.ds[b] * kz[c];
-      double run = 0;
 #pragma unroll
-      for (int a = 0; a < K - 1; ++a) {
-        run += sx.ds[a] * w;
+      for (int a = 0; a < N - 1; ++a) {
+        const double run = cx[a] * w;
         if (run != 0.0) add(0, a, b, c, c1 * run);
       }
     }
 #pragma unroll
-  for (int a = 0; a < K; ++a)
+  for (int a = 0; a < N; ++a)
 #pragma unroll
-    for (int c = 0; c < K; ++c) {
+    for (int c = 0; c < N; ++c) {
       const double w = sx.s0[a] * hz[c] + sx.ds[a] * kz[c];
-      double run = 0;
 #pragma unroll
-      for (int b = 0; b < K - 1; ++b) {
-        run += sy.ds[b] * w;
+      for (int b = 0; b < N - 1; ++b) {
+        const double run = cy[b] * w;
         if (run != 0.0) add(1, a, b, c, c2 * run);
       }
     }
 #pragma unroll
-  for (int a = 0; a < K; ++a)
+  for (int a = 0; a < N; ++a)
 #pragma unroll
-    for (int b = 0; b < K; ++b) {
+    for (int b = 0; b < N; ++b) {
       const double w = sx.s0[a] * hy[b] + sx.ds[a] * ky[b];
-      double run = 0;
 #pragma unroll
-      for (int c = 0; c < K - 1; ++c) {
-        run += sz.ds[c] * w;
+      for (int c = 0; c < N - 1; ++c) {
+        const double run = cz[c] * w;
         if (run != 0.0) add(2, a, b, c, c3 * run);
       }
     }

@@ -280,10 +280,19 @@ __device__ __forceinline__ void deposit_one(const double xo[3], const double xn[
     // FP32 grids: coefficients in units of the quantum (power-of-two
     // scalings, exact), so that each contribution is one product
     const double k = TWO ? 1.0 : ts.s;
-    esirkepov<K>(sh[0], sh[1], sh[2], c1 * k, c2 * k, c3 * k, [&](int comp, int a, int b, int c, double v) {
+    auto add = [&](int comp, int a, int b, int c, double v) {
       const int i = comp * w.R + o + (c * w.r1 + b) * w.r0 + a;
       acc_add<TWO>(&jh[i], &jl[i], v, ts);
-    });
+    };
+    // most waves hold no particle that changes cell: their stencils' last
+    // node is empty in every direction, and a smaller loop skips it
+    bool moves = false;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) moves = moves || sh[d].s0[K - 1] != 0.0 || sh[d].ds[K - 1] != 0.0;
+    if (__builtin_amdgcn_ballot_w64(moves) == 0)
+      esirkepov<K, K - 1>(sh[0], sh[1], sh[2], c1 * k, c2 * k, c3 * k, add);
+    else
+      esirkepov<K>(sh[0], sh[1], sh[2], c1 * k, c2 * k, c3 * k, add);
   } else {
     const size_t pl = (size_t)m.n1 * m.n2;
     int gw[3][K];
