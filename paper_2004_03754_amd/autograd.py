@@ -82,8 +82,10 @@ class PICRun(torch.autograd.Function):
         gCE = torch.zeros(b.PIC_MAX_M, dtype=torch.float64, device=dev)
         gCB = torch.zeros(b.PIC_MAX_M, dtype=torch.float64, device=dev)
         K = min(cfg.K, cfg.nsteps)
-        # K + 1 state buffers: a segment's states t^{s0} .. t^{s0+n}
-        slots = [_clone_state(E0, B0, x0, u0) for _ in range(K + 1)]
+        # K + 1 state buffers: a segment's states t^{s0} .. t^{s0+n} (every
+        # one is written before it is read: storage only, no copies)
+        slots = [([torch.empty_like(v) for v in E0], [torch.empty_like(v) for v in B0], torch.empty_like(x0),
+                  torch.empty_like(u0)) for _ in range(K + 1)]
         halves = [[torch.empty_like(v) for v in B0] for _ in range(K)]  # B^{n+1/2} of each step
         grid = b.Grid(slots[0][0], slots[0][1], cfg.dx, cfg.dt, ce, cb, ndim=cfg.ndim)
         lam = b.Particles(lx, lu, q=cfg.q, m=cfg.m, w=cfg.w)
