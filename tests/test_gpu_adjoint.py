@@ -322,10 +322,12 @@ def test_autograd_run_matches_oracle(nsteps, K, pusher, coeffs16):
     assert _rel(leaves[1].grad.numpy(), gsum["CB"]) <= 1e-11
 
 
-def test_envelope_gradients_match_central_differences(coeffs16):
+@pytest.mark.parametrize("a0s", [(1.0, 30.0), (100.0, 1000.0)])
+def test_envelope_gradients_match_central_differences(a0s, coeffs16):
     """Config-4 shape at a small size: gradients of mean final gamma plus the
     vacuum phase error with respect to three coefficients and each plane's
-    a0, through the envelope -> fields map and the checkpointed run, against
+    a0 (1 and 30, and 100 and 1000: the top of the workload's a0 range),
+    through the envelope -> fields map and the checkpointed run, against
     central differences of the GPU forward (h = 1e-6 relative)."""
     from paper_2004_03754_amd import autograd as pa
     CE, CB = coeffs16
@@ -340,7 +342,7 @@ def test_envelope_gradients_match_central_differences(coeffs16):
     u = np.zeros_like(x)
     cfg = pa.RunConfig(DX, wl.DT, nsteps, K=16, ndim=2, q=QM)
     # reference field: the initial pulse moved on by the elapsed time
-    Eref, _ = pa.sin2_pulse_fields(n1, n2, nb, DX, torch.tensor([1.0, 30.0]), Lp, xh + nsteps * wl.DT)
+    Eref, _ = pa.sin2_pulse_fields(n1, n2, nb, DX, torch.tensor(list(a0s)), Lp, xh + nsteps * wl.DT)
 
     def loss(ce, cb, a0):
         E0, B0 = pa.sin2_pulse_fields(n1, n2, nb, DX, a0, Lp, xh)
@@ -349,12 +351,12 @@ def test_envelope_gradients_match_central_differences(coeffs16):
         return torch.mean(gam) + torch.sum((Ef[1] - Eref[1]) ** 2) / torch.sum(Eref[1] ** 2)
 
     ce, cb = _t(CE).requires_grad_(), _t(CB).requires_grad_()
-    a0 = torch.tensor([1.0, 30.0], dtype=torch.float64, requires_grad=True)
+    a0 = torch.tensor(list(a0s), dtype=torch.float64, requires_grad=True)
     Lv = loss(ce, cb, a0)
     Lv.backward()
     checks = [("CE", 0), ("CE", 5), ("CB", 1), ("a0", 0), ("a0", 1)]
     for name, j in checks:
-        base = {"CE": _t(CE), "CB": _t(CB), "a0": torch.tensor([1.0, 30.0], dtype=torch.float64)}
+        base = {"CE": _t(CE), "CB": _t(CB), "a0": torch.tensor(list(a0s), dtype=torch.float64)}
         h = 1e-6 * max(abs(float(base[name][j])), 1.0)
         vals = []
         for sgn in (1, -1):
