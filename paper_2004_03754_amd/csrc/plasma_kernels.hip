@@ -144,22 +144,36 @@ __global__ __launch_bounds__(256) void tile_scatter_kernel(const double* __restr
                                                            double* __restrict__ su2, double* __restrict__ su3,
                                                            int64_t* __restrict__ sid) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int key = p < np ? keys[p] : -1;
+  const bool live = p < np;
+  const int key = live ? keys[p] : -1;
+  // the particle's state is read before the cursor atomic, so that its
+  // loads overlap the atomic's round trip
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  int64_t pid = 0;
+  if (live) {
+    v[0] = x1[p];
+    v[1] = x2[p];
+    v[2] = x3[p];
+    v[3] = u1[p];
+    v[4] = u2[p];
+    v[5] = u3[p];
+    if (id) pid = id[p];
+  }
   int leader_lane, runlen;
   key_runs(key, leader_lane, runlen);
   const int lane = threadIdx.x & 63;
   int base = 0;
   if (leader_lane == lane && key >= 0) base = atomicAdd(&cursors[key], runlen);
   base = __shfl(base, leader_lane);
-  if (p >= np) return;
+  if (!live) return;
   const int64_t q = (int64_t)offsets[key] + base + (lane - leader_lane);
-  sx1[q] = x1[p];
-  sx2[q] = x2[p];
-  sx3[q] = x3[p];
-  su1[q] = u1[p];
-  su2[q] = u2[p];
-  su3[q] = u3[p];
-  if (id) sid[q] = id[p];
+  sx1[q] = v[0];
+  sx2[q] = v[1];
+  sx3[q] = v[2];
+  su1[q] = v[3];
+  su2[q] = v[4];
+  su3[q] = v[5];
+  if (id) sid[q] = pid;
 }
 
 // ---------------------------------------------------------------------------
