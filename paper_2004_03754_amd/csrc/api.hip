@@ -714,13 +714,17 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
             scr.u[d] = st.us[d];
           }
           scr.id = species[s]->id ? st.ids : nullptr;
+          // after the first step of the call, the push before counted the tiles
           rc = launch_tile_sort(g->mesh, tg, *species[s], scr, st.keys, st.counts, st.offsets, st.cursors,
-                                st.segsum, g->stream);
+                                st.segsum, g->stream, step > 0);
           src = scr;
         }
+        // the push before a sort writes the sort's keys and tile counts
+        const bool count_next = (step + 1) % g->sort_every == 0 && step + 1 < nsteps;
         if (rc == PIC_OK)
           rc = launch_tile_push(g->prec, g->mesh, tg, cur, cur + 3, g->J, st.offsets, src, *species[s], pusher,
-                                g->dt, stage, g->stream);
+                                g->dt, stage, g->stream, count_next ? st.keys : nullptr,
+                                count_next ? st.counts : nullptr);
         continue;
       }
       if (vac && vuse[s]) {

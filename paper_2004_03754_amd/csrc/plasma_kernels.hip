@@ -32,11 +32,15 @@ __device__ __forceinline__ int cell_of(double x, double idx, int n) {
   return (int)f;
 }
 
-__device__ __forceinline__ int tile_key(const double* const* x, int64_t p, const Mesh& m, const TileGeom& tg) {
-  const int cx = cell_of(x[0][p], m.idx1, m.n1) / tg.t[0];
-  const int cy = cell_of(x[1][p], m.idx2, m.n2) / tg.t[1];
-  const int cz = cell_of(x[2][p], m.idx3, m.n3) / tg.t[2];
+__device__ __forceinline__ int tile_key_at(double x1, double x2, double x3, const Mesh& m, const TileGeom& tg) {
+  const int cx = cell_of(x1, m.idx1, m.n1) / tg.t[0];
+  const int cy = cell_of(x2, m.idx2, m.n2) / tg.t[1];
+  const int cz = cell_of(x3, m.idx3, m.n3) / tg.t[2];
   return (cz * tg.nt[1] + cy) * tg.nt[0] + cx;
+}
+
+__device__ __forceinline__ int tile_key(const double* const* x, int64_t p, const Mesh& m, const TileGeom& tg) {
+  return tile_key_at(x[0][p], x[1][p], x[2][p], m, tg);
 }
 
 // lanes with equal consecutive keys form runs; returns the run leader lane
@@ -358,7 +362,7 @@ __global__ __launch_bounds__(256) void tile_push_kernel(
     Mesh m, TileGeom tg, const int* __restrict__ offsets, const double* sx1, const double* sx2, const double* sx3,
     const double* su1, const double* su2, const double* su3, const int64_t* sid, double* dx1, double* dx2,
     double* dx3, double* du1, double* du2, double* du3, int64_t* did, double qm, double qw, double dt,
-    double* stage) {
+    double* stage, int* __restrict__ keys, int* __restrict__ counts) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const TileWin w = tile_window(blockIdx.x, tg);
   unsigned long long* jh = reinterpret_cast<unsigned long long*>(lds_raw);
@@ -392,6 +396,19 @@ __global__ __launch_bounds__(256) void tile_push_kernel(
     du2[i] = u[1];
     du3[i] = u[2];
     if (sid && sid != did) did[i] = sid[i];
+    if (keys) {  // the next sort's tile key and count, from the new position
+      const int key = tile_key_at(xn[0], xn[1], xn[2], m, tg);
+      keys[i] = key;
+      // one add per wave when its active lanes share the key (the common
+      // case on tile-sorted particles), else one per lane
+      const int k0 = __builtin_amdgcn_readfirstlane(key);
+      const unsigned long long act = __ballot(1), same = __ballot(key == k0);
+      if (same == act) {
+        if ((int)(threadIdx.x & 63) == __ffsll((long long)act) - 1) atomicAdd(&counts[k0], __popcll(act));
+      } else {
+        atomicAdd(&counts[key], 1);
+      }
+    }
     deposit_one<T, ORDER, TWO>(x, xn, m, tg, w, jh, jl, ts, c1, c2, c3, Jg);
   }
   __syncthreads();
@@ -508,7 +525,7 @@ size_t tile_lds(const TileGeom& tg, bool two) {
 template <typename T>
 int run_tile_push(const Mesh& m, const TileGeom& tg, void* const E[3], void* const B[3], void* const J[3],
                   const int* offsets, const pic_particles& src, const pic_particles& dst, int pusher, double dt,
-                  double* stage, hipStream_t s) {
+                  double* stage, int* keys, int* counts, hipStream_t s) {
   constexpr bool TWO = sizeof(T) == sizeof(double);
   const size_t lds = tile_lds(tg, TWO);
   if (lds > 160 * 1024) return set_error(PIC_EUNSUPPORTED, "plasma tile needs %zu bytes of LDS", lds);
@@ -527,7 +544,7 @@ int run_tile_push(const Mesh& m, const TileGeom& tg, void* const E[3], void* con
                      (const double*)src.x[0], (const double*)src.x[1], (const double*)src.x[2],
                      (const double*)src.u[0], (const double*)src.u[1], (const double*)src.u[2],
                      (const int64_t*)src.id, dst.x[0], dst.x[1], dst.x[2], dst.u[0], dst.u[1], dst.u[2], dst.id, qm,
-                     qw, dt, stage);
+                     qw, dt, stage, keys, counts);
   if (hipGetLastError() != hipSuccess) return set_error(PIC_EHIP, "tile push launch failed");
   if (stage) {
     const int64_t work = 3 * (int64_t)m.n1 * m.n2 * m.n3;
@@ -586,13 +603,15 @@ TileGeom make_tile_geom(const Mesh& m, double dt, int sort_every) {
 int scan_segments(int ntiles) { return (ntiles + kScanSeg - 1) / kScanSeg; }
 
 int launch_tile_sort(const Mesh& m, const TileGeom& tg, const pic_particles& p, const pic_particles& scratch,
-                     int* keys, int* counts, int* offsets, int* cursors, int* segsum, void* stream) {
+                     int* keys, int* counts, int* offsets, int* cursors, int* segsum, void* stream, bool counted) {
   hipStream_t s = (hipStream_t)stream;
   if (p.np == 0) return PIC_OK;
-  if (hipMemsetAsync(counts, 0, sizeof(int) * tg.ntiles, s) != hipSuccess)
-    return set_error(PIC_EHIP, "tile sort: clear counts");
   const dim3 grid((unsigned)((p.np + 255) / 256));
-  hipLaunchKernelGGL(tile_count_kernel, grid, dim3(256), 0, s, p.x[0], p.x[1], p.x[2], p.np, m, tg, keys, counts);
+  if (!counted) {
+    if (hipMemsetAsync(counts, 0, sizeof(int) * tg.ntiles, s) != hipSuccess)
+      return set_error(PIC_EHIP, "tile sort: clear counts");
+    hipLaunchKernelGGL(tile_count_kernel, grid, dim3(256), 0, s, p.x[0], p.x[1], p.x[2], p.np, m, tg, keys, counts);
+  }
   const int nseg = (tg.ntiles + kScanSeg - 1) / kScanSeg;
   hipLaunchKernelGGL(tile_segsum_kernel, dim3(nseg), dim3(1024), 0, s, counts, tg.ntiles, segsum);
   hipLaunchKernelGGL(tile_segscan_kernel, dim3(nseg), dim3(1024), 0, s, counts, tg.ntiles, segsum, nseg, offsets,
@@ -646,11 +665,13 @@ int launch_unsort(const pic_particles& sorted, const int64_t* ids, const pic_par
 
 int launch_tile_push(int prec, const Mesh& m, const TileGeom& tg, void* const E[3], void* const B[3],
                      void* const J[3], const int* offsets, const pic_particles& src, const pic_particles& dst,
-                     int pusher, double dt, double* stage, void* stream) {
+                     int pusher, double dt, double* stage, void* stream, int* keys, int* counts) {
   hipStream_t s = (hipStream_t)stream;
   if (src.np == 0) return PIC_OK;
-  return prec == PIC_FP64 ? run_tile_push<double>(m, tg, E, B, J, offsets, src, dst, pusher, dt, stage, s)
-                          : run_tile_push<float>(m, tg, E, B, J, offsets, src, dst, pusher, dt, stage, s);
+  if (keys && hipMemsetAsync(counts, 0, sizeof(int) * tg.ntiles, s) != hipSuccess)
+    return set_error(PIC_EHIP, "tile push: clear counts");
+  return prec == PIC_FP64 ? run_tile_push<double>(m, tg, E, B, J, offsets, src, dst, pusher, dt, stage, keys, counts, s)
+                          : run_tile_push<float>(m, tg, E, B, J, offsets, src, dst, pusher, dt, stage, keys, counts, s);
 }
 
 int launch_tile_deposit(int prec, const Mesh& m, const TileGeom& tg, void* const J[3], const int* offsets,
