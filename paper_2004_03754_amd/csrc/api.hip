@@ -16,12 +16,12 @@
 // Per-species buffers of the tile-sorted plasma path (grow-only).
 struct SortState {
   int64_t cap = 0;
-  int ntiles = 0;
+  int nbins = 0;  // sort keys (tiles times their x3 planes)
   int* keys = nullptr;
   int* counts = nullptr;
   int* offsets = nullptr;
   int* cursors = nullptr;
-  int* segsum = nullptr;  // per-segment sums of the tile-count scan
+  int* segsum = nullptr;  // per-segment sums of the count scan
   double* xs[3] = {nullptr, nullptr, nullptr};
   double* us[3] = {nullptr, nullptr, nullptr};
   int64_t* ids = nullptr;
@@ -282,16 +282,16 @@ static void free_sort(SortState& st) {
   st = SortState();
 }
 
-static int ensure_sort(pic_grid* g, SortState& st, int64_t np, int ntiles, bool ids) {
-  if (np <= st.cap && ntiles == st.ntiles && (!ids || st.ids)) return PIC_OK;
+static int ensure_sort(pic_grid* g, SortState& st, int64_t np, int nbins, bool ids) {
+  if (np <= st.cap && nbins == st.nbins && (!ids || st.ids)) return PIC_OK;
   (void)hipStreamSynchronize(g->stream);
   free_sort(st);
   const size_t n = (size_t)(np > 0 ? np : 1);
   bool ok = hipMalloc((void**)&st.keys, n * sizeof(int)) == hipSuccess &&
-            hipMalloc((void**)&st.counts, (size_t)ntiles * sizeof(int)) == hipSuccess &&
-            hipMalloc((void**)&st.offsets, ((size_t)ntiles + 1) * sizeof(int)) == hipSuccess &&
-            hipMalloc((void**)&st.cursors, (size_t)ntiles * sizeof(int)) == hipSuccess &&
-            hipMalloc((void**)&st.segsum, (size_t)scan_segments(ntiles) * sizeof(int)) == hipSuccess;
+            hipMalloc((void**)&st.counts, (size_t)nbins * sizeof(int)) == hipSuccess &&
+            hipMalloc((void**)&st.offsets, ((size_t)nbins + 1) * sizeof(int)) == hipSuccess &&
+            hipMalloc((void**)&st.cursors, (size_t)nbins * sizeof(int)) == hipSuccess &&
+            hipMalloc((void**)&st.segsum, (size_t)scan_segments(nbins) * sizeof(int)) == hipSuccess;
   for (int d = 0; d < 3 && ok; ++d)
     ok = hipMalloc((void**)&st.xs[d], n * sizeof(double)) == hipSuccess &&
          hipMalloc((void**)&st.us[d], n * sizeof(double)) == hipSuccess;
@@ -301,7 +301,7 @@ static int ensure_sort(pic_grid* g, SortState& st, int64_t np, int ntiles, bool 
     return set_error(PIC_ENOMEM, "cannot allocate particle sort buffers for %lld particles", (long long)np);
   }
   st.cap = np;
-  st.ntiles = ntiles;
+  st.nbins = nbins;
   return PIC_OK;
 }
 
@@ -575,7 +575,7 @@ int pic_deposit_J(pic_grid* g, const pic_particles* p, double* const x_old[3], i
   // kernel accumulates each tile's current on chip (moves below one cell, so
   // the window needs no drift margin)
   const TileGeom tg = make_tile_geom(g->mesh, g->dt, 1);
-  rc = ensure_sort(g, g->dsort, p->np, tg.ntiles, false);
+  rc = ensure_sort(g, g->dsort, p->np, tg.nbins, false);
   double* stage = nullptr;
   if (rc == PIC_OK && g->deposit_mode == PIC_DEPOSIT_DETERMINISTIC) {
     rc = ensure_stage(g, tg);
@@ -647,7 +647,7 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
     for (int s = 0; s < nspecies && rc == PIC_OK; ++s) rc = check_sortable(species[s]);
     if ((int)g->sorts.size() < nspecies) g->sorts.resize(nspecies);
     for (int s = 0; s < nspecies && rc == PIC_OK; ++s)
-      rc = ensure_sort(g, g->sorts[s], species[s]->np, tg.ntiles, species[s]->id != nullptr);
+      rc = ensure_sort(g, g->sorts[s], species[s]->np, tg.nbins, species[s]->id != nullptr);
     if (rc == PIC_OK && g->deposit_mode == PIC_DEPOSIT_DETERMINISTIC) {
       rc = ensure_stage(g, tg);
       stage = g->stage;
@@ -676,8 +676,8 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
       if (rc) break;
       SortState& A = g->vsort_a[s];
       SortState& B = g->vsort_b[s];
-      rc = ensure_sort(g, A, species[s]->np, tg.ntiles, true);
-      if (rc == PIC_OK) rc = ensure_sort(g, B, species[s]->np, tg.ntiles, true);
+      rc = ensure_sort(g, A, species[s]->np, tg.nbins, true);
+      if (rc == PIC_OK) rc = ensure_sort(g, B, species[s]->np, tg.nbins, true);
       if (rc) break;
       vuse[s] = 1;
       vcur[s] = valt[s] = *species[s];

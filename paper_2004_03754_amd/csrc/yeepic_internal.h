@@ -64,6 +64,8 @@ struct TileGeom {
   int m[3];   // drift margin in cells
   int r[3];   // nodes of the on-chip current tile per direction
   int ntiles;
+  int sub;    // sort bins per tile: one per x3 cell plane of the tile
+  int nbins;  // ntiles * sub: the sort's keys
 };
 TileGeom make_tile_geom(const Mesh& m, double dt, int sort_every);
 // counting sort of p by tile into scratch; segsum holds scan_segments(ntiles)
