@@ -360,8 +360,11 @@ __device__ __forceinline__ void acc_flush(const unsigned long long* jh, const un
   }
 }
 
+// FP32 linear-shape pushes fit three workgroups per CU in LDS: the Boris and
+// Higuera-Cary ones are held to the registers of three waves per SIMD too
 template <typename T, int PUSH, int ORDER, bool TWO>
-__global__ __launch_bounds__(256) void tile_push_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!TWO && ORDER == 1 && PUSH != PIC_PUSH_ANALYTIC ? 3 : 1)))
+void tile_push_kernel(
     const T* __restrict__ E1, const T* __restrict__ E2, const T* __restrict__ E3, const T* __restrict__ B1,
     const T* __restrict__ B2, const T* __restrict__ B3, T* __restrict__ J1, T* __restrict__ J2, T* __restrict__ J3,
     Mesh m, TileGeom tg, const int* __restrict__ offsets, const double* sx1, const double* sx2, const double* sx3,
@@ -380,9 +383,24 @@ __global__ __launch_bounds__(256) void tile_push_kernel(
   const TileScale ts = tile_scale<TWO>(end - beg, fmax(fabs(c1), fmax(fabs(c2), fabs(c3))));
   acc_clear(jh, (TWO ? 6 : 3) * w.R);
   __syncthreads();
+  // the next particle's position is loaded one iteration ahead, so that its
+  // memory latency overlaps this particle's work instead of delaying the
+  // gather that depends on it
+  double xc[3] = {0.0, 0.0, 0.0};
+  if (beg + (int)threadIdx.x < end) {
+    xc[0] = sx1[beg + threadIdx.x];
+    xc[1] = sx2[beg + threadIdx.x];
+    xc[2] = sx3[beg + threadIdx.x];
+  }
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
-    const double x[3] = {sx1[i], sx2[i], sx3[i]};
+    const double x[3] = {xc[0], xc[1], xc[2]};
     double u[3] = {su1[i], su2[i], su3[i]};
+    const int inext = i + blockDim.x;
+    if (inext < end) {
+      xc[0] = sx1[inext];
+      xc[1] = sx2[inext];
+      xc[2] = sx3[inext];
+    }
     double E[3], B[3];
     gather_o<T, 3, ORDER>(E1, E2, E3, B1, B2, B3, m, x, E, B);
     if (PUSH == PIC_PUSH_BORIS)
