@@ -612,7 +612,10 @@ __device__ __forceinline__ void esirkepov(const ShapeK<K>& sx, const ShapeK<K>& 
                                           double c2, double c3, Add add) {
   static_assert(N == K || N == K - 1, "node count");
   // The running sum of W_d along d is (prefix sum of the shape differences
-  // up to the node) times the transverse weight.  A particle that stays in
+  // up to the node) times the transverse weight.  Exactly zero contributions
+  // are skipped on the full stencil (where every direction without a cell
+  // change leaves a row of them), not on the short one, where they are rare
+  // and the test would cost more than the add.  A particle that stays in
   // its cell along d has an empty last node there, so the prefix sum up to
   // the node before it is exactly zero; it is set so (the differences'
   // rounding would leave a residue), which makes the full loop give the same
@@ -647,7 +650,7 @@ __device__ __forceinline__ void esirkepov(const ShapeK<K>& sx, const ShapeK<K>& 
 #pragma unroll
       for (int a = 0; a < N - 1; ++a) {
         const double run = cx[a] * w;
-        if (run != 0.0) add(0, a, b, c, c1 * run);
+        if (N < K || run != 0.0) add(0, a, b, c, c1 * run);
       }
     }
 #pragma unroll
@@ -658,7 +661,7 @@ __device__ __forceinline__ void esirkepov(const ShapeK<K>& sx, const ShapeK<K>& 
 #pragma unroll
       for (int b = 0; b < N - 1; ++b) {
         const double run = cy[b] * w;
-        if (run != 0.0) add(1, a, b, c, c2 * run);
+        if (N < K || run != 0.0) add(1, a, b, c, c2 * run);
       }
     }
 #pragma unroll
@@ -669,7 +672,7 @@ __device__ __forceinline__ void esirkepov(const ShapeK<K>& sx, const ShapeK<K>& 
 #pragma unroll
       for (int c = 0; c < N - 1; ++c) {
         const double run = cz[c] * w;
-        if (run != 0.0) add(2, a, b, c, c3 * run);
+        if (N < K || run != 0.0) add(2, a, b, c, c3 * run);
       }
     }
 }
