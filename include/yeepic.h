@@ -245,9 +245,9 @@ int pic_set_deposit_mode(pic_grid *g, int mode);
  * deposited current.
  * With deposit on a 3D grid the particles of every species are sorted by
  * spatial tile (8^3 cells), and within a tile by x3 cell plane, at the first
- * step and then every
- * pic_set_sort_interval steps, and the current of each tile is accumulated in
- * on-chip memory: such calls REORDER the particles (x, u and id together).
+ * step and then every pic_set_sort_interval steps, and the current of each
+ * tile is accumulated in on-chip memory: such calls REORDER the particles
+ * (x, u and id together).
  * Vacuum calls and 2D grids keep the order.  A vacuum call on a 3D grid with
  * nsteps >= 2 pushes each species of at least 32768 particles as a copy in
  * library scratch sorted by the same tiles (two copies of 56 bytes per
