@@ -78,26 +78,6 @@ def _device_uniform_particles(npart, lo, hi, seed, torch):
     return x.contiguous(), torch.zeros_like(x)
 
 
-def _device_plasma(n, dx, ppd, u_th, seed, torch):
-    """ppd^3 electrons per cell on a regular sub-lattice (cell-centred
-    offsets), momenta N(0, u_th^2) per component from a seeded generator."""
-    n1, n2, n3 = n
-    dev = "cuda:0"
-    off = (torch.arange(ppd, device=dev, dtype=torch.float64) + 0.5) / ppd
-    cx = ((torch.arange(n1, device=dev, dtype=torch.float64)[:, None] + off[None, :]).reshape(-1)) * dx[0]
-    cy = ((torch.arange(n2, device=dev, dtype=torch.float64)[:, None] + off[None, :]).reshape(-1)) * dx[1]
-    cz = ((torch.arange(n3, device=dev, dtype=torch.float64)[:, None] + off[None, :]).reshape(-1)) * dx[2]
-    npart = cx.numel() * cy.numel() * cz.numel()
-    x = torch.empty((3, npart), device=dev, dtype=torch.float64)
-    x[0].view(cz.numel(), cy.numel(), cx.numel()).copy_(cx[None, None, :].expand(cz.numel(), cy.numel(), -1))
-    x[1].view(cz.numel(), cy.numel(), cx.numel()).copy_(cy[None, :, None].expand(cz.numel(), -1, cx.numel()))
-    x[2].view(cz.numel(), cy.numel(), cx.numel()).copy_(cz[:, None, None].expand(-1, cy.numel(), cx.numel()))
-    g = torch.Generator(device=dev)
-    g.manual_seed(seed)
-    u = u_th * torch.randn((3, npart), generator=g, device=dev, dtype=torch.float64)
-    return x, u
-
-
 def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -220,7 +200,7 @@ def run_plasma(torch, b, wl, CE, CB, steps, dt=None, order=1):
     pulse = wl.Sin2Pulse(a0=10.0, Lp=10 * L0, period=n[0] * dx[0])
     E, B = _device_fields(n, dx, pulse, 12 * L0, 4 * L0, torch.float32, torch)
     J = [torch.zeros_like(E[0]) for _ in range(3)]
-    xd, ud = _device_plasma(n, dx, 2, 0.01, 3, torch)
+    xd, ud = wl.device_lattice_particles(n, dx, 2, 0.01, 3, torch)
     npart = xd.shape[1]
     grid = b.Grid(E, B, dx, dt, CE, CB, J=J, prec="fp32")
     grid.set_shape(order)

@@ -170,6 +170,29 @@ def lattice_particles(n, dx, ppc_per_dim, seed, u_th):
     return X, U
 
 
+def device_lattice_particles(n, dx, ppc_per_dim, u_th, seed, torch):
+    """The plasma load of ``lattice_particles`` built on cuda:0 (no host copy
+    of a full-size load): ppc_per_dim^3 particles per cell on the cell-centred
+    sub-lattice, x1 fastest, then x2, then x3; momenta N(0, u_th^2) per
+    component from a seeded device generator.  ``torch`` is passed in so that
+    this module does not import it."""
+    n1, n2, n3 = n
+    dev = "cuda:0"
+    off = (torch.arange(ppc_per_dim, device=dev, dtype=torch.float64) + 0.5) / ppc_per_dim
+    cx = ((torch.arange(n1, device=dev, dtype=torch.float64)[:, None] + off[None, :]).reshape(-1)) * dx[0]
+    cy = ((torch.arange(n2, device=dev, dtype=torch.float64)[:, None] + off[None, :]).reshape(-1)) * dx[1]
+    cz = ((torch.arange(n3, device=dev, dtype=torch.float64)[:, None] + off[None, :]).reshape(-1)) * dx[2]
+    npart = cx.numel() * cy.numel() * cz.numel()
+    x = torch.empty((3, npart), device=dev, dtype=torch.float64)
+    x[0].view(cz.numel(), cy.numel(), cx.numel()).copy_(cx[None, None, :].expand(cz.numel(), cy.numel(), -1))
+    x[1].view(cz.numel(), cy.numel(), cx.numel()).copy_(cy[None, :, None].expand(cz.numel(), -1, cx.numel()))
+    x[2].view(cz.numel(), cy.numel(), cx.numel()).copy_(cz[:, None, None].expand(-1, cy.numel(), cx.numel()))
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    u = u_th * torch.randn((3, npart), generator=g, device=dev, dtype=torch.float64)
+    return x, u
+
+
 def small_moves(x, dx, L, seed, frac=0.9):
     """New positions within ``frac`` cells of ``x`` (periodic), for deposit
     checks."""

@@ -6,6 +6,11 @@ the oracle can compute.
   reaches at most two cells along x2 and x3, so after s steps the window's
   interior, 2s cells away from its edges, is exactly the full run's; fields
   there and electrons that start there are compared.
+* 512 x 256 x 256 with FP32 fields and 268M electrons (the plasma
+  workload): the oracle runs on a periodic 512 x 24 x 24 window around the
+  axis with every electron that starts in it; the same reach argument gives
+  an exact interior, where fields, the last step's current and the electrons
+  that start there are compared.
 * 2048 x 512 x 512 with FP32 fields (the mixed-precision workload): the
   plane wave does not depend on x2 and x3, so a periodic 2048 x 4 x 4 window
   is exactly the full run; FP32 fields are held to 1e-5 of the FP64 oracle
@@ -17,7 +22,7 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-from oracle import pic  # noqa: E402
+from oracle import fdtd, particles, pic  # noqa: E402
 from paper_2004_03754_amd import binding as b, workloads as wl  # noqa: E402
 
 torch = pytest.importorskip("torch")
@@ -88,6 +93,90 @@ def test_headline_workload_window_parity(steps, half):
     check(float(np.max(np.abs(ug - sp["u"]) / np.maximum(1.0, np.abs(sp["u"])))), 1e-12,
           f"headline {steps} steps u")
     check(float(np.max(np.abs(xg - sp["x"]))) / (n[0] * DX[0]), 1e-12, f"headline {steps} steps x")
+    grid.close()
+
+
+def test_plasma_workload_window_parity():
+    """The plasma workload at full size in the benchmark's launch
+    configuration: 512 x 256 x 256 cells, FP32 fields, 268,435,456 electrons
+    (8 per cell on the sub-lattice, u_th = 0.01, w = 0.01/8), Gaussian laser
+    a0 = 10, w0 = 4 lambda0; Boris, Esirkepov deposit, sort interval 3, for
+    4 steps (sorts before steps 0 and 3, the second from the keys the push
+    before it wrote).  The oracle (FP64, on the FP32 initial values) runs a
+    periodic 512 x 24 x 24 window around the axis with the 2.4M electrons
+    that start in it.  A step reaches at most two cells along x2 and x3 and
+    an electron moves at most 0.125 cells, so after 4 steps everything 10
+    cells inside the window is exactly the full run's.  There: fields to
+    1e-5 of the largest (FP32 storage), the last step's current to 1e-5 of
+    the largest, and every electron that starts there (by id, the GPU
+    reorders them): gamma to 1e-6, u to 1e-6 of max(1, |u|), x to 1e-6 of
+    a cell."""
+    CE = b.design_coeffs(16, 0.5, "E")
+    CB = b.design_coeffs(16, 0.5, "B")
+    n = (512, 256, 256)
+    steps, half, marg = 4, 12, 10
+    qw = 0.01 / 8
+    d = "cuda:0"
+    pulse = wl.Sin2Pulse(a0=10.0, Lp=10 * L0, period=n[0] * DX[0])
+    E, B = _laser_device(n, pulse, 12 * L0, 4 * L0, torch.float32)
+    J = [torch.zeros_like(E[0]) for _ in range(3)]
+    xd, ud = wl.device_lattice_particles(n, DX, 2, 0.01, 3, torch)
+    npart = xd.shape[1]
+    ids = torch.arange(npart, device=d, dtype=torch.int64)
+    w0, w1 = 128 - half, 128 + half
+    in_w = ((xd[1] >= w0 * DX[1]) & (xd[1] < w1 * DX[1]) & (xd[2] >= w0 * DX[2]) & (xd[2] < w1 * DX[2]))
+    widx = torch.nonzero(in_w).flatten()
+    xs, us, wid = host(xd[:, widx]), host(ud[:, widx]), widx.cpu().numpy()
+    del in_w, widx
+    xs[1] -= w0 * DX[1]
+    xs[2] -= w0 * DX[2]
+    Ew = [host(e[w0:w1, w0:w1, :]) for e in E]
+    Bw = [host(v[w0:w1, w0:w1, :]) for v in B]
+    grid = b.Grid(E, B, DX, wl.DT, CE, CB, J=J, prec="fp32")
+    p = b.Particles(xd, ud, q=-1.0, m=1.0, w=qw, id=ids)
+    print(f"plasma window parity: 512x256x256 FP32, {npart} electrons, {steps} steps", flush=True)
+    grid.step_n([p], steps, pusher="boris", deposit=True)
+    grid.sync()
+    # oracle: steps - 1 steps, then the last one by hand to keep its current
+    sp = {"x": xs, "u": us, "q": -1.0, "m": 1.0, "w": qw}
+    Er, Br = pic.run(Ew, Bw, [sp], CE, CB, DX, wl.DT, steps - 1, pusher="boris", deposit=True)
+    Ep, Bp = particles.gather(Er, Br, sp["x"], DX)
+    u_new = particles.boris(sp["u"], Ep, Bp, -1.0, wl.DT)
+    Lw = [n[0] * DX[0], 2 * half * DX[1], 2 * half * DX[2]]
+    x_new, _ = particles.advance_position(sp["x"], u_new, wl.DT, Lw)
+    Jr = particles.deposit(sp["x"], x_new, -1.0, qw, DX, wl.DT, Er[0].shape, 3, u=u_new)
+    Er, Br = fdtd.sweep(Er, Br, Jr, CE, CB, DX, wl.DT)
+    c = slice(marg, 2 * half - marg)
+    fscale = max(float(np.max(np.abs(r[c, c, :]))) for r in list(Er) + list(Br))
+    ferr = max(float(np.max(np.abs(host(g[w0:w1, w0:w1, :])[c, c, :] - r[c, c, :])))
+               for g, r in zip(E + B, list(Er) + list(Br))) / fscale
+    jscale = max(float(np.max(np.abs(r[c, c, :]))) for r in Jr)
+    jerr = max(float(np.max(np.abs(host(g[w0:w1, w0:w1, :])[c, c, :] - r[c, c, :]))) for g, r in zip(J, Jr)) / jscale
+    # electrons that start 10 cells inside, found on the GPU by id
+    inner = ((xs[1] >= marg * DX[1]) & (xs[1] < (2 * half - marg) * DX[1]) &
+             (xs[2] >= marg * DX[2]) & (xs[2] < (2 * half - marg) * DX[2]))
+    sel = np.flatnonzero(inner)
+    inv = torch.empty_like(ids)
+    inv[ids] = torch.arange(npart, device=d, dtype=torch.int64)
+    at = inv[torch.as_tensor(wid[sel], device=d)]
+    del inv
+    xg, ug = host(xd[:, at]), host(ud[:, at])
+    xg[1] -= w0 * DX[1]
+    xg[2] -= w0 * DX[2]
+    ur, xr = u_new[:, sel], x_new[:, sel]
+    uerr = float(np.max(np.linalg.norm(ug - ur, axis=0) / np.maximum(1.0, np.linalg.norm(ur, axis=0))))
+    g_g, g_r = np.sqrt(1 + np.sum(ug * ug, 0)), np.sqrt(1 + np.sum(ur * ur, 0))
+    gerr = float(np.max(np.abs(g_g - g_r) / g_r))
+    xerr = max(float(np.max(np.abs(xg[k] - xr[k]))) / DX[k] for k in range(3))
+    print(f"plasma window: fields {ferr:.2e} (joint, max {fscale:.3g}), current {jerr:.2e} (max {jscale:.3g}); "
+          f"{sel.size} electrons: u {uerr:.2e}, gamma {gerr:.2e}, x {xerr:.2e} cells", flush=True)
+    assert sel.size > 40000
+    check(ferr, 1e-5, "plasma full size fields")
+    check(jerr, 1e-5, "plasma full size current")
+    check(gerr, 1e-6, "plasma full size gamma")
+    check(uerr, 1e-6, "plasma full size u")
+    check(xerr, 1e-6, "plasma full size x (cells)")
+    grid.check(p)
     grid.close()
 
 
