@@ -369,6 +369,82 @@ def test_envelope_gradients_match_central_differences(a0s, coeffs16):
         assert abs(fd - gr) <= 1e-5 * abs(fd) + 1e-8 * max(1.0, abs(float(Lv))), (name, j, fd, gr)
 
 
+def test_config4_full_size_gradients():
+    """The differentiated workload at its full size and length, as the bench
+    runs it: 16 stacked 2048 x 256 planes, 2048 steps, one sin^2 envelope per
+    plane (a0 = 10^U(0,3), seed 4, L_p = 10 lambda0, head at 12 lambda0), 64
+    electrons per plane at rest ahead of it, Boris, the library's
+    proposed-solver fit; loss = mean final gamma + the vacuum phase error of
+    E2.  The oracle cannot run this size; two properties that hold at any
+    size are checked instead.
+    (1) The gradients with respect to C^E, C^B and every plane's (a0, L_p,
+    head) do not depend on the checkpoint interval: K = 64 (the bench's, 32
+    segments) and K = 128 give the same values to 1e-14 (each reverse step
+    sees the same recomputed states).
+    (2) Central differences of the GPU forward, h = 1e-9 relative, for the
+    three largest a0 (where the electrons reach gamma ~ 1e5), one plane's
+    L_p and head, the largest a0's L_p, C^E_1 and C^B_2, agree to 1e-3.  The
+    bound is loose for a reason: the linear-shape gather makes the loss only
+    piecewise smooth (its slope jumps whenever an electron crosses a cell
+    face), and over 2048 steps of 1024 electrons the difference quotient
+    moves by 1e-7 .. 3e-4 between steps of 1e-8, 1e-9 and 1e-10 (and by 2e-3
+    at 1e-6), while the adjoint, the exact derivative of the discrete map
+    (pinned to the oracle's autograd at 1e-12 at smaller sizes), does not."""
+    from paper_2004_03754_amd import autograd as pa
+    CE = b.design_coeffs(16, 0.5, "E")
+    CB = b.design_coeffs(16, 0.5, "B")
+    n1, n2, nb, npb, steps = 2048, 256, 16, 64, 2048
+    L0 = wl.LAMBDA0
+    a0v = torch.tensor(10.0 ** (3.0 * wl.rng(4).random(nb)), dtype=torch.float64)
+    Lpv = torch.full((nb,), 10 * L0, dtype=torch.float64)
+    hv = torch.full((nb,), 12 * L0, dtype=torch.float64)
+    x = torch.zeros((3, nb * npb), dtype=torch.float64)
+    x[0] = (12.5 * L0 + torch.arange(npb, dtype=torch.float64) * (2 * L0 / npb)).repeat(nb)
+    x[1] = 0.5 * n2 * DX[1]
+    x[2] = torch.arange(nb, dtype=torch.float64).repeat_interleave(npb) + 0.5
+    xd = x.to("cuda:0").contiguous()
+    ud = torch.zeros_like(xd)
+    with torch.no_grad():
+        Eref, _ = pa.sin2_pulse_fields(n1, n2, nb, DX, a0v, Lpv, hv + steps * wl.DT)
+    den = torch.sum(Eref[1] ** 2)
+
+    def loss(a, K=64):
+        E0, B0 = pa.sin2_pulse_fields(n1, n2, nb, DX, a["a0"], a["Lp"], a["head"])
+        cfg = pa.RunConfig(DX, wl.DT, steps, K=K, ndim=2)
+        Ef, Bf, xf, uf = pa.run(a["CE"], a["CB"], E0, B0, xd, ud, cfg)
+        return torch.mean(torch.sqrt(1.0 + torch.sum(uf * uf, 0))) + torch.sum((Ef[1] - Eref[1]) ** 2) / den
+
+    base = {"CE": _t(CE), "CB": _t(CB), "a0": a0v, "Lp": Lpv, "head": hv}
+    grads = {}
+    for K in (64, 128):
+        print(f"config-4 full size: 16 x 2048x256, 2048 steps, K = {K}", flush=True)
+        lv = {k: v.clone().requires_grad_() for k, v in base.items()}
+        Lv = loss(lv, K)
+        Lv.backward()
+        grads[K] = {k: v.grad.numpy().copy() for k, v in lv.items()}
+    for k in base:
+        check(_rel(grads[128][k], grads[64][k]), 1e-14, f"config-4 full size grad {k}: K = 128 vs K = 64")
+    g64 = grads[64]
+    order = np.argsort(a0v.numpy())
+    checks = [("a0", int(order[-1])), ("a0", int(order[-2])), ("a0", int(order[-3])), ("Lp", int(order[nb // 2])),
+              ("head", int(order[-1])), ("Lp", int(order[-1])), ("CE", 0), ("CB", 1)]
+    for name, j in checks:
+        h = 1e-9 * max(abs(float(base[name][j])), 1.0)
+        vals = []
+        for sgn in (1, -1):
+            a = {k: v.clone() for k, v in base.items()}
+            a[name][j] += sgn * h
+            with torch.no_grad():
+                vals.append(float(loss(a)))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        gr = float(g64[name][j])
+        # the quotient's rounding floor: a few ulps of L over 2h, ten times
+        floor = 10 * 4 * 2.0 ** -52 * max(1.0, abs(float(Lv))) / (2 * h)
+        err = abs(fd - gr) / (abs(fd) + 1e3 * floor)
+        print(f"  d L / d {name}[{j}]: adjoint {gr:.10e}, central difference {fd:.10e}", flush=True)
+        check(err, 1e-3, f"config-4 full size d/d{name}[{j}] vs central difference")
+
+
 def test_config4_length_run_matches_oracle(coeffs16):
     """The differentiated workload's shape at its length: 2 planes, 256
     steps, checkpoints every K = 64, Boris; each plane a sin^2 pulse
