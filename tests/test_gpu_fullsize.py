@@ -180,6 +180,75 @@ def test_plasma_workload_window_parity():
     grid.close()
 
 
+def _rho_device(x, q, w, n):
+    """Charge density on the nodes from device positions: q w times the
+    linear shape (the definition the Esirkepov deposit conserves, Sec. 3.3),
+    summed with index_add in FP64, one of the eight corners at a time."""
+    n1, n2, n3 = n
+    rho = torch.zeros(n3 * n2 * n1, device="cuda:0", dtype=torch.float64)
+    idx, wts = [], []
+    for d, nd in enumerate((n1, n2, n3)):
+        u = x[d] * (1.0 / DX[d])
+        f = torch.floor(u)
+        i0 = f.to(torch.int64) % nd
+        idx.append((i0, (i0 + 1) % nd))
+        wts.append((1.0 - (u - f), u - f))
+    for a in range(2):
+        for bb in range(2):
+            for c in range(2):
+                lin = (idx[2][c] * n2 + idx[1][bb]) * n1 + idx[0][a]
+                rho.index_add_(0, lin, q * w * wts[0][a] * wts[1][bb] * wts[2][c])
+    return rho.view(n3, n2, n1)
+
+
+def _div_yee_device(E):
+    """Gauss-law divergence with the Yee (C^B = e1) stencil on the nodes:
+    backward differences along each direction (periodic), FP64."""
+    e = [c.to(torch.float64) for c in E]
+    return ((e[0] - torch.roll(e[0], 1, 2)) / DX[0] + (e[1] - torch.roll(e[1], 1, 1)) / DX[1]
+            + (e[2] - torch.roll(e[2], 1, 0)) / DX[2])
+
+
+def test_plasma_workload_gauss_law_200_steps():
+    """The plasma workload at full size for its 200 steps (512 x 256 x 256,
+    FP32 fields, 268M electrons, the bench's launch configuration): Sec. 3.3,
+    with the charge-conserving deposit at dt = dx1/2 (Ampere stencil = Yee,
+    no x1 correction) div E - rho keeps its initial value on every node.  rho
+    from the GPU's particle positions, div E from its fields (both in FP64);
+    the change is at most the FP32 rounding of E in each step's update
+    accumulated linearly, 200 x sum_d(2/dx_d) x 2^-24 x max|E|; the plasma
+    must have responded far more than that."""
+    CE = b.design_coeffs(16, 0.5, "E")
+    CB = b.design_coeffs(16, 0.5, "B")
+    n = (512, 256, 256)
+    steps = 200
+    qw = 0.01 / 8
+    pulse = wl.Sin2Pulse(a0=10.0, Lp=10 * L0, period=n[0] * DX[0])
+    E, B = _laser_device(n, pulse, 12 * L0, 4 * L0, torch.float32)
+    J = [torch.zeros_like(E[0]) for _ in range(3)]
+    xd, ud = wl.device_lattice_particles(n, DX, 2, 0.01, 3, torch)
+    rho0 = _rho_device(xd, -1.0, qw, n)
+    res0 = _div_yee_device(E) - rho0
+    grid = b.Grid(E, B, DX, wl.DT, CE, CB, J=J, prec="fp32")
+    p = b.Particles(xd, ud, q=-1.0, m=1.0, w=qw)
+    print(f"plasma Gauss law: 512x256x256 FP32, {xd.shape[1]} electrons, {steps} steps", flush=True)
+    grid.step_n([p], steps, pusher="boris", deposit=True)
+    grid.sync()
+    rho = _rho_device(xd, -1.0, qw, n)
+    res = _div_yee_device(E) - rho
+    drift = float(torch.max(torch.abs(res - res0)))
+    response = float(torch.max(torch.abs(rho - rho0)))
+    del res, res0, rho, rho0
+    emax = max(float(torch.max(torch.abs(e))) for e in E)
+    bound = steps * sum(2 / d for d in DX) * 2.0 ** -24 * emax
+    print(f"plasma Gauss law over {steps} steps: drift {drift:.2e}, bound {bound:.2e}, "
+          f"max change of rho {response:.2e}", flush=True)
+    check(drift / bound, 1.0, "full-size plasma Gauss-law drift / bound")
+    assert response > 100 * drift
+    grid.check(p)
+    grid.close()
+
+
 def test_headline_analogue_500_steps():
     """A 256 x 64 x 64 analogue of the headline workload over 500 steps
     (FP64, proposed solver at dt = dx1/2, exact pusher): a Gaussian sin^2
