@@ -304,6 +304,12 @@ __device__ __forceinline__ double analytic_solve(const double u[3], const double
   }
   if (kw * fabs(tau) > 50.0) tau = copysign(50.0 / kw, dt);
   conv = false;
+  // the last two step lengths: a step that is not below half of the one
+  // before the last one is replaced by bisection, so that steps that cross
+  // the root back and forth (Newton on log t can cycle between the two ends
+  // of the bracket when t rises steeply past the root) still halve the
+  // bracket every other iteration
+  double dx = hi - lo, dxold = dx;
   for (int it = 0; it < max_iter; ++it) {
     const ExpCoef e = exp_coef(k2, w2, tau);
     const double t = e.a1 * U0[0] + e.A1 * V1[0] + e.a3 * V2[0] + e.A3 * V3[0];
@@ -338,7 +344,9 @@ __device__ __forceinline__ double analytic_solve(const double u[3], const double
     } else {
       nx = tau - log(ratio) * (t / g);
     }
-    if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
+    if (!(nx > lo && nx < hi) || fabs(nx - tau) > 0.5 * dxold) nx = 0.5 * (lo + hi);
+    dxold = dx;
+    dx = fabs(nx - tau);
     const bool small = fabs(nx - tau) <= 1e-15 * fabs(tau);
     tau = nx;
     if (small) {

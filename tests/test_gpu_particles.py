@@ -116,6 +116,35 @@ def test_strong_uniform_fields_against_50_digit_values(pusher):
     grid.close()
 
 
+def test_exact_push_root_solve_does_not_cycle():
+    """An exact push whose proper-time solve used to cycle: Newton on log t
+    jumped between the two ends of the bracket (t/dt = 0.39 and 25.8), each
+    step landing just inside it, and ended at the 100-iteration cap far from
+    the root.  The state is one of the 2048 x 512 x 512 plane wave's
+    electrons (a0 = 1e4, FP64 fields) within its first 100 steps.  The solve
+    must converge (no PIC_ENOCONV) and give the oracle's momentum to 1e-12.
+    The electron sits on a node, so the gather returns the uniform field
+    values exactly on both sides."""
+    u0 = np.array([[10.214248728212798], [-4.468296289411733], [0.0]])
+    Ev = (0.0, -533.9441938657718, 0.0)
+    Bv = (0.0, 0.0, -531.3731066300709)
+    dt = 0.09817477042468103
+    n1, n2, dx = 64, 4, (0.25, 1.0)
+    E = [np.full((1, n2, n1), v) for v in Ev]
+    B = [np.full((1, n2, n1), v) for v in Bv]
+    x = np.array([[16 * dx[0]], [2 * dx[1]], [0.5]])
+    grid = b.Grid([dev(e) for e in E], [dev(v) for v in B], dx, dt, [1.0], [1.0], ndim=2)
+    ud = dev(u0)
+    p = b.Particles(dev(x), ud, q=-1.0, m=1.0)
+    grid.gather_push(p, "analytic")
+    grid.sync()
+    grid.check(p)
+    ref = pt.analytic(u0, np.array(Ev)[:, None], np.array(Bv)[:, None], -1.0, dt)
+    err = float(np.linalg.norm(host(ud) - ref) / max(1.0, np.linalg.norm(ref)))
+    check(err, 1e-12, "exact push after a cycling root solve")
+    grid.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("ndim", [3, 2])
 def test_deposit(ndim, prec, coeffs16):
