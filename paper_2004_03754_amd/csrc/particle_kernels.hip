@@ -23,8 +23,12 @@ __global__ __launch_bounds__(256) void gather_push_kernel(const T* __restrict__ 
                                                           double* __restrict__ o3) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= np) return;
-  double x[3] = {x1[p], x2[p], (NDIM == 3 || m.n3 > 1) ? x3[p] : 0.0};
-  double u[3] = {u1[p], u2[p], u3[p]};
+  // particle state is streamed once: non-temporal loads and stores keep it
+  // from evicting the field lines the gathers share in L2
+  double x[3] = {__builtin_nontemporal_load(x1 + p), __builtin_nontemporal_load(x2 + p),
+                 (NDIM == 3 || m.n3 > 1) ? __builtin_nontemporal_load(x3 + p) : 0.0};
+  double u[3] = {__builtin_nontemporal_load(u1 + p), __builtin_nontemporal_load(u2 + p),
+                 __builtin_nontemporal_load(u3 + p)};
   double E[3], B[3];
   gather_o<T, NDIM, ORDER>(E1, E2, E3, B1, B2, B3, m, x, E, B);
   if (PUSH == PIC_PUSH_BORIS)
@@ -35,16 +39,16 @@ __global__ __launch_bounds__(256) void gather_push_kernel(const T* __restrict__ 
     analytic(u, E, B, qm, dt, m);
   const double ig = dt / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   if (o1) {
-    o1[p] = x[0];
-    o2[p] = x[1];
-    if (NDIM == 3 && o3) o3[p] = x[2];
+    __builtin_nontemporal_store(x[0], o1 + p);
+    __builtin_nontemporal_store(x[1], o2 + p);
+    if (NDIM == 3 && o3) __builtin_nontemporal_store(x[2], o3 + p);
   }
-  x1[p] = wrap_pos(x[0] + ig * u[0], m.L1);
-  x2[p] = wrap_pos(x[1] + ig * u[1], m.L2);
-  if (NDIM == 3) x3[p] = wrap_pos(x[2] + ig * u[2], m.L3);
-  u1[p] = u[0];
-  u2[p] = u[1];
-  u3[p] = u[2];
+  __builtin_nontemporal_store(wrap_pos(x[0] + ig * u[0], m.L1), x1 + p);
+  __builtin_nontemporal_store(wrap_pos(x[1] + ig * u[1], m.L2), x2 + p);
+  if (NDIM == 3) __builtin_nontemporal_store(wrap_pos(x[2] + ig * u[2], m.L3), x3 + p);
+  __builtin_nontemporal_store(u[0], u1 + p);
+  __builtin_nontemporal_store(u[1], u2 + p);
+  __builtin_nontemporal_store(u[2], u3 + p);
 }
 
 template <typename T, int NDIM, int ORDER>

@@ -160,13 +160,13 @@ __global__ __launch_bounds__(256) void tile_scatter_kernel(const double* __restr
   double v[6] = {0, 0, 0, 0, 0, 0};
   int64_t pid = 0;
   if (live) {
-    v[0] = x1[p];
-    v[1] = x2[p];
-    v[2] = x3[p];
-    v[3] = u1[p];
-    v[4] = u2[p];
-    v[5] = u3[p];
-    if (id) pid = id[p];
+    v[0] = __builtin_nontemporal_load(x1 + p);
+    v[1] = __builtin_nontemporal_load(x2 + p);
+    v[2] = __builtin_nontemporal_load(x3 + p);
+    v[3] = __builtin_nontemporal_load(u1 + p);
+    v[4] = __builtin_nontemporal_load(u2 + p);
+    v[5] = __builtin_nontemporal_load(u3 + p);
+    if (id) pid = __builtin_nontemporal_load(id + p);
   }
   int leader_lane, runlen;
   key_runs(key, leader_lane, runlen);
@@ -176,13 +176,13 @@ __global__ __launch_bounds__(256) void tile_scatter_kernel(const double* __restr
   base = __shfl(base, leader_lane);
   if (!live) return;
   const int64_t q = (int64_t)offsets[key] + base + (lane - leader_lane);
-  sx1[q] = v[0];
-  sx2[q] = v[1];
-  sx3[q] = v[2];
-  su1[q] = v[3];
-  su2[q] = v[4];
-  su3[q] = v[5];
-  if (id) sid[q] = pid;
+  __builtin_nontemporal_store(v[0], sx1 + q);
+  __builtin_nontemporal_store(v[1], sx2 + q);
+  __builtin_nontemporal_store(v[2], sx3 + q);
+  __builtin_nontemporal_store(v[3], su1 + q);
+  __builtin_nontemporal_store(v[4], su2 + q);
+  __builtin_nontemporal_store(v[5], su3 + q);
+  if (id) __builtin_nontemporal_store(pid, sid + q);
 }
 
 // ---------------------------------------------------------------------------
@@ -360,6 +360,15 @@ __device__ __forceinline__ void acc_flush(const unsigned long long* jh, const un
   }
 }
 
+// Workgroups are dealt to the eight XCDs in turn (workgroup b to XCD
+// b % 8).  Tile of workgroup b: each XCD takes one contiguous run of tiles,
+// so the tiles an XCD holds at once are neighbours whose field rows and
+// current nodes share its L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int x = b & 7, k = b >> 3, q = nb >> 3, r = nb & 7;
+  return x * q + min(x, r) + k;
+}
+
 // FP32 linear-shape pushes fit three workgroups per CU in LDS: the Boris and
 // Higuera-Cary ones are held to the registers of three waves per SIMD too
 template <typename T, int PUSH, int ORDER, bool TWO>
@@ -372,10 +381,10 @@ void tile_push_kernel(
     double* dx3, double* du1, double* du2, double* du3, int64_t* did, double qm, double qw, double dt,
     double* stage, int* __restrict__ keys, int* __restrict__ counts) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const TileWin w = tile_window(blockIdx.x, tg);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const TileWin w = tile_window(tile, tg);
   unsigned long long* jh = reinterpret_cast<unsigned long long*>(lds_raw);
   unsigned long long* jl = jh + 3 * w.R;
-  const int tile = blockIdx.x;
   const int beg = offsets[tile * tg.sub], end = offsets[(tile + 1) * tg.sub];
   T* const Jg[3] = {J1, J2, J3};
   if (end == beg && !stage) return;  // uniform: no particles, nothing to add
@@ -388,18 +397,19 @@ void tile_push_kernel(
   // gather that depends on it
   double xc[3] = {0.0, 0.0, 0.0};
   if (beg + (int)threadIdx.x < end) {
-    xc[0] = sx1[beg + threadIdx.x];
-    xc[1] = sx2[beg + threadIdx.x];
-    xc[2] = sx3[beg + threadIdx.x];
+    xc[0] = __builtin_nontemporal_load(sx1 + beg + threadIdx.x);
+    xc[1] = __builtin_nontemporal_load(sx2 + beg + threadIdx.x);
+    xc[2] = __builtin_nontemporal_load(sx3 + beg + threadIdx.x);
   }
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
     const double x[3] = {xc[0], xc[1], xc[2]};
-    double u[3] = {su1[i], su2[i], su3[i]};
+    double u[3] = {__builtin_nontemporal_load(su1 + i), __builtin_nontemporal_load(su2 + i),
+                   __builtin_nontemporal_load(su3 + i)};
     const int inext = i + blockDim.x;
     if (inext < end) {
-      xc[0] = sx1[inext];
-      xc[1] = sx2[inext];
-      xc[2] = sx3[inext];
+      xc[0] = __builtin_nontemporal_load(sx1 + inext);
+      xc[1] = __builtin_nontemporal_load(sx2 + inext);
+      xc[2] = __builtin_nontemporal_load(sx3 + inext);
     }
     double E[3], B[3];
     gather_o<T, 3, ORDER>(E1, E2, E3, B1, B2, B3, m, x, E, B);
@@ -412,12 +422,12 @@ void tile_push_kernel(
     const double ig = dt / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     const double xn[3] = {wrap_pos(x[0] + ig * u[0], m.L1), wrap_pos(x[1] + ig * u[1], m.L2),
                           wrap_pos(x[2] + ig * u[2], m.L3)};
-    dx1[i] = xn[0];
-    dx2[i] = xn[1];
-    dx3[i] = xn[2];
-    du1[i] = u[0];
-    du2[i] = u[1];
-    du3[i] = u[2];
+    __builtin_nontemporal_store(xn[0], dx1 + i);
+    __builtin_nontemporal_store(xn[1], dx2 + i);
+    __builtin_nontemporal_store(xn[2], dx3 + i);
+    __builtin_nontemporal_store(u[0], du1 + i);
+    __builtin_nontemporal_store(u[1], du2 + i);
+    __builtin_nontemporal_store(u[2], du3 + i);
     if (sid && sid != did) did[i] = sid[i];
     if (keys) {  // the next sort's tile key and count, from the new position
       const int key = tile_key_at(xn[0], xn[1], xn[2], m, tg);
@@ -447,10 +457,10 @@ __global__ __launch_bounds__(256) void tile_deposit_kernel(T* __restrict__ J1, T
                                                            const double* xn2, const double* xn3, double qw, double dt,
                                                            double* stage) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const TileWin w = tile_window(blockIdx.x, tg);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const TileWin w = tile_window(tile, tg);
   unsigned long long* jh = reinterpret_cast<unsigned long long*>(lds_raw);
   unsigned long long* jl = jh + 3 * w.R;
-  const int tile = blockIdx.x;
   const int beg = offsets[tile * tg.sub], end = offsets[(tile + 1) * tg.sub];
   T* const Jg[3] = {J1, J2, J3};
   if (end == beg && !stage) return;
@@ -459,8 +469,10 @@ __global__ __launch_bounds__(256) void tile_deposit_kernel(T* __restrict__ J1, T
   acc_clear(jh, (TWO ? 6 : 3) * w.R);
   __syncthreads();
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
-    const double xo[3] = {xo1[i], xo2[i], xo3[i]};
-    const double xn[3] = {xn1[i], xn2[i], xn3[i]};
+    const double xo[3] = {__builtin_nontemporal_load(xo1 + i), __builtin_nontemporal_load(xo2 + i),
+                          __builtin_nontemporal_load(xo3 + i)};
+    const double xn[3] = {__builtin_nontemporal_load(xn1 + i), __builtin_nontemporal_load(xn2 + i),
+                          __builtin_nontemporal_load(xn3 + i)};
     deposit_one<T, ORDER, TWO>(xo, xn, m, tg, w, jh, jl, ts, c1, c2, c3, Jg);
   }
   __syncthreads();
