@@ -343,6 +343,36 @@ __device__ __forceinline__ void acc_flush(const unsigned long long* jh, const un
                                           const TileScale& ts, const TileWin& w, const TileGeom& tg, const Mesh& m,
                                           int tile, T* const Jg[3], double* stage) {
   const size_t pl = (size_t)m.n1 * m.n2;
+  if (!stage && w.r0 <= 64) {
+    // one x1 row of the window per L lanes (the row's nodes in its first
+    // r0 lanes), so that each lane keeps its x1 node and steps its row
+    // indices by carries instead of dividing; row = (comp r2 + c) r1 + b
+    const int L = w.r0 <= 16 ? 16 : (w.r0 <= 32 ? 32 : 64);
+    const int a = (int)threadIdx.x % L, P = (int)blockDim.x / L, r2 = tg.r[2];
+    if (a >= w.r0) return;
+    const int gx = wrapn(w.lo[0] + a - tg.m[0] - 1, m.n1);
+    int row = (int)threadIdx.x / L;
+    int b = row % w.r1, c = (row / w.r1) % r2, comp = row / (w.r1 * r2);
+    for (; row < 3 * w.r1 * r2; row += P) {
+      const int i = row * w.r0 + a;
+      const double v = acc_value<TWO>(jh[i], TWO ? jl[i] : 0ull, ts);
+      if (v != 0.0) {
+        const int gy = wrapn(w.lo[1] + b - tg.m[1] - 1, m.n2);
+        const int gz = wrapn(w.lo[2] + c - tg.m[2] - 1, m.n3);
+        unsafeAtomicAdd(&Jg[comp][(size_t)gz * pl + (size_t)gy * m.n1 + gx], (T)v);
+      }
+      b += P;
+      while (b >= w.r1) {
+        b -= w.r1;
+        ++c;
+      }
+      while (c >= r2) {
+        c -= r2;
+        ++comp;
+      }
+    }
+    return;
+  }
   for (int i = threadIdx.x; i < 3 * w.R; i += blockDim.x) {
     const double v = acc_value<TWO>(jh[i], TWO ? jl[i] : 0ull, ts);
     if (stage) {
