@@ -58,6 +58,11 @@ def _device_fields(n, dx, pulse, x_head, w0, dtype, torch):
     B = [torch.zeros((n3, n2, n1), device=dev, dtype=dtype) for _ in range(3)]
     E[1].copy_((P[:, :, None] * torch.as_tensor(e2, device=dev)[None, None, :]).to(dtype))
     B[2].copy_((P[:, :, None] * torch.as_tensor(b3, device=dev)[None, None, :]).to(dtype))
+    lon = wl.laser_longitudinal(n, dx, pulse, x_head, w0)
+    if lon is not None:  # the Gaussian beam's longitudinal E1, B1
+        e1, p1, b1, q1 = (torch.as_tensor(a, device=dev, dtype=torch.float64) for a in lon)
+        E[0].copy_((p1[:, :, None] * e1[None, None, :]).to(dtype))
+        B[0].copy_((q1[:, :, None] * b1[None, None, :]).to(dtype))
     return E, B
 
 

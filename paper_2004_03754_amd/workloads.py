@@ -121,15 +121,48 @@ def laser_profiles(n, dx, pulse, x_head=0.0, w0=None, centre=None):
     return e2, b3, prof
 
 
+def laser_longitudinal(n, dx, pulse, x_head=0.0, w0=None, centre=None):
+    """Factors of the first-order longitudinal fields of the Gaussian beam,
+    E1 = e1[i] p1[k, j] and B1 = b1[i] q1[k, j], or None without ``w0``.
+
+    With E2 = f(x1) g and B3 = f(x1) g, f = -a'(x_head - x1) and g =
+    exp(-r_perp^2/w0^2), the longitudinal components that make both fields
+    divergence-free are E1 = -a(x_head - x1) dg/dx2 and B1 = -a(x_head - x1)
+    dg/dx3 (d/dx1 of a(x_head - x1) is f), i.e. a(x_head - x1) (2 x2/w0^2) g
+    and a(x_head - x1) (2 x3/w0^2) g: the paraxial beam's first-order terms.
+    Each is sampled at its own staggered location: E1 at ((i+1/2), j, k),
+    B1 at (i, j+1/2, k+1/2) cells."""
+    if w0 is None:
+        return None
+    n1, n2, n3 = n
+    i = np.arange(n1, dtype=np.float64)
+    e1 = pulse.a(x_head - (i + 0.5) * dx[0])
+    b1 = pulse.a(x_head - i * dx[0])
+    c2, c3 = centre if centre is not None else (n2 * dx[1] / 2, n3 * dx[2] / 2)
+    yj = np.arange(n2) * dx[1] - c2
+    zk = np.arange(n3) * dx[2] - c3
+    yh = yj + 0.5 * dx[1]
+    zh = zk + 0.5 * dx[2]
+    p1 = (2 * yj[None, :] / w0 ** 2) * np.exp(-(zk[:, None] ** 2 + yj[None, :] ** 2) / w0 ** 2)
+    q1 = (2 * zh[:, None] / w0 ** 2) * np.exp(-(zh[:, None] ** 2 + yh[None, :] ** 2) / w0 ** 2)
+    return e1, p1, b1, q1
+
+
 def laser_fields(n, dx, pulse, x_head=0.0, w0=None, centre=None, dtype=np.float64):
-    """(E, B) at t = 0 on the (n3, n2, n1) mesh: E2 = B3 = -a'(x_head - x1)
-    (times exp(-r_perp^2/w0^2) if ``w0``), every other component zero."""
+    """(E, B) at t = 0 on the (n3, n2, n1) mesh: E2 = B3 = -a'(x_head - x1),
+    times exp(-r_perp^2/w0^2) with the longitudinal E1, B1 of
+    ``laser_longitudinal`` if ``w0``; every other component zero."""
     n1, n2, n3 = n
     e2, b3, prof = laser_profiles(n, dx, pulse, x_head, w0, centre)
     E = [np.zeros((n3, n2, n1), dtype=dtype) for _ in range(3)]
     B = [np.zeros((n3, n2, n1), dtype=dtype) for _ in range(3)]
     E[1][...] = (prof[:, :, None] * e2[None, None, :]).astype(dtype)
     B[2][...] = (prof[:, :, None] * b3[None, None, :]).astype(dtype)
+    lon = laser_longitudinal(n, dx, pulse, x_head, w0, centre)
+    if lon is not None:
+        e1, p1, b1, q1 = lon
+        E[0][...] = (p1[:, :, None] * e1[None, None, :]).astype(dtype)
+        B[0][...] = (q1[:, :, None] * b1[None, None, :]).astype(dtype)
     return E, B
 
 

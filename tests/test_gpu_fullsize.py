@@ -41,6 +41,11 @@ def _laser_device(n, pulse, x_head, w0, dtype):
     E2 = (pr[:, :, None] * torch.as_tensor(e2, device=d)[None, None, :]).to(dtype).contiguous()
     B3 = (pr[:, :, None] * torch.as_tensor(b3, device=d)[None, None, :]).to(dtype).contiguous()
     z = [torch.zeros_like(E2) for _ in range(4)]
+    lon = wl.laser_longitudinal(n, DX, pulse, x_head, w0)
+    if lon is not None:
+        e1, p1, b1, q1 = (torch.as_tensor(a, device=d, dtype=torch.float64) for a in lon)
+        z[0] = (p1[:, :, None] * e1[None, None, :]).to(dtype).contiguous()
+        z[2] = (q1[:, :, None] * b1[None, None, :]).to(dtype).contiguous()
     return [z[0], E2, z[1]], [z[2], z[3], B3]
 
 
