@@ -393,7 +393,8 @@ __device__ __forceinline__ void acc_flush(const unsigned long long* jh, const un
 // Workgroups are dealt to the eight XCDs in turn (workgroup b to XCD
 // b % 8).  Tile of workgroup b: each XCD takes one contiguous run of tiles,
 // so the tiles an XCD holds at once are neighbours whose field rows and
-// current nodes share its L2.
+// current nodes share its L2.  (Grids have n1 a multiple of 64, so the tile
+// count is a multiple of 8; the formula is a bijection for any count.)
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int x = b & 7, k = b >> 3, q = nb >> 3, r = nb & 7;
   return x * q + min(x, r) + k;
