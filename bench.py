@@ -175,6 +175,10 @@ def run_plane_wave(torch, b, wl, CE, CB, steps):
         grid.close()
         del E, B, xd, ud, grid, p
         torch.cuda.empty_cache()
+        # plain copies of six arrays of the same size, for the sweep's share of them
+        ceil_gbps, _ = stream_ceiling(torch, cells, reps=2, dtype=dtype)
+        out[prec]["stream_ceiling_GBps"] = ceil_gbps
+        out[prec]["sweep_frac_of_stream_ceiling"] = gbps / ceil_gbps
     g32, f32 = keep["fp32"]
     g64, f64 = keep["fp64"]
     rel = (torch.abs(g32 - g64) / g64).cpu()
@@ -456,6 +460,31 @@ def cpu_baseline():
                       f"{d['steps']} steps after 1 warm-up, {d['seconds']:.1f} s, NumPy FP64 single thread"}
 
 
+def stream_ceiling(torch, nelem, reps=5, dtype=None):
+    """The HBM rate of a plain device copy (STREAM copy) of six arrays of
+    ``nelem`` elements (FP64 unless ``dtype``), one copy after another, timed
+    over ``reps`` rounds: 12 array passes, the traffic of a sweep without its
+    stencil."""
+    dtype = torch.float64 if dtype is None else dtype
+    src = [torch.empty(nelem, device="cuda:0", dtype=dtype) for _ in range(6)]
+    dst = [torch.empty_like(a) for a in src]
+    for a, c in zip(src, dst):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    t0, t1 = _events(torch)
+    t0.record()
+    for _ in range(reps):
+        for a, c in zip(src, dst):
+            c.copy_(a)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    elem = src[0].element_size()
+    del src, dst
+    torch.cuda.empty_cache()
+    return 12 * elem * nelem / (ms * 1e-3) / 1e9, ms
+
+
 def copy_calibration(nbytes=1 << 29, reps=3):
     """A plain device-to-device copy of ``nbytes`` (reads nbytes, writes
     nbytes), repeated ``reps`` times: the known traffic against which the HBM
@@ -571,6 +600,11 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "fused B-half/E/B-half sweep, 96 B/cell FP64"},
     }
+    ceil_gbps, ceil_ms = stream_ceiling(torch, cells)
+    res["stream_ceiling"] = {
+        "GBps": ceil_gbps, "ms": ceil_ms, "sweep_frac_of_ceiling": achieved / ceil_gbps,
+        "note": "plain device copies of six FP64 arrays of the headline mesh (STREAM copy, 12 array "
+                "passes): the HBM rate a stencil-free stream reaches on this GPU"}
     if not args.no_extras:
         # mixed precision on the same workload
         fp32 = run_vacuum(torch, b, wl, n, "fp32", pulse, 12 * L, 4 * L, 1 << 20, box, max(50, args.steps // 5),
