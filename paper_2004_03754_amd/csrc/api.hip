@@ -25,6 +25,7 @@ struct SortState {
   double* xs[3] = {nullptr, nullptr, nullptr};
   double* us[3] = {nullptr, nullptr, nullptr};
   int64_t* ids = nullptr;
+  int* perm = nullptr;  // a sort's permutation (sorted position -> source index)
 };
 
 struct pic_grid {
@@ -276,7 +277,7 @@ static int check_particles(const pic_grid* g, const pic_particles* p) {
 
 static void free_sort(SortState& st) {
   void* ptrs[] = {st.keys, st.counts, st.offsets, st.cursors, st.segsum, st.xs[0], st.xs[1], st.xs[2],
-                  st.us[0], st.us[1], st.us[2], st.ids};
+                  st.us[0], st.us[1], st.us[2], st.ids, st.perm};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   st = SortState();
@@ -291,7 +292,8 @@ static int ensure_sort(pic_grid* g, SortState& st, int64_t np, int nbins, bool i
             hipMalloc((void**)&st.counts, (size_t)nbins * sizeof(int)) == hipSuccess &&
             hipMalloc((void**)&st.offsets, ((size_t)nbins + 1) * sizeof(int)) == hipSuccess &&
             hipMalloc((void**)&st.cursors, (size_t)nbins * sizeof(int)) == hipSuccess &&
-            hipMalloc((void**)&st.segsum, (size_t)scan_segments(nbins) * sizeof(int)) == hipSuccess;
+            hipMalloc((void**)&st.segsum, (size_t)scan_segments(nbins) * sizeof(int)) == hipSuccess &&
+            hipMalloc((void**)&st.perm, n * sizeof(int)) == hipSuccess;
   for (int d = 0; d < 3 && ok; ++d)
     ok = hipMalloc((void**)&st.xs[d], n * sizeof(double)) == hipSuccess &&
          hipMalloc((void**)&st.us[d], n * sizeof(double)) == hipSuccess;
@@ -699,6 +701,15 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
     }
     if (rc) return rc;
   }
+  // 3D plasma: a species' particles live in its own arrays or in the sort
+  // scratch.  A sort only ranks them (a permutation), and the push after it
+  // reads them through the permutation from one set and writes them sorted
+  // into the other; steps between sorts push in place.  A call with an odd
+  // number of sorts moves the particles at its first sort instead (scatter
+  // into scratch, push back), so that every call ends with the particles in
+  // the species' own arrays.
+  const int nsorts = tiled ? (nsteps + g->sort_every - 1) / g->sort_every : 0;
+  std::vector<char> in_scratch(tiled ? nspecies : 0, 0);
   for (int step = 0; step < nsteps && rc == PIC_OK; ++step) {
     if (deposit)
       for (int c = 0; c < 3 && rc == PIC_OK; ++c)
@@ -706,25 +717,36 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
     for (int s = 0; s < nspecies && rc == PIC_OK; ++s) {
       if (tiled) {
         SortState& st = g->sorts[s];
-        pic_particles src = *species[s];
+        pic_particles scr = *species[s];
+        for (int d = 0; d < 3; ++d) {
+          scr.x[d] = st.xs[d];
+          scr.u[d] = st.us[d];
+        }
+        scr.id = species[s]->id ? st.ids : nullptr;
+        const pic_particles here = in_scratch[s] ? scr : *species[s];
+        pic_particles src = here, dst = here;
+        const int* perm = nullptr;
         if (step % g->sort_every == 0) {
-          pic_particles scr = *species[s];
-          for (int d = 0; d < 3; ++d) {
-            scr.x[d] = st.xs[d];
-            scr.u[d] = st.us[d];
-          }
-          scr.id = species[s]->id ? st.ids : nullptr;
           // after the first step of the call, the push before counted the tiles
-          rc = launch_tile_sort(g->mesh, tg, *species[s], scr, st.keys, st.counts, st.offsets, st.cursors,
-                                st.segsum, g->stream, step > 0);
-          src = scr;
+          if (step == 0 && nsorts % 2 == 1) {
+            rc = launch_tile_sort(g->mesh, tg, *species[s], scr, st.keys, st.counts, st.offsets, st.cursors,
+                                  st.segsum, g->stream, false);
+            src = scr;
+            dst = *species[s];
+          } else {
+            rc = launch_tile_sort(g->mesh, tg, here, scr, st.keys, st.counts, st.offsets, st.cursors, st.segsum,
+                                  g->stream, step > 0, st.perm);
+            perm = st.perm;
+            dst = in_scratch[s] ? *species[s] : scr;
+            in_scratch[s] = !in_scratch[s];
+          }
         }
         // the push before a sort writes the sort's keys and tile counts
         const bool count_next = (step + 1) % g->sort_every == 0 && step + 1 < nsteps;
         if (rc == PIC_OK)
-          rc = launch_tile_push(g->prec, g->mesh, tg, cur, cur + 3, g->J, st.offsets, src, *species[s], pusher,
-                                g->dt, stage, g->stream, count_next ? st.keys : nullptr,
-                                count_next ? st.counts : nullptr);
+          rc = launch_tile_push(g->prec, g->mesh, tg, cur, cur + 3, g->J, st.offsets, src, dst, pusher, g->dt,
+                                stage, g->stream, count_next ? st.keys : nullptr, count_next ? st.counts : nullptr,
+                                perm);
         continue;
       }
       if (vac && vuse[s]) {

@@ -4,6 +4,7 @@
 //   tile_count   tile key of every particle, counts per tile (wave-aggregated)
 //   tile_scan    exclusive scan of the counts (one workgroup)
 //   tile_scatter counting-sort scatter of x, u (and ids) into scratch
+//   tile_rank    the same sort as a permutation only: perm[sorted] = source
 //   tile_push    per tile: gather + push + position update of its particles,
 //                Esirkepov current into an LDS tile, one atomic flush per node
 //   tile_deposit the same current for given old and new positions
@@ -183,6 +184,27 @@ __global__ __launch_bounds__(256) void tile_scatter_kernel(const double* __restr
   __builtin_nontemporal_store(v[4], su2 + q);
   __builtin_nontemporal_store(v[5], su3 + q);
   if (id) __builtin_nontemporal_store(pid, sid + q);
+}
+
+// The counting sort's placement without moving the particles: perm[q] = p
+// for the sorted position q of particle p (the same cursor runs as
+// tile_scatter).  The push that follows reads each particle through perm and
+// writes it at its sorted position into the other particle buffer, so a sort
+// costs no pass over the particle data of its own.
+__global__ __launch_bounds__(256) void tile_rank_kernel(const int* __restrict__ keys, const int* __restrict__ offsets,
+                                                        int* __restrict__ cursors, int64_t np,
+                                                        int* __restrict__ perm) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = p < np;
+  const int key = live ? keys[p] : -1;
+  int leader_lane, runlen;
+  key_runs(key, leader_lane, runlen);
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+  if (leader_lane == lane && key >= 0) base = atomicAdd(&cursors[key], runlen);
+  base = __shfl(base, leader_lane);
+  if (!live) return;
+  perm[(int64_t)offsets[key] + base + (lane - leader_lane)] = (int)p;
 }
 
 // ---------------------------------------------------------------------------
@@ -409,8 +431,8 @@ void tile_push_kernel(
     const T* __restrict__ B2, const T* __restrict__ B3, T* __restrict__ J1, T* __restrict__ J2, T* __restrict__ J3,
     Mesh m, TileGeom tg, const int* __restrict__ offsets, const double* sx1, const double* sx2, const double* sx3,
     const double* su1, const double* su2, const double* su3, const int64_t* sid, double* dx1, double* dx2,
-    double* dx3, double* du1, double* du2, double* du3, int64_t* did, double qm, double qw, double dt,
-    double* stage, int* __restrict__ keys, int* __restrict__ counts) {
+    double* dx3, double* du1, double* du2, double* du3, int64_t* did, const int* __restrict__ perm, double qm,
+    double qw, double dt, double* stage, int* __restrict__ keys, int* __restrict__ counts) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const TileWin w = tile_window(tile, tg);
@@ -425,22 +447,27 @@ void tile_push_kernel(
   __syncthreads();
   // the next particle's position is loaded one iteration ahead, so that its
   // memory latency overlaps this particle's work instead of delaying the
-  // gather that depends on it
+  // gather that depends on it.  Particle i (sorted position) is read from
+  // source index perm[i] when the sort left a permutation, else from i.
   double xc[3] = {0.0, 0.0, 0.0};
+  int pc = 0;
   if (beg + (int)threadIdx.x < end) {
-    xc[0] = __builtin_nontemporal_load(sx1 + beg + threadIdx.x);
-    xc[1] = __builtin_nontemporal_load(sx2 + beg + threadIdx.x);
-    xc[2] = __builtin_nontemporal_load(sx3 + beg + threadIdx.x);
+    pc = perm ? perm[beg + threadIdx.x] : beg + (int)threadIdx.x;
+    xc[0] = __builtin_nontemporal_load(sx1 + pc);
+    xc[1] = __builtin_nontemporal_load(sx2 + pc);
+    xc[2] = __builtin_nontemporal_load(sx3 + pc);
   }
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
     const double x[3] = {xc[0], xc[1], xc[2]};
-    double u[3] = {__builtin_nontemporal_load(su1 + i), __builtin_nontemporal_load(su2 + i),
-                   __builtin_nontemporal_load(su3 + i)};
+    const int si = pc;
+    double u[3] = {__builtin_nontemporal_load(su1 + si), __builtin_nontemporal_load(su2 + si),
+                   __builtin_nontemporal_load(su3 + si)};
     const int inext = i + blockDim.x;
     if (inext < end) {
-      xc[0] = __builtin_nontemporal_load(sx1 + inext);
-      xc[1] = __builtin_nontemporal_load(sx2 + inext);
-      xc[2] = __builtin_nontemporal_load(sx3 + inext);
+      pc = perm ? perm[inext] : inext;
+      xc[0] = __builtin_nontemporal_load(sx1 + pc);
+      xc[1] = __builtin_nontemporal_load(sx2 + pc);
+      xc[2] = __builtin_nontemporal_load(sx3 + pc);
     }
     double E[3], B[3];
     gather_o<T, 3, ORDER>(E1, E2, E3, B1, B2, B3, m, x, E, B);
@@ -459,7 +486,7 @@ void tile_push_kernel(
     __builtin_nontemporal_store(u[0], du1 + i);
     __builtin_nontemporal_store(u[1], du2 + i);
     __builtin_nontemporal_store(u[2], du3 + i);
-    if (sid && sid != did) did[i] = sid[i];
+    if (sid && sid != did) did[i] = sid[si];
     if (keys) {  // the next sort's tile key and count, from the new position
       const int key = tile_key_at(xn[0], xn[1], xn[2], m, tg);
       keys[i] = key;
@@ -590,7 +617,7 @@ size_t tile_lds(const TileGeom& tg, bool two) {
 template <typename T>
 int run_tile_push(const Mesh& m, const TileGeom& tg, void* const E[3], void* const B[3], void* const J[3],
                   const int* offsets, const pic_particles& src, const pic_particles& dst, int pusher, double dt,
-                  double* stage, int* keys, int* counts, hipStream_t s) {
+                  double* stage, int* keys, int* counts, const int* perm, hipStream_t s) {
   constexpr bool TWO = sizeof(T) == sizeof(double);
   const size_t lds = tile_lds(tg, TWO);
   if (lds > 160 * 1024) return set_error(PIC_EUNSUPPORTED, "plasma tile needs %zu bytes of LDS", lds);
@@ -608,8 +635,8 @@ int run_tile_push(const Mesh& m, const TileGeom& tg, void* const E[3], void* con
                      (const T*)B[0], (const T*)B[1], (const T*)B[2], (T*)J[0], (T*)J[1], (T*)J[2], m, tg, offsets,
                      (const double*)src.x[0], (const double*)src.x[1], (const double*)src.x[2],
                      (const double*)src.u[0], (const double*)src.u[1], (const double*)src.u[2],
-                     (const int64_t*)src.id, dst.x[0], dst.x[1], dst.x[2], dst.u[0], dst.u[1], dst.u[2], dst.id, qm,
-                     qw, dt, stage, keys, counts);
+                     (const int64_t*)src.id, dst.x[0], dst.x[1], dst.x[2], dst.u[0], dst.u[1], dst.u[2], dst.id, perm,
+                     qm, qw, dt, stage, keys, counts);
   if (hipGetLastError() != hipSuccess) return set_error(PIC_EHIP, "tile push launch failed");
   if (stage) {
     const int64_t work = 3 * (int64_t)m.n1 * m.n2 * m.n3;
@@ -670,7 +697,8 @@ TileGeom make_tile_geom(const Mesh& m, double dt, int sort_every) {
 int scan_segments(int ntiles) { return (ntiles + kScanSeg - 1) / kScanSeg; }
 
 int launch_tile_sort(const Mesh& m, const TileGeom& tg, const pic_particles& p, const pic_particles& scratch,
-                     int* keys, int* counts, int* offsets, int* cursors, int* segsum, void* stream, bool counted) {
+                     int* keys, int* counts, int* offsets, int* cursors, int* segsum, void* stream, bool counted,
+                     int* perm) {
   hipStream_t s = (hipStream_t)stream;
   if (p.np == 0) return PIC_OK;
   const dim3 grid((unsigned)((p.np + 255) / 256));
@@ -683,9 +711,12 @@ int launch_tile_sort(const Mesh& m, const TileGeom& tg, const pic_particles& p, 
   hipLaunchKernelGGL(tile_segsum_kernel, dim3(nseg), dim3(1024), 0, s, counts, tg.nbins, segsum);
   hipLaunchKernelGGL(tile_segscan_kernel, dim3(nseg), dim3(1024), 0, s, counts, tg.nbins, segsum, nseg, offsets,
                      cursors);
-  hipLaunchKernelGGL(tile_scatter_kernel, grid, dim3(256), 0, s, p.x[0], p.x[1], p.x[2], p.u[0], p.u[1], p.u[2],
-                     p.id, keys, offsets, cursors, p.np, scratch.x[0], scratch.x[1], scratch.x[2], scratch.u[0],
-                     scratch.u[1], scratch.u[2], scratch.id);
+  if (perm)
+    hipLaunchKernelGGL(tile_rank_kernel, grid, dim3(256), 0, s, keys, offsets, cursors, p.np, perm);
+  else
+    hipLaunchKernelGGL(tile_scatter_kernel, grid, dim3(256), 0, s, p.x[0], p.x[1], p.x[2], p.u[0], p.u[1], p.u[2],
+                       p.id, keys, offsets, cursors, p.np, scratch.x[0], scratch.x[1], scratch.x[2], scratch.u[0],
+                       scratch.u[1], scratch.u[2], scratch.id);
   return hipGetLastError() == hipSuccess ? PIC_OK : set_error(PIC_EHIP, "tile sort launch failed");
 }
 
@@ -732,13 +763,14 @@ int launch_unsort(const pic_particles& sorted, const int64_t* ids, const pic_par
 
 int launch_tile_push(int prec, const Mesh& m, const TileGeom& tg, void* const E[3], void* const B[3],
                      void* const J[3], const int* offsets, const pic_particles& src, const pic_particles& dst,
-                     int pusher, double dt, double* stage, void* stream, int* keys, int* counts) {
+                     int pusher, double dt, double* stage, void* stream, int* keys, int* counts, const int* perm) {
   hipStream_t s = (hipStream_t)stream;
   if (src.np == 0) return PIC_OK;
   if (keys && hipMemsetAsync(counts, 0, sizeof(int) * tg.nbins, s) != hipSuccess)
     return set_error(PIC_EHIP, "tile push: clear counts");
-  return prec == PIC_FP64 ? run_tile_push<double>(m, tg, E, B, J, offsets, src, dst, pusher, dt, stage, keys, counts, s)
-                          : run_tile_push<float>(m, tg, E, B, J, offsets, src, dst, pusher, dt, stage, keys, counts, s);
+  return prec == PIC_FP64
+             ? run_tile_push<double>(m, tg, E, B, J, offsets, src, dst, pusher, dt, stage, keys, counts, perm, s)
+             : run_tile_push<float>(m, tg, E, B, J, offsets, src, dst, pusher, dt, stage, keys, counts, perm, s);
 }
 
 int launch_tile_deposit(int prec, const Mesh& m, const TileGeom& tg, void* const J[3], const int* offsets,

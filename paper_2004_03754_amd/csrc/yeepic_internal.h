@@ -70,11 +70,13 @@ struct TileGeom {
 TileGeom make_tile_geom(const Mesh& m, double dt, int sort_every);
 // counting sort of p by tile into scratch; segsum holds scan_segments(ntiles)
 // ints.  ``counted``: keys and counts of p already hold every particle's tile
-// and the tiles' counts (written by the push that produced p).
+// and the tiles' counts (written by the push that produced p).  With
+// ``perm`` (np ints) nothing is moved: perm[q] receives the index in p of the
+// particle whose sorted position is q, and scratch is not used.
 int scan_segments(int ntiles);
 int launch_tile_sort(const Mesh& m, const TileGeom& tg, const pic_particles& p, const pic_particles& scratch,
                      int* keys, int* counts, int* offsets, int* cursors, int* segsum, void* stream,
-                     bool counted = false);
+                     bool counted = false, int* perm = nullptr);
 // ids[i] = i; dst[ids[i]] = sorted[i] for x and u (3D)
 int launch_iota(int64_t* ids, int64_t np, void* stream);
 int launch_unsort(const pic_particles& sorted, const int64_t* ids, const pic_particles& dst, void* stream);
@@ -83,10 +85,13 @@ int launch_unsort(const pic_particles& sorted, const int64_t* ids, const pic_par
 // order instead of being added to J with atomics.
 // ``keys``, ``counts`` (or nullptr): also write each pushed particle's tile
 // key (indexed as dst) and the tiles' counts, for a sort of dst right after.
+// ``perm`` (or nullptr): the particle at sorted position i is read from src
+// at perm[i] (a sort's permutation; src and dst must then not alias), else
+// from src at i.
 int launch_tile_push(int prec, const Mesh& m, const TileGeom& tg, void* const E[3], void* const B[3],
                      void* const J[3], const int* offsets, const pic_particles& src, const pic_particles& dst,
                      int pusher, double dt, double* stage, void* stream, int* keys = nullptr,
-                     int* counts = nullptr);
+                     int* counts = nullptr, const int* perm = nullptr);
 // Esirkepov current of particles sorted by the tile of their old position:
 // sorted.x holds the old positions, sorted.u the new ones.
 int launch_tile_deposit(int prec, const Mesh& m, const TileGeom& tg, void* const J[3], const int* offsets,
