@@ -247,7 +247,10 @@ int pic_set_deposit_mode(pic_grid *g, int mode);
  * spatial tile (8^3 cells), and within a tile by x3 cell plane, at the first
  * step and then every pic_set_sort_interval steps, and the current of each
  * tile is accumulated in on-chip memory: such calls REORDER the particles
- * (x, u and id together).
+ * (x, u and id together).  Between sorts the particles may sit in the
+ * library's second particle set (56 bytes per particle plus 8 bytes of sort
+ * keys and permutation, grow-only, PIC_ENOMEM if they cannot be allocated);
+ * every call returns with them in the caller's arrays.
  * Vacuum calls and 2D grids keep the order.  A vacuum call on a 3D grid with
  * nsteps >= 2 pushes each species of at least 32768 particles as a copy in
  * library scratch sorted by the same tiles (two copies of 56 bytes per
