@@ -191,20 +191,36 @@ __global__ __launch_bounds__(256) void tile_scatter_kernel(const double* __restr
 // tile_scatter).  The push that follows reads each particle through perm and
 // writes it at its sorted position into the other particle buffer, so a sort
 // costs no pass over the particle data of its own.
+// Each wave ranks four runs of 64 consecutive particles (one per group of its
+// 256-particle chunk), so that the four key -> offset -> cursor round trips
+// overlap.
+constexpr int kRankGroups = 4;
+
 __global__ __launch_bounds__(256) void tile_rank_kernel(const int* __restrict__ keys, const int* __restrict__ offsets,
                                                         int* __restrict__ cursors, int64_t np,
                                                         int* __restrict__ perm) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = p < np;
-  const int key = live ? keys[p] : -1;
-  int leader_lane, runlen;
-  key_runs(key, leader_lane, runlen);
   const int lane = threadIdx.x & 63;
-  int base = 0;
-  if (leader_lane == lane && key >= 0) base = atomicAdd(&cursors[key], runlen);
-  base = __shfl(base, leader_lane);
-  if (!live) return;
-  perm[(int64_t)offsets[key] + base + (lane - leader_lane)] = (int)p;
+  const int64_t p0 = ((int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63)) * kRankGroups + lane;
+  int key[kRankGroups], off[kRankGroups], lead[kRankGroups], base[kRankGroups];
+#pragma unroll
+  for (int r = 0; r < kRankGroups; ++r) {
+    const int64_t p = p0 + 64 * r;
+    key[r] = p < np ? keys[p] : -1;
+  }
+#pragma unroll
+  for (int r = 0; r < kRankGroups; ++r) {
+    int runlen;
+    key_runs(key[r], lead[r], runlen);
+    off[r] = key[r] >= 0 ? offsets[key[r]] : 0;
+    base[r] = 0;
+    if (lead[r] == lane && key[r] >= 0) base[r] = atomicAdd(&cursors[key[r]], runlen);
+  }
+#pragma unroll
+  for (int r = 0; r < kRankGroups; ++r) {
+    const int b = __shfl(base[r], lead[r]);
+    const int64_t p = p0 + 64 * r;
+    if (p < np) perm[(int64_t)off[r] + b + (lane - lead[r])] = (int)p;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -712,7 +728,8 @@ int launch_tile_sort(const Mesh& m, const TileGeom& tg, const pic_particles& p, 
   hipLaunchKernelGGL(tile_segscan_kernel, dim3(nseg), dim3(1024), 0, s, counts, tg.nbins, segsum, nseg, offsets,
                      cursors);
   if (perm)
-    hipLaunchKernelGGL(tile_rank_kernel, grid, dim3(256), 0, s, keys, offsets, cursors, p.np, perm);
+    hipLaunchKernelGGL(tile_rank_kernel, dim3((unsigned)((p.np + 256 * kRankGroups - 1) / (256 * kRankGroups))),
+                       dim3(256), 0, s, keys, offsets, cursors, p.np, perm);
   else
     hipLaunchKernelGGL(tile_scatter_kernel, grid, dim3(256), 0, s, p.x[0], p.x[1], p.x[2], p.u[0], p.u[1], p.u[2],
                        p.id, keys, offsets, cursors, p.np, scratch.x[0], scratch.x[1], scratch.x[2], scratch.u[0],
