@@ -64,6 +64,49 @@ def test_step_n_plasma(pusher, nsteps, prec, coeffs16):
     grid.close()
 
 
+@pytest.mark.parametrize("nsteps", [4, 9])
+def test_step_n_two_species_ragged_counts(nsteps, coeffs16):
+    """Two species through the sorted plasma path, FP64: electrons with ids
+    at a particle count that is not a multiple of the sort kernels' chunks
+    (24,539), and positrons without ids (11,111).  4 steps take two sorts
+    (both permutations the next push reads through: the particles pass
+    through the library's second set and back); 9 steps take three (the
+    first a scatter).  Fields against the oracle to 1e-12; electrons by id;
+    positrons (no ids to match) through order-free sums of x, u and u^2 to
+    1e-12 of their scale, and the caller's arrays must hold every one of them."""
+    CE, CB = coeffs16
+    n = (128, 16, 12)
+    L = [n[d] * DX[d] for d in range(3)]
+    pulse = wl.Sin2Pulse(a0=2.0, Lp=4 * wl.LAMBDA0, period=L[0])
+    E, B = wl.laser_fields(n, DX, pulse, x_head=3 * wl.LAMBDA0, w0=2 * wl.LAMBDA0)
+    x, u = wl.lattice_particles(n, DX, 1, seed=3, u_th=0.05)
+    xe, ue = x[:, :24539].copy(), u[:, :24539].copy()
+    xp, up = wl.uniform_particles(11111, [0, 0, 0], L, seed=8, u_th=0.05)
+    grid = b.Grid([dev(e) for e in E], [dev(v) for v in B], DX, wl.DT, CE, CB,
+                  J=[dev(np.zeros_like(e)) for e in E])
+    xed, ued, xpd, upd = dev(xe), dev(ue), dev(xp), dev(up)
+    ids = torch.arange(xe.shape[1], device="cuda:0", dtype=torch.int64)
+    pe = b.Particles(xed, ued, q=-1.0, m=1.0, w=0.01, id=ids)
+    pp = b.Particles(xpd, upd, q=1.0, m=1.0, w=0.005)
+    grid.step_n([pe, pp], nsteps, pusher="boris", deposit=True)
+    grid.sync()
+    se = {"x": xe.copy(), "u": ue.copy(), "q": -1.0, "m": 1.0, "w": 0.01}
+    spp = {"x": xp.copy(), "u": up.copy(), "q": 1.0, "m": 1.0, "w": 0.005}
+    Er, Br = pic.run(E, B, [se, spp], CE, CB, DX, wl.DT, nsteps, pusher="boris", deposit=True)
+    assert_fields_close(grid.E, Er, 1e-12, "two species E")
+    assert_fields_close(grid.B, Br, 1e-12, "two species B")
+    assert sorted(host(ids).astype(np.int64).tolist()) == list(range(xe.shape[1]))
+    check(np.max(np.abs(_by_id(ued, ids) - se["u"]) / np.maximum(1, np.abs(se["u"]))), 1e-12, "electrons u")
+    Lb = np.asarray(L)[:, None]
+    d = _by_id(xed, ids) - se["x"]
+    check(np.max(np.abs((d + Lb / 2) % Lb - Lb / 2)), 1e-12, "electrons x")
+    xg, ug = host(xpd), host(upd)
+    for name, g, r in (("x", xg, spp["x"]), ("u", ug, spp["u"]), ("u^2", ug ** 2, spp["u"] ** 2)):
+        scale = max(float(np.sum(np.abs(r))), 1e-300)
+        check(float(np.max(np.abs(g.sum(axis=1) - r.sum(axis=1)))) / scale, 1e-12, f"positrons sum {name}")
+    grid.close()
+
+
 @pytest.mark.parametrize("interval", [1, 3])
 def test_sort_interval(interval, coeffs16):
     """Other re-sort intervals (larger on-chip current tiles) give the same
