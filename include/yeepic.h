@@ -250,7 +250,8 @@ int pic_set_deposit_mode(pic_grid *g, int mode);
  * (x, u and id together).  Between sorts the particles may sit in the
  * library's second particle set (56 bytes per particle plus 8 bytes of sort
  * keys and permutation, grow-only, PIC_ENOMEM if they cannot be allocated);
- * every call returns with them in the caller's arrays.
+ * a call that succeeds returns with them in the caller's arrays (after a
+ * failed call their state is unspecified).
  * Vacuum calls and 2D grids keep the order.  A vacuum call on a 3D grid with
  * nsteps >= 2 pushes each species of at least 32768 particles as a copy in
  * library scratch sorted by the same tiles (two copies of 56 bytes per

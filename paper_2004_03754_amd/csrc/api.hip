@@ -283,8 +283,13 @@ static void free_sort(SortState& st) {
   st = SortState();
 }
 
-static int ensure_sort(pic_grid* g, SortState& st, int64_t np, int nbins, bool ids) {
-  if (np <= st.cap && nbins == st.nbins && (!ids || st.ids)) return PIC_OK;
+// Sort buffers for np particles: keys, counts and scan state; with
+// ``payload`` the second particle set (x, u, and ids with ``ids``); with
+// ``perm`` the permutation.
+static int ensure_sort(pic_grid* g, SortState& st, int64_t np, int nbins, bool ids, bool perm = false,
+                       bool payload = true) {
+  if (np <= st.cap && nbins == st.nbins && (!ids || st.ids) && (!perm || st.perm) && (!payload || st.xs[0]))
+    return PIC_OK;
   (void)hipStreamSynchronize(g->stream);
   free_sort(st);
   const size_t n = (size_t)(np > 0 ? np : 1);
@@ -292,12 +297,12 @@ static int ensure_sort(pic_grid* g, SortState& st, int64_t np, int nbins, bool i
             hipMalloc((void**)&st.counts, (size_t)nbins * sizeof(int)) == hipSuccess &&
             hipMalloc((void**)&st.offsets, ((size_t)nbins + 1) * sizeof(int)) == hipSuccess &&
             hipMalloc((void**)&st.cursors, (size_t)nbins * sizeof(int)) == hipSuccess &&
-            hipMalloc((void**)&st.segsum, (size_t)scan_segments(nbins) * sizeof(int)) == hipSuccess &&
-            hipMalloc((void**)&st.perm, n * sizeof(int)) == hipSuccess;
-  for (int d = 0; d < 3 && ok; ++d)
+            hipMalloc((void**)&st.segsum, (size_t)scan_segments(nbins) * sizeof(int)) == hipSuccess;
+  for (int d = 0; d < 3 && ok && payload; ++d)
     ok = hipMalloc((void**)&st.xs[d], n * sizeof(double)) == hipSuccess &&
          hipMalloc((void**)&st.us[d], n * sizeof(double)) == hipSuccess;
   if (ok && ids) ok = hipMalloc((void**)&st.ids, n * sizeof(int64_t)) == hipSuccess;
+  if (ok && perm) ok = hipMalloc((void**)&st.perm, n * sizeof(int)) == hipSuccess;
   if (!ok) {
     free_sort(st);
     return set_error(PIC_ENOMEM, "cannot allocate particle sort buffers for %lld particles", (long long)np);
@@ -573,32 +578,29 @@ int pic_deposit_J(pic_grid* g, const pic_particles* p, double* const x_old[3], i
     }
   }
   if (g->ndim != 3 || p->np == 0) return launch_deposit(g->prec, g->mesh, g->J, *p, x_old, g->dt, g->stream);
-  // 3D: counting sort of (x_old, x) by the tile of x_old, then the tile
-  // kernel accumulates each tile's current on chip (moves below one cell, so
-  // the window needs no drift margin)
+  // 3D: counting sort of (x_old, x) by the tile of x_old, as a permutation
+  // the tile kernel reads the pairs through; it accumulates each tile's
+  // current on chip (moves below one cell, so the window needs no drift
+  // margin)
   const TileGeom tg = make_tile_geom(g->mesh, g->dt, 1);
-  rc = ensure_sort(g, g->dsort, p->np, tg.nbins, false);
+  rc = ensure_sort(g, g->dsort, p->np, tg.nbins, false, true, false);
   double* stage = nullptr;
   if (rc == PIC_OK && g->deposit_mode == PIC_DEPOSIT_DETERMINISTIC) {
     rc = ensure_stage(g, tg);
     stage = g->stage;
   }
   if (rc) return rc;
-  pic_particles pairs = *p;  // keys from x_old; x_new travels as the payload
-  pic_particles sorted = *p;
+  pic_particles pairs = *p;  // keys from x_old; x_new read beside it
   for (int d = 0; d < 3; ++d) {
     pairs.x[d] = x_old[d];
     pairs.u[d] = p->x[d];
-    sorted.x[d] = g->dsort.xs[d];
-    sorted.u[d] = g->dsort.us[d];
   }
   pairs.id = nullptr;
-  sorted.id = nullptr;
   SortState& st = g->dsort;
-  rc = launch_tile_sort(g->mesh, tg, pairs, sorted, st.keys, st.counts, st.offsets, st.cursors, st.segsum,
-                        g->stream);
+  rc = launch_tile_sort(g->mesh, tg, pairs, pairs, st.keys, st.counts, st.offsets, st.cursors, st.segsum, g->stream,
+                        false, st.perm);
   if (rc) return rc;
-  return launch_tile_deposit(g->prec, g->mesh, tg, g->J, st.offsets, sorted, g->dt, stage, g->stream);
+  return launch_tile_deposit(g->prec, g->mesh, tg, g->J, st.offsets, pairs, g->dt, stage, g->stream, st.perm);
 }
 
 int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nsteps, int pusher, int deposit) {
@@ -649,7 +651,7 @@ int pic_step_n(pic_grid* g, pic_particles* const* species, int nspecies, int nst
     for (int s = 0; s < nspecies && rc == PIC_OK; ++s) rc = check_sortable(species[s]);
     if ((int)g->sorts.size() < nspecies) g->sorts.resize(nspecies);
     for (int s = 0; s < nspecies && rc == PIC_OK; ++s)
-      rc = ensure_sort(g, g->sorts[s], species[s]->np, tg.nbins, species[s]->id != nullptr);
+      rc = ensure_sort(g, g->sorts[s], species[s]->np, tg.nbins, species[s]->id != nullptr, true);
     if (rc == PIC_OK && g->deposit_mode == PIC_DEPOSIT_DETERMINISTIC) {
       rc = ensure_stage(g, tg);
       stage = g->stage;

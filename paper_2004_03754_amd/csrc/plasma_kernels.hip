@@ -529,7 +529,7 @@ __global__ __launch_bounds__(256) void tile_deposit_kernel(T* __restrict__ J1, T
                                                            const int* __restrict__ offsets, const double* xo1,
                                                            const double* xo2, const double* xo3, const double* xn1,
                                                            const double* xn2, const double* xn3, double qw, double dt,
-                                                           double* stage) {
+                                                           double* stage, const int* __restrict__ perm) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const TileWin w = tile_window(tile, tg);
@@ -543,10 +543,11 @@ __global__ __launch_bounds__(256) void tile_deposit_kernel(T* __restrict__ J1, T
   acc_clear(jh, (TWO ? 6 : 3) * w.R);
   __syncthreads();
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
-    const double xo[3] = {__builtin_nontemporal_load(xo1 + i), __builtin_nontemporal_load(xo2 + i),
-                          __builtin_nontemporal_load(xo3 + i)};
-    const double xn[3] = {__builtin_nontemporal_load(xn1 + i), __builtin_nontemporal_load(xn2 + i),
-                          __builtin_nontemporal_load(xn3 + i)};
+    const int si = perm ? perm[i] : i;  // the pair at sorted position i
+    const double xo[3] = {__builtin_nontemporal_load(xo1 + si), __builtin_nontemporal_load(xo2 + si),
+                          __builtin_nontemporal_load(xo3 + si)};
+    const double xn[3] = {__builtin_nontemporal_load(xn1 + si), __builtin_nontemporal_load(xn2 + si),
+                          __builtin_nontemporal_load(xn3 + si)};
     deposit_one<T, ORDER, TWO>(xo, xn, m, tg, w, jh, jl, ts, c1, c2, c3, Jg);
   }
   __syncthreads();
@@ -665,7 +666,7 @@ int run_tile_push(const Mesh& m, const TileGeom& tg, void* const E[3], void* con
 
 template <typename T>
 int run_tile_deposit(const Mesh& m, const TileGeom& tg, void* const J[3], const int* offsets,
-                     const pic_particles& sorted, double dt, double* stage, hipStream_t s) {
+                     const pic_particles& sorted, double dt, double* stage, const int* perm, hipStream_t s) {
   constexpr bool TWO = sizeof(T) == sizeof(double);
   const size_t lds = tile_lds(tg, TWO);
   if (lds > 160 * 1024) return set_error(PIC_EUNSUPPORTED, "deposit tile needs %zu bytes of LDS", lds);
@@ -675,7 +676,8 @@ int run_tile_deposit(const Mesh& m, const TileGeom& tg, void* const J[3], const 
   const double qw = sorted.q * sorted.w;
   hipLaunchKernelGGL(k, dim3(tg.ntiles), dim3(256), lds, s, (T*)J[0], (T*)J[1], (T*)J[2], m, tg, offsets,
                      (const double*)sorted.x[0], (const double*)sorted.x[1], (const double*)sorted.x[2],
-                     (const double*)sorted.u[0], (const double*)sorted.u[1], (const double*)sorted.u[2], qw, dt, stage);
+                     (const double*)sorted.u[0], (const double*)sorted.u[1], (const double*)sorted.u[2], qw, dt, stage,
+                     perm);
   if (hipGetLastError() != hipSuccess) return set_error(PIC_EHIP, "tile deposit launch failed");
   if (stage) {
     const int64_t work = 3 * (int64_t)m.n1 * m.n2 * m.n3;
@@ -791,11 +793,11 @@ int launch_tile_push(int prec, const Mesh& m, const TileGeom& tg, void* const E[
 }
 
 int launch_tile_deposit(int prec, const Mesh& m, const TileGeom& tg, void* const J[3], const int* offsets,
-                        const pic_particles& sorted, double dt, double* stage, void* stream) {
+                        const pic_particles& sorted, double dt, double* stage, void* stream, const int* perm) {
   hipStream_t s = (hipStream_t)stream;
   if (sorted.np == 0) return PIC_OK;
-  return prec == PIC_FP64 ? run_tile_deposit<double>(m, tg, J, offsets, sorted, dt, stage, s)
-                          : run_tile_deposit<float>(m, tg, J, offsets, sorted, dt, stage, s);
+  return prec == PIC_FP64 ? run_tile_deposit<double>(m, tg, J, offsets, sorted, dt, stage, perm, s)
+                          : run_tile_deposit<float>(m, tg, J, offsets, sorted, dt, stage, perm, s);
 }
 
 size_t stage_doubles(const TileGeom& tg) { return (size_t)tg.ntiles * 3 * tg.r[0] * tg.r[1] * tg.r[2]; }

@@ -93,9 +93,11 @@ int launch_tile_push(int prec, const Mesh& m, const TileGeom& tg, void* const E[
                      int pusher, double dt, double* stage, void* stream, int* keys = nullptr,
                      int* counts = nullptr, const int* perm = nullptr);
 // Esirkepov current of particles sorted by the tile of their old position:
-// sorted.x holds the old positions, sorted.u the new ones.
+// sorted.x holds the old positions, sorted.u the new ones; with ``perm`` the
+// pair at sorted position i is read at perm[i].
 int launch_tile_deposit(int prec, const Mesh& m, const TileGeom& tg, void* const J[3], const int* offsets,
-                        const pic_particles& sorted, double dt, double* stage, void* stream);
+                        const pic_particles& sorted, double dt, double* stage, void* stream,
+                        const int* perm = nullptr);
 size_t stage_doubles(const TileGeom& tg);
 
 // Adjoint kernels (adjoint_kernels.hip).  launch_coef_grad adds
