@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "yeepic_internal.h"
 
 namespace yeepic {
@@ -612,75 +614,81 @@ __device__ __forceinline__ ShapeK<ORDER + 2> shape_o(double xo, double xn, doubl
 // Esirkepov 3D decomposition (Sec. 3.3, cited method): for each node
 // (a, b, c) of the K x K x K local stencil, add the current contributions
 // J_d = -q w (dx_d/dt) * (running sum of W_d along d).  ``add(comp, a, b, c, v)``
-// receives stencil-local node indices.  N < K: only the first N nodes per
-// direction, for particles known not to change cell (nearest node, at the
-// quadratic shape) in any direction, whose last node carries no weight.
-template <int K, int N = K, typename Add>
+// receives stencil-local node indices.  N1, N2, N3 < K: only the first K - 1
+// nodes along that direction, for particles known not to change cell
+// (nearest node, at the quadratic shape) along it, whose last node there
+// carries no weight.
+template <int K, int N1 = K, int N2 = K, int N3 = K, typename Add>
 __device__ __forceinline__ void esirkepov(const ShapeK<K>& sx, const ShapeK<K>& sy, const ShapeK<K>& sz, double c1,
                                           double c2, double c3, Add add) {
-  static_assert(N == K || N == K - 1, "node count");
+  static_assert((N1 == K || N1 == K - 1) && (N2 == K || N2 == K - 1) && (N3 == K || N3 == K - 1), "node count");
   // The running sum of W_d along d is (prefix sum of the shape differences
   // up to the node) times the transverse weight.  Exactly zero contributions
-  // are skipped on the full stencil (where every direction without a cell
-  // change leaves a row of them), not on the short one, where they are rare
-  // and the test would cost more than the add.  A particle that stays in
-  // its cell along d has an empty last node there, so the prefix sum up to
-  // the node before it is exactly zero; it is set so (the differences'
-  // rounding would leave a residue), which makes the full loop give the same
-  // contributions as the N = K - 1 loop for such a particle.
-  auto prefix = [](const ShapeK<K>& sh, double cs[N > 1 ? N - 1 : 1]) {
+  // are skipped when some direction takes its full stencil (where every
+  // direction without a cell change leaves a row of them), not on the short
+  // one, where they are rare and the test would cost more than the add.  A
+  // particle that stays in its cell along d has an empty last node there, so
+  // the prefix sum up to the node before it is exactly zero; it is set so
+  // (the differences' rounding would leave a residue), which makes the full
+  // loop give the same contributions as the short one for such a particle.
+  constexpr bool kSkipZero = N1 == K || N2 == K || N3 == K;
+  auto prefix = [](const ShapeK<K>& sh, auto& cs, auto nn) {
+    constexpr int N = decltype(nn)::value;
     cs[0] = sh.ds[0];
 #pragma unroll
     for (int n = 1; n < N - 1; ++n) cs[n] = cs[n - 1] + sh.ds[n];
     if (N == K && sh.s0[K - 1] == 0.0 && sh.ds[K - 1] == 0.0) cs[N - 2] = 0.0;
   };
-  double cx[N - 1], cy[N - 1], cz[N - 1];
-  prefix(sx, cx);
-  prefix(sy, cy);
-  prefix(sz, cz);
+  double cx[N1 > 1 ? N1 - 1 : 1], cy[N2 > 1 ? N2 - 1 : 1], cz[N3 > 1 ? N3 - 1 : 1];
+  prefix(sx, cx, std::integral_constant<int, N1>{});
+  prefix(sy, cy, std::integral_constant<int, N2>{});
+  prefix(sz, cz, std::integral_constant<int, N3>{});
   // The transverse weight of W_d at nodes (p, q) of the two other directions,
   //   S0_p S0_q + (dS_p S0_q + S0_p dS_q)/2 + dS_p dS_q/3,
   // taken as S0_p h_q + dS_p k_q with h = S0 + dS/2, k = S0/2 + dS/3 (the
   // same quantity, two operations per node)
-  double hy[N], ky[N], hz[N], kz[N];
+  double hy[N2], ky[N2], hz[N3], kz[N3];
 #pragma unroll
-  for (int n = 0; n < N; ++n) {
+  for (int n = 0; n < N2; ++n) {
     hy[n] = sy.s0[n] + 0.5 * sy.ds[n];
     ky[n] = 0.5 * sy.s0[n] + (1.0 / 3.0) * sy.ds[n];
+  }
+#pragma unroll
+  for (int n = 0; n < N3; ++n) {
     hz[n] = sz.s0[n] + 0.5 * sz.ds[n];
     kz[n] = 0.5 * sz.s0[n] + (1.0 / 3.0) * sz.ds[n];
   }
 #pragma unroll
-  for (int b = 0; b < N; ++b)
+  for (int b = 0; b < N2; ++b)
 #pragma unroll
-    for (int c = 0; c < N; ++c) {
+    for (int c = 0; c < N3; ++c) {
       const double w = sy.s0[b] * hz[c] + sy.ds[b] * kz[c];
 #pragma unroll
-      for (int a = 0; a < N - 1; ++a) {
+      for (int a = 0; a < N1 - 1; ++a) {
         const double run = cx[a] * w;
-        if (N < K || run != 0.0) add(0, a, b, c, c1 * run);
+        if (!kSkipZero || run != 0.0) add(0, a, b, c, c1 * run);
       }
     }
 #pragma unroll
-  for (int a = 0; a < N; ++a)
+  for (int a = 0; a < N1; ++a)
 #pragma unroll
-    for (int c = 0; c < N; ++c) {
+    for (int c = 0; c < N3; ++c) {
       const double w = sx.s0[a] * hz[c] + sx.ds[a] * kz[c];
 #pragma unroll
-      for (int b = 0; b < N - 1; ++b) {
+      for (int b = 0; b < N2 - 1; ++b) {
         const double run = cy[b] * w;
-        if (N < K || run != 0.0) add(1, a, b, c, c2 * run);
+        if (!kSkipZero || run != 0.0) add(1, a, b, c, c2 * run);
       }
     }
 #pragma unroll
-  for (int a = 0; a < N; ++a)
+  for (int a = 0; a < N1; ++a)
 #pragma unroll
-    for (int b = 0; b < N; ++b) {
+    for (int b = 0; b < N2; ++b) {
       const double w = sx.s0[a] * hy[b] + sx.ds[a] * ky[b];
 #pragma unroll
-      for (int c = 0; c < N - 1; ++c) {
+      for (int c = 0; c < N3 - 1; ++c) {
         const double run = cz[c] * w;
-        if (N < K || run != 0.0) add(2, a, b, c, c3 * run);
+        if (!kSkipZero || run != 0.0) add(2, a, b, c, c3 * run);
       }
     }
 }

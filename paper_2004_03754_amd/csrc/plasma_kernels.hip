@@ -345,15 +345,23 @@ __device__ __forceinline__ void deposit_one(const double xo[3], const double xn[
       const int i = comp * w.R + o + (c * w.r1 + b) * w.r0 + a;
       acc_add<TWO>(&jh[i], &jl[i], v, ts);
     };
-    // most waves hold no particle that changes cell: their stencils' last
-    // node is empty in every direction, and a smaller loop skips it
-    bool moves = false;
+    // along a direction in which no particle of the wave changes cell, every
+    // stencil's last node is empty there, and a smaller loop skips it
+    int full = 0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) moves = moves || sh[d].s0[K - 1] != 0.0 || sh[d].ds[K - 1] != 0.0;
-    if (__builtin_amdgcn_ballot_w64(moves) == 0)
-      esirkepov<K, K - 1>(sh[0], sh[1], sh[2], c1 * k, c2 * k, c3 * k, add);
-    else
-      esirkepov<K>(sh[0], sh[1], sh[2], c1 * k, c2 * k, c3 * k, add);
+    for (int d = 0; d < 3; ++d)
+      full |= __builtin_amdgcn_ballot_w64(sh[d].s0[K - 1] != 0.0 || sh[d].ds[K - 1] != 0.0) ? 1 << d : 0;
+    const double k1 = c1 * k, k2 = c2 * k, k3 = c3 * k;
+    switch (full) {
+      case 0: esirkepov<K, K - 1, K - 1, K - 1>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
+      case 1: esirkepov<K, K, K - 1, K - 1>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
+      case 2: esirkepov<K, K - 1, K, K - 1>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
+      case 3: esirkepov<K, K, K, K - 1>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
+      case 4: esirkepov<K, K - 1, K - 1, K>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
+      case 5: esirkepov<K, K, K - 1, K>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
+      case 6: esirkepov<K, K - 1, K, K>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
+      default: esirkepov<K>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
+    }
   } else {
     const size_t pl = (size_t)m.n1 * m.n2;
     int gw[3][K];
