@@ -617,21 +617,23 @@ __device__ __forceinline__ ShapeK<ORDER + 2> shape_o(double xo, double xn, doubl
 // receives stencil-local node indices.  N1, N2, N3 < K: only the first K - 1
 // nodes along that direction, for particles known not to change cell
 // (nearest node, at the quadratic shape) along it, whose last node there
-// carries no weight.
-template <int K, int N1 = K, int N2 = K, int N3 = K, typename Add>
+// carries no weight.  SKIP: exactly zero contributions are not passed to
+// ``add`` when some direction takes its full stencil (for adds that cost
+// more than the test: global atomics, two-word accumulators).
+template <int K, int N1 = K, int N2 = K, int N3 = K, bool SKIP = true, typename Add>
 __device__ __forceinline__ void esirkepov(const ShapeK<K>& sx, const ShapeK<K>& sy, const ShapeK<K>& sz, double c1,
                                           double c2, double c3, Add add) {
   static_assert((N1 == K || N1 == K - 1) && (N2 == K || N2 == K - 1) && (N3 == K || N3 == K - 1), "node count");
   // The running sum of W_d along d is (prefix sum of the shape differences
-  // up to the node) times the transverse weight.  Exactly zero contributions
-  // are skipped when some direction takes its full stencil (where every
-  // direction without a cell change leaves a row of them), not on the short
-  // one, where they are rare and the test would cost more than the add.  A
-  // particle that stays in its cell along d has an empty last node there, so
-  // the prefix sum up to the node before it is exactly zero; it is set so
-  // (the differences' rounding would leave a residue), which makes the full
-  // loop give the same contributions as the short one for such a particle.
-  constexpr bool kSkipZero = N1 == K || N2 == K || N3 == K;
+  // up to the node) times the transverse weight.  With SKIP, exactly zero
+  // contributions are skipped when some direction takes its full stencil
+  // (where every particle without a cell change along it leaves a row of
+  // them), never on the short one, where they are rare.  A particle that
+  // stays in its cell along d has an empty last node there, so the prefix sum
+  // up to the node before it is exactly zero; it is set so (the differences'
+  // rounding would leave a residue), which makes the full loop give the same
+  // contributions as the short one for such a particle.
+  constexpr bool kSkipZero = SKIP && (N1 == K || N2 == K || N3 == K);
   auto prefix = [](const ShapeK<K>& sh, auto& cs, auto nn) {
     constexpr int N = decltype(nn)::value;
     cs[0] = sh.ds[0];

@@ -352,15 +352,17 @@ __device__ __forceinline__ void deposit_one(const double xo[3], const double xn[
     for (int d = 0; d < 3; ++d)
       full |= __builtin_amdgcn_ballot_w64(sh[d].s0[K - 1] != 0.0 || sh[d].ds[K - 1] != 0.0) ? 1 << d : 0;
     const double k1 = c1 * k, k2 = c2 * k, k3 = c3 * k;
+    // one-word (FP32 grid) accumulators add exact zeros faster than they
+    // test for them; two-word ones skip them
     switch (full) {
-      case 0: esirkepov<K, K - 1, K - 1, K - 1>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
-      case 1: esirkepov<K, K, K - 1, K - 1>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
-      case 2: esirkepov<K, K - 1, K, K - 1>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
-      case 3: esirkepov<K, K, K, K - 1>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
-      case 4: esirkepov<K, K - 1, K - 1, K>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
-      case 5: esirkepov<K, K, K - 1, K>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
-      case 6: esirkepov<K, K - 1, K, K>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
-      default: esirkepov<K>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
+      case 0: esirkepov<K, K - 1, K - 1, K - 1, TWO>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
+      case 1: esirkepov<K, K, K - 1, K - 1, TWO>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
+      case 2: esirkepov<K, K - 1, K, K - 1, TWO>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
+      case 3: esirkepov<K, K, K, K - 1, TWO>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
+      case 4: esirkepov<K, K - 1, K - 1, K, TWO>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
+      case 5: esirkepov<K, K, K - 1, K, TWO>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
+      case 6: esirkepov<K, K - 1, K, K, TWO>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
+      default: esirkepov<K, K, K, K, TWO>(sh[0], sh[1], sh[2], k1, k2, k3, add); break;
     }
   } else {
     const size_t pl = (size_t)m.n1 * m.n2;
