@@ -216,7 +216,9 @@ int pic_set_shape(pic_grid *g, int order);
  * current for every C^B: the x1 correction of Eq. (correction) is applied
  * where Ampere's law reads J (see pic_advance_E and pic_current_correction).
  * On a 3D grid the (x_old, x) pairs are counting-sorted by the 8^3-cell tile
- * of x_old, and within a tile by its x3 cell plane, into library scratch (grow-only, 52 bytes per particle) and each
+ * of x_old, and within a tile by its x3 cell plane, as a permutation in
+ * library scratch (grow-only, 8 bytes of keys and permutation per particle)
+ * through which the tile kernel reads them, and each
  * tile's current is summed on chip in 64-bit fixed point whose quantum is
  * set per tile from its particle count, so that no sum can overflow; FP64
  * grids keep two words per node, making each tile's sum exact before one
