@@ -615,6 +615,9 @@ def main():
             "sweep_GBps": fp32["sweep_bytes"] / (fp32["ms_sweep"] * 1e-3) / 1e9,
             "speedup_vs_fp64_step": main_run["ms_step"] / fp32["ms_step"],
             "speedup_vs_fp64_sweep": main_run["ms_sweep"] / fp32["ms_sweep"]}
+        c32, _ = stream_ceiling(torch, cells, dtype=torch.float32)
+        res["fp32_fields"]["stream_ceiling_GBps"] = c32
+        res["fp32_fields"]["sweep_frac_of_stream_ceiling"] = res["fp32_fields"]["sweep_GBps"] / c32
         # the headline workload with the Higuera-Cary pusher (Sec. 4.1's default pusher)
         hc = run_vacuum(torch, b, wl, n, "fp64", pulse, 12 * L, 4 * L, 1 << 20, box, max(50, args.steps // 5),
                         args.warmup, "hc", 2, CE, CB)
