@@ -1225,11 +1225,12 @@ int run_sweep_yee(const Mesh& m, void* const Ein[3], void* const Bin[3], void* c
   const int tiles = tiles_x * ((m.n2 + TY - 1) / TY);
   // FP32 tiles fit two workgroups per CU (LDS and 128 VGPRs); that pays
   // where the mesh has fewer than two tiles per CU (the x3 march is then
-  // split to fill the slots).  With at least two tiles per CU one workgroup
-  // per CU (144 VGPRs, no spills) streams faster.  FP64 takes one workgroup
-  // per CU.
+  // split to fill the slots) and there is no current to read.  With at least
+  // two tiles per CU, or with J (whose 128-VGPR build spills 13 registers),
+  // one workgroup per CU (144 VGPRs, no spills) streams faster.  FP64 takes
+  // one workgroup per CU.
   if constexpr (sizeof(T) == 4) {
-    if (tiles >= 2 * device_cus())
+    if (tiles >= 2 * device_cus() || (J && J[0]))
       return launch_sweep_yee<T, ME, TX, TY, NT, 2>(m, Ein, Bin, J, Eout, Bout, Bh, c, tiles_x, tiles, 1, s);
     return launch_sweep_yee<T, ME, TX, TY, NT, 4>(m, Ein, Bin, J, Eout, Bout, Bh, c, tiles_x, tiles, 2, s);
   }
