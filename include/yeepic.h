@@ -216,7 +216,8 @@ int pic_set_shape(pic_grid *g, int order);
  * current for every C^B: the x1 correction of Eq. (correction) is applied
  * where Ampere's law reads J (see pic_advance_E and pic_current_correction).
  * On a 3D grid the (x_old, x) pairs are counting-sorted by the 8^3-cell tile
- * of x_old, and within a tile by its x3 cell plane, as a permutation in
+ * of x_old, and within a tile by its x3 cell plane and pair of x2 cell rows,
+ * as a permutation in
  * library scratch (grow-only, 8 bytes of keys and permutation per particle)
  * through which the tile kernel reads them, and each
  * tile's current is summed on chip in 64-bit fixed point whose quantum is
@@ -246,7 +247,8 @@ int pic_set_deposit_mode(pic_grid *g, int mode);
  * inside; the fields end in the caller's arrays, J holds the last step's
  * deposited current.
  * With deposit on a 3D grid the particles of every species are sorted by
- * spatial tile (8^3 cells), and within a tile by x3 cell plane, at the first
+ * spatial tile (8^3 cells), and within a tile by x3 cell plane and pair of x2
+ * cell rows, at the first
  * step and then every pic_set_sort_interval steps, and the current of each
  * tile is accumulated in on-chip memory: such calls REORDER the particles
  * (x, u and id together).  Between sorts the particles may sit in the

@@ -16,7 +16,7 @@
 // Per-species buffers of the tile-sorted plasma path (grow-only).
 struct SortState {
   int64_t cap = 0;
-  int nbins = 0;  // sort keys (tiles times their x3 planes)
+  int nbins = 0;  // sort keys (tiles times their bins: x3 planes and pairs of x2 rows)
   int* keys = nullptr;
   int* counts = nullptr;
   int* offsets = nullptr;

@@ -33,16 +33,21 @@ __device__ __forceinline__ int cell_of(double x, double idx, int n) {
   return (int)f;
 }
 
-// Sort key of a position: its tile, then the tile's x3 cell plane.  A
-// tile's particles are thus grouped by plane, so that the 64 particles of a
-// wave mostly share one plane: the gather's loads of a wave then touch about
-// 8 field rows instead of the tile's 64, and the L1 serves far fewer lines.
+// Sort key of a position: its tile, then within the tile its x3 cell plane
+// and pair of x2 cell rows.  A tile's particles are thus grouped so that the
+// 64 particles of a wave mostly share one plane and two rows (16 cells, 4
+// particles per cell at 8 per cell): the gather's loads of a wave then touch
+// about 3 field rows per plane instead of the tile's 64, and the L1, shared
+// by the waves of three tiles, keeps far more of them.  (Finer bins crowd a
+// wave's current atomics onto fewer nodes.)
 __device__ __forceinline__ int tile_key_at(double x1, double x2, double x3, const Mesh& m, const TileGeom& tg) {
   const int cx = cell_of(x1, m.idx1, m.n1) / tg.t[0];
-  const int cy = cell_of(x2, m.idx2, m.n2) / tg.t[1];
+  const int y = cell_of(x2, m.idx2, m.n2);
+  const int cy = y / tg.t[1];
   const int z = cell_of(x3, m.idx3, m.n3);
   const int cz = z / tg.t[2];
-  return ((cz * tg.nt[1] + cy) * tg.nt[0] + cx) * tg.sub + (z - cz * tg.t[2]);
+  const int pairs = (tg.t[1] + 1) / 2;
+  return ((cz * tg.nt[1] + cy) * tg.nt[0] + cx) * tg.sub + (z - cz * tg.t[2]) * pairs + (y - cy * tg.t[1]) / 2;
 }
 
 __device__ __forceinline__ int tile_key(const double* const* x, int64_t p, const Mesh& m, const TileGeom& tg) {
@@ -717,7 +722,7 @@ TileGeom make_tile_geom(const Mesh& m, double dt, int sort_every) {
     tg.r[d] = tg.t[d] + 2 * tg.m[d] + 2 + (m.order == 2 ? 2 : 1);
     tg.ntiles *= tg.nt[d];
   }
-  tg.sub = tg.t[2];
+  tg.sub = tg.t[2] * ((tg.t[1] + 1) / 2);  // bins per tile: x3 planes times pairs of x2 rows
   tg.nbins = tg.ntiles * tg.sub;
   return tg;
 }

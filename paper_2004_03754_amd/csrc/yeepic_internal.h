@@ -64,7 +64,7 @@ struct TileGeom {
   int m[3];   // drift margin in cells
   int r[3];   // nodes of the on-chip current tile per direction
   int ntiles;
-  int sub;    // sort bins per tile: one per x3 cell plane of the tile
+  int sub;    // sort bins per tile: one per x3 cell plane and pair of x2 cell rows of the tile
   int nbins;  // ntiles * sub: the sort's keys
 };
 TileGeom make_tile_geom(const Mesh& m, double dt, int sort_every);
