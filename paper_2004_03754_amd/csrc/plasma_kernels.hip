@@ -41,11 +41,13 @@ __device__ __forceinline__ int cell_of(double x, double idx, int n) {
 // by the waves of three tiles, keeps far more of them.  (Finer bins crowd a
 // wave's current atomics onto fewer nodes.)
 __device__ __forceinline__ int tile_key_at(double x1, double x2, double x3, const Mesh& m, const TileGeom& tg) {
-  const int cx = cell_of(x1, m.idx1, m.n1) / tg.t[0];
+  // divisions by the tile size as one multiply-high each (exact for cell
+  // indices below 2^29 at tile sizes up to 8)
+  const int cx = (int)__umulhi((unsigned)cell_of(x1, m.idx1, m.n1), tg.mt[0]);
   const int y = cell_of(x2, m.idx2, m.n2);
-  const int cy = y / tg.t[1];
+  const int cy = (int)__umulhi((unsigned)y, tg.mt[1]);
   const int z = cell_of(x3, m.idx3, m.n3);
-  const int cz = z / tg.t[2];
+  const int cz = (int)__umulhi((unsigned)z, tg.mt[2]);
   const int pairs = (tg.t[1] + 1) / 2;
   return ((cz * tg.nt[1] + cy) * tg.nt[0] + cx) * tg.sub + (z - cz * tg.t[2]) * pairs + (y - cy * tg.t[1]) / 2;
 }
@@ -712,6 +714,7 @@ TileGeom make_tile_geom(const Mesh& m, double dt, int sort_every) {
   tg.ntiles = 1;
   for (int d = 0; d < 3; ++d) {
     tg.t[d] = n[d] < 8 ? n[d] : 8;
+    tg.mt[d] = tg.t[d] == 1 ? 0u : (unsigned)((1ull << 32) / (unsigned)tg.t[d] + 1);
     tg.nt[d] = (n[d] + tg.t[d] - 1) / tg.t[d];
     // |v| < 1: at most (S-1) dt/dx cells of drift before the next sort
     tg.m[d] = (int)std::ceil((sort_every - 1) * dt / dx[d] - 1e-12);

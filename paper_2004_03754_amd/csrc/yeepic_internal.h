@@ -65,6 +65,7 @@ struct TileGeom {
   int r[3];   // nodes of the on-chip current tile per direction
   int ntiles;
   int sub;    // sort bins per tile: one per x3 cell plane and pair of x2 cell rows of the tile
+  unsigned mt[3];  // cell / t[d] == umulhi(cell, mt[d]): floor(2^32 / t) + 1 (0 for t = 1, where cell is 0)
   int nbins;  // ntiles * sub: the sort's keys
 };
 TileGeom make_tile_geom(const Mesh& m, double dt, int sort_every);
