@@ -406,14 +406,19 @@ __device__ __forceinline__ void acc_flush(const unsigned long long* jh, const un
     const int a = (int)threadIdx.x % L, P = (int)blockDim.x / L, r2 = tg.r[2];
     if (a >= w.r0) return;
     const int gx = wrapn(w.lo[0] + a - tg.m[0] - 1, m.n1);
+    // a window row's mesh row lo + b - m - 1 lies in [-n, 2n) when the mesh
+    // is at least as wide as the window: one conditional add or subtract
+    // wraps it (else the general remainder)
+    const bool near = m.n2 >= w.r1 && m.n3 >= r2;
+    auto wrap_row = [&](int v, int n) { return near ? (v < 0 ? v + n : (v >= n ? v - n : v)) : wrapn(v, n); };
     int row = (int)threadIdx.x / L;
     int b = row % w.r1, c = (row / w.r1) % r2, comp = row / (w.r1 * r2);
     for (; row < 3 * w.r1 * r2; row += P) {
       const int i = row * w.r0 + a;
       const double v = acc_value<TWO>(jh[i], TWO ? jl[i] : 0ull, ts);
       if (v != 0.0) {
-        const int gy = wrapn(w.lo[1] + b - tg.m[1] - 1, m.n2);
-        const int gz = wrapn(w.lo[2] + c - tg.m[2] - 1, m.n3);
+        const int gy = wrap_row(w.lo[1] + b - tg.m[1] - 1, m.n2);
+        const int gz = wrap_row(w.lo[2] + c - tg.m[2] - 1, m.n3);
         unsafeAtomicAdd(&Jg[comp][(size_t)gz * pl + (size_t)gy * m.n1 + gx], (T)v);
       }
       b += P;
